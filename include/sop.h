@@ -1,0 +1,300 @@
+/*
+ * sop.h - C ABI of the Surface Octahedral Probe (SOP) query-and-shade library for
+ *         AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the deferred-shading step of ComGS (arXiv 2510.07729), Sec. 3.1.2
+ * ("Material and Lighting Decomposition"):
+ *   - every shading point x evaluates the rendering equation (Eq. 6) by the Monte Carlo
+ *     estimate of Eq. 7 over S_r Hammersley directions on its hemisphere;
+ *   - incident light is the environment map attenuated by occlusion plus indirect light
+ *     (Eq. 8);
+ *   - occlusion O and indirect radiance L_in come from the octahedral textures of the K
+ *     nearest surface octahedral probes, blended with spatial and back-face weights
+ *     (Eq. 9-11, "Efficient Querying through SOPs");
+ *   - probe textures are initialised by tracing rays through the Gaussians (Sec. 3.1.2,
+ *     paragraph introducing SOPs; Sec. 4.1 implementation details).
+ * Two entry points go beyond the paper: the adjoint of the shading step
+ * (sop_shade_backward) for gradient-based reconstruction (the learnable quantities of
+ * Sec. 4.1), and a learned direction proposal (sop_proposal_*).
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers are DEVICE pointers owned by the caller unless a field says "host".
+ *     Arrays are contiguous, row-major, 32-bit IEEE float unless a format field says
+ *     otherwise, and 4-byte aligned (8-byte for half textures, 16-byte for f32 textures).
+ *   - Every call is asynchronous and ordered on the HIP stream it is given; no call
+ *     synchronises the host except sop_plan_create, sop_bake_plan_create and the
+ *     sop_*_check helpers, which say so.
+ *   - sop_knn, sop_query, sop_shade, sop_shade_backward, sop_bake and the proposal calls
+ *     never allocate: their scratch memory is the caller's workspace `ws` of `ws_bytes`
+ *     bytes (256-byte aligned), sized by the matching *_workspace_size function.
+ *   - Every argument is validated on the host before any device work is enqueued. A call
+ *     that fails returns a status other than SOP_OK, enqueues nothing and leaves its outputs
+ *     untouched; sop_last_error() then returns a message (thread-local) naming the problem.
+ *     SOP_ERR_DEVICE reports a HIP runtime error raised while enqueueing.
+ *   - Two calls that share a plan, a workspace or an accumulated gradient buffer must not
+ *     run concurrently on different streams.
+ */
+#ifndef SOP_H_
+#define SOP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* HIP stream handle (hipStream_t); NULL is the legacy default stream. */
+typedef struct ihipStream_t* sop_stream;
+
+typedef enum sop_status {
+  SOP_OK = 0,
+  SOP_ERR_INVALID_ARGUMENT = 1,   /* NULL/misaligned pointer, size or option out of range   */
+  SOP_ERR_UNSUPPORTED = 2,        /* valid request the library does not implement           */
+  SOP_ERR_WORKSPACE_TOO_SMALL = 3,/* ws_bytes below the *_workspace_size figure             */
+  SOP_ERR_DEVICE = 4,             /* HIP runtime error (message holds hipGetErrorString)    */
+  SOP_ERR_OUT_OF_MEMORY = 5       /* plan creation could not allocate device memory         */
+} sop_status;
+
+typedef enum sop_texel_format {
+  SOP_TEXEL_F32 = 0,              /* 4 x float per texel (16 bytes)                         */
+  SOP_TEXEL_F16 = 1               /* 4 x IEEE half per texel (8 bytes)                      */
+} sop_texel_format;
+
+/* Library limits. */
+#define SOP_MAX_K        16       /* neighbours per shading point                           */
+#define SOP_MAX_DIRS     4096     /* directions per shading point                           */
+#define SOP_MAX_RES      256      /* octahedral texture side                                */
+#define SOP_LATTICE_BITS 15       /* neighbour search quantises positions to 2^15 per axis  */
+
+/* ----------------------------------------------------------------------------------------
+ * Inputs
+ * --------------------------------------------------------------------------------------*/
+
+/* Probe positions (Sec. 3.1.2, "Automatic Placement of SOPs"). bounds_lo/hi are HOST
+ * values: the box in which positions are quantised for the neighbour search. Positions
+ * outside the box are clamped onto it by the quantisation; hi > lo on every axis. */
+typedef struct sop_probe_set {
+  int32_t      count;            /* P >= 0                                                */
+  const float* pos;              /* device [P,3]; may be NULL when P == 0                 */
+  float        bounds_lo[3];     /* host                                                  */
+  float        bounds_hi[3];     /* host                                                  */
+} sop_probe_set;
+
+/* Probe textures {L_in, O} (Sec. 3.1.2): one octahedral map per probe, +z at the centre of
+ * the square. Layout [P][row v][column u][channel], channels (R, G, B, O). */
+typedef struct sop_probe_maps {
+  int32_t     res;               /* R_t, 2 <= res <= SOP_MAX_RES                          */
+  int32_t     format;            /* sop_texel_format                                      */
+  const void* texels;            /* device [P,res,res,4]                                  */
+} sop_probe_maps;
+
+/* Environment map L_dir (Eq. 8) as an equirectangular image: row 0 is around +z, column u
+ * covers azimuth phi = 2*pi*u/W - pi. Layout [H][W][3] (RGB). */
+typedef struct sop_envmap {
+  int32_t      height;           /* H >= 1                                                */
+  int32_t      width;            /* W >= 1                                                */
+  const float* texels;           /* device [H,W,3]                                        */
+} sop_envmap;
+
+/* Shading points (G-buffer texels, Sec. 3.1 "Multi-Target Rendering"). The view direction
+ * is either given per point (`view`, unit vectors toward the viewer) or derived from one
+ * camera position per frame: points [f*points_per_frame, (f+1)*points_per_frame) see
+ * cam_pos[f]. Normals must be unit length; the BRDF assumes n . view > 0. */
+typedef struct sop_points {
+  int64_t      count;            /* N >= 0                                                */
+  const float* pos;              /* device [N,3]                                          */
+  const float* normal;           /* device [N,3]                                          */
+  const float* view;             /* device [N,3] or NULL (then cam_pos is used)           */
+  const float* cam_pos;          /* device [n_frames,3], used when view == NULL           */
+  int64_t      points_per_frame; /* >= 1 when view == NULL                               */
+  int32_t      n_frames;         /* N == n_frames * points_per_frame when view == NULL    */
+  const float* albedo;           /* device [N,3]                                          */
+  const float* roughness;        /* device [N]                                            */
+  const float* metallic;         /* device [N]                                            */
+} sop_points;
+
+/* Result of the neighbour search (sop_knn), reusable by sop_query/sop_shade/
+ * sop_shade_backward so that a forward and its backward search only once. */
+typedef struct sop_neighbors {
+  int32_t        k;              /* K, 1 <= K <= SOP_MAX_K                                */
+  const int32_t* order;          /* device [N]: processing order (a permutation of 0..N-1
+                                    grouping points that share probes); NULL = identity  */
+  const int32_t* idx;            /* device [N,K]: probe indices, ascending (d^2, index);
+                                    -1 pads a short list                                 */
+  const float*   weight;         /* device [N,K]: normalised weights, 0 on pads           */
+} sop_neighbors;
+
+typedef struct sop_plan sop_plan;             /* probe grid (opaque)                      */
+
+/* ----------------------------------------------------------------------------------------
+ * Probe plan: quantised lattice + uniform grid over the probes, the acceleration structure
+ * of the fixed-radius / k-nearest search of Sec. 3.1.2 ("Efficient Querying").
+ * --------------------------------------------------------------------------------------*/
+
+/* Creates a plan for `probes` and builds its grid on `stream`. Allocates device memory for
+ * the grid (O(P) plus the cell table) and synchronises `stream` once. The plan keeps no
+ * pointer to probes->pos after the call. Release with sop_plan_destroy. */
+sop_status sop_plan_create(const sop_probe_set* probes, sop_stream stream, sop_plan** out);
+
+/* Rebuilds the grid of `plan` for new positions `pos` (device [P,3], same P and bounds as at
+ * creation). Asynchronous, allocates nothing. */
+sop_status sop_plan_rebuild(sop_plan* plan, const float* pos, sop_stream stream);
+
+/* Frees the plan. Work that uses it must have completed. NULL is accepted. */
+sop_status sop_plan_destroy(sop_plan* plan);
+
+/* Number of probes and grid cells of a plan (host values). */
+sop_status sop_plan_info(const sop_plan* plan, int32_t* n_probes, int32_t grid_dims[3],
+                         float* lattice_scale);
+
+/* ----------------------------------------------------------------------------------------
+ * Neighbour search (Eq. 9-11).
+ * Positions are quantised to the integer lattice q = clamp(floor((x - lo) * sc), 0, 2^15-1)
+ * per axis, in 32-bit float arithmetic, with one isotropic scale
+ * sc = 32768 / max_axis(hi - lo). Candidates are the probes with squared lattice distance
+ * d^2 <= floor((radius*sc)^2) (radius = +inf: all probes); the K smallest by (d^2, probe
+ * index) are kept. If the smallest d^2 is 0, that single probe is used with weight 1.
+ * Otherwise w_k = (1/|p_k - x|) * (0.5 * (1 + (p_k - x)/|p_k - x| . n) + 0.01), normalised
+ * to sum 1 (Eq. 10-11 with n_p read as the shading normal).
+ * --------------------------------------------------------------------------------------*/
+
+/* Writes order[N], idx[N,K] and w[N,K] (see sop_neighbors). order may be NULL. */
+sop_status sop_knn(const sop_plan* plan, const sop_points* pts, int32_t k, float radius,
+                   int32_t* order, int32_t* idx, float* w,
+                   void* ws, size_t ws_bytes, sop_stream stream);
+
+/* Eq. 9 as a primitive: for every point i and given world direction dirs[i,j] (unit, device
+ * [N,D,3]) returns the interpolated indirect radiance L_in[i,j,0..2] and occlusion O[i,j]
+ * (device [N,D,3] and [N,D]). nb may be NULL (the search then runs with k/radius).
+ * Each probe texture is read with bilinear filtering and octahedral mirror wrap. */
+sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps, const sop_points* pts,
+                     const sop_neighbors* nb, const float* dirs, int32_t n_dirs, int32_t k,
+                     float radius, float* L_in, float* O,
+                     void* ws, size_t ws_bytes, sop_stream stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Shading (Eq. 6-8 with the estimator of Eq. 7).
+ * Direction j of S at point i: cos(theta) = 1 - (j + 0.5)/S,
+ * phi = 2*pi * (((bitreverse32(j) >> 8) + rho) mod 2^24) / 2^24 in the orthonormal frame of
+ * the normal (Duff et al. 2017). rho = pcg_hash(seed) >> 8 (or, per point,
+ * pcg_hash(seed ^ pcg_hash(i)) >> 8), pcg_hash as in Jarzynski & Olano 2020.
+ * BRDF (a reading of the "simplified Disney BRDF"): Lambert (1-m)*a/pi plus GGX
+ * D*F*G/(4 NoL NoV), alpha = r^2, Smith-Schlick G with k = alpha/2, Schlick F with
+ * F0 = 0.04(1-m) + a*m, NoV = max(n.v, 1e-4).
+ * rgb_i = (2*pi/S) * sum_j f(w_j) * L_i(w_j) * cos(theta_j),
+ * L_i = (1 - O(w)) * L_env(w) + L_in(w).
+ * --------------------------------------------------------------------------------------*/
+
+typedef enum sop_sampler {
+  SOP_SAMPLER_HAMMERSLEY = 0      /* uniform hemisphere Hammersley set (Eq. 7)              */
+} sop_sampler;
+
+typedef struct sop_shade_opts {
+  int32_t  n_dirs;               /* S, 1 <= S <= SOP_MAX_DIRS                             */
+  int32_t  k;                    /* K, 1 <= K <= SOP_MAX_K (ignored when nb != NULL)       */
+  float    radius;               /* FRNN radius in world units, +inf = unlimited          */
+  uint32_t seed;                 /* rotation seed of the direction set                    */
+  int32_t  rotate_per_point;     /* 0: one rotation per call, 1: one per point            */
+  int32_t  sampler;              /* sop_sampler                                           */
+  float*   out_irradiance;       /* optional device [N,3]: (2pi/S) sum_j L_i cos(theta)   */
+} sop_shade_opts;
+
+/* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL. */
+sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
+                     const sop_points* pts, const sop_neighbors* nb,
+                     const sop_shade_opts* opts, float* rgb,
+                     void* ws, size_t ws_bytes, sop_stream stream);
+
+/* Adjoint of sop_shade for the upstream gradient grad_rgb[N,3]. Recomputes every sample
+ * (nothing is stored by the forward). Per-point gradients are OVERWRITTEN:
+ * g_albedo[N,3], g_rough[N], g_metal[N] (each may be NULL). Texture gradients are
+ * ACCUMULATED (+=) and may be NULL: g_env[H,W,3] and g_tex[P,res,res,4] (always f32, also
+ * for half textures; channel 3 is dL/dO). Geometry (positions, normals, views) and the
+ * neighbour weights receive no gradient. Accumulation order is not fixed, so g_env/g_tex
+ * may differ between runs by float rounding. */
+sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_maps* maps,
+                              const sop_envmap* env, const sop_points* pts,
+                              const sop_neighbors* nb, const sop_shade_opts* opts,
+                              const float* grad_rgb, float* g_albedo, float* g_rough,
+                              float* g_metal, float* g_env, float* g_tex,
+                              void* ws, size_t ws_bytes, sop_stream stream);
+
+typedef enum sop_op {
+  SOP_OP_KNN = 0,
+  SOP_OP_QUERY = 1,
+  SOP_OP_SHADE = 2,
+  SOP_OP_SHADE_BACKWARD = 3
+} sop_op;
+
+/* Workspace bytes that `op` needs for n_points points with k neighbours and n_dirs
+ * directions on `plan`, assuming the neighbour search runs inside the call (nb == NULL);
+ * with_neighbors != 0 gives the smaller figure for calls that receive nb. Returns 0 on an
+ * invalid argument. */
+size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points, int32_t k,
+                          int32_t n_dirs, int32_t with_neighbors);
+
+/* ----------------------------------------------------------------------------------------
+ * Bake: probe textures by ray tracing through 3D Gaussians (Sec. 3.1.2, the SOP texture
+ * initialisation "via ray tracing"; Sec. 4.1). For texel (u,v) of probe p the ray starts at
+ * p along the octahedral decode of the texel centre. Each Gaussian responds at the ray
+ * parameter t* of maximum density; alpha = min(alpha_max, opacity * exp(-m^2/2)) with m the
+ * Mahalanobis distance at t*; Gaussians with t* <= t_min or alpha < alpha_min are skipped.
+ * The rest are blended front to back in ascending (t*, index) as in Eq. 1: T starts at 1,
+ * blending stops before a Gaussian that would take T*(1-alpha) below T_min.
+ * Outputs (R,G,B) = sum T*alpha*color, O = sum T*alpha, depth = sum T*alpha*t* / O (0 when
+ * O == 0), the unbiased depth D/W of Sec. 3.1.
+ * --------------------------------------------------------------------------------------*/
+
+typedef struct sop_gaussians {
+  int32_t      count;            /* G >= 0                                                */
+  const float* mean;             /* device [G,3]                                          */
+  const float* scale;            /* device [G,3]: standard deviations, > 0                */
+  const float* rotation;         /* device [G,4]: quaternion (w,x,y,z), normalised here   */
+  const float* opacity;          /* device [G], in [0,1]                                  */
+  const float* color;            /* device [G,3]                                          */
+} sop_gaussians;
+
+typedef struct sop_bake_opts {
+  float t_min;                   /* default 0                                             */
+  float alpha_min;               /* default 1/255                                         */
+  float alpha_max;               /* default 0.99                                          */
+  float T_min;                   /* default 1e-4                                          */
+} sop_bake_opts;
+
+typedef struct sop_bake_plan sop_bake_plan;   /* Gaussian grid (opaque)                   */
+
+/* Precomputes per-Gaussian frames and registers every Gaussian in the cells of a uniform
+ * grid overlapped by its cut-off ellipsoid (where its response can reach alpha_min).
+ * Allocates device memory sized by a counting pass and synchronises `stream` once. */
+sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bake_opts* opts,
+                                sop_stream stream, sop_bake_plan** out);
+
+/* Re-registers Gaussians with the same count G into the existing grid, asynchronously and
+ * without allocating. If the new registration exceeds the capacity fixed at creation,
+ * sop_bake writes NaN to every output texel and sop_bake_plan_check reports it. */
+sop_status sop_bake_plan_update(sop_bake_plan* plan, const sop_gaussians* g,
+                                sop_stream stream);
+
+/* Synchronises `stream` and returns SOP_ERR_WORKSPACE_TOO_SMALL if the last update of the
+ * plan overflowed its grid capacity, else SOP_OK. */
+sop_status sop_bake_plan_check(const sop_bake_plan* plan, sop_stream stream);
+
+sop_status sop_bake_plan_destroy(sop_bake_plan* plan);
+
+/* Traces every texel of P probes at resolution res. texels: device [P,res,res,4] f32
+ * (R,G,B,O); depth: device [P,res,res] f32 or NULL. No workspace. */
+sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n_probes,
+                    int32_t res, float* texels, float* depth, sop_stream stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Misc
+ * --------------------------------------------------------------------------------------*/
+const char* sop_status_string(sop_status s);
+const char* sop_last_error(void);
+int32_t     sop_version(void);          /* major*10000 + minor*100 + patch */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SOP_H_ */
