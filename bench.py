@@ -1,0 +1,253 @@
+"""Benchmark of the SOP hot path on one MI355X.
+
+One step = one pass of the whole path over the object workload: re-register the 100k
+Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays), rebuild the probe
+grid, order the 200k shading points and find their 8 nearest probes, shade them with 128
+directions (forward) and run the adjoint (backward) into the probe and environment
+gradients. value = shaded point-direction samples (N*S) per second of the whole step.
+
+Prints ONE JSON line. Per-kernel durations are measured with HIP events on the stream the
+kernels run on; algorithmic flop counts per sample are documented below.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "shaded point·direction samples/s fwd+bwd; % HBM roofline; speedup at matched error"
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector, published (packed FMA)
+PEAK_HBM_GBS = 8000.0
+
+
+# Algorithmic FP32 operations per sample (+, -, *, / and each transcendental, sqrt, floor
+# count 1; a fused multiply-add counts 2), counted from the definitions the kernels
+# implement (direction, environment fetch, octahedral taps, K-probe blend, incident light,
+# BRDF, accumulation). Per-point work (frame, material constants) is not counted.
+def flops_fwd(K: int) -> int:
+    direction, env, taps, light, brdf, acc = 24, 45, 25, 7, 69, 6
+    return direction + env + taps + 36 * K + light + brdf + acc
+
+
+def flops_bwd(K: int) -> int:
+    recompute = flops_fwd(K) - 6
+    material, texture, environment = 28 + 81, 20 * K, 12
+    return recompute + material + texture + environment
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2510_07729_amd import scenes, sop
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+
+    # ------------------------------------------------------------------ workload (untimed)
+    t0 = time.time()
+    gs = scenes.object_gaussians()
+    probes_np = scenes.object_probes()
+    sc = scenes.object_scene()
+    N, S, K, R = sc.n, sc.n_dirs, sc.k, 32
+    P = probes_np.shape[0]
+    G = gs.count
+    grad_np = np.random.default_rng(123).standard_normal((N, 3)).astype(np.float32)
+    print(f"# workload built in {time.time() - t0:.1f}s: G={G} P={P} R={R} N={N} S={S} K={K}",
+          file=sys.stderr, flush=True)
+
+    g_mean, g_scale, g_rot, g_op, g_col = (d(gs.mean), d(gs.scale), d(gs.rotation),
+                                           d(gs.opacity), d(gs.color))
+    probes = d(probes_np)
+    env = d(sc.env)
+    pts = sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                     view=d(sc.view))
+    grad = d(grad_np)
+    tex = torch.empty((P, R, R, 4), dtype=torch.float32, device=dev)
+    dep = torch.empty((P, R, R), dtype=torch.float32, device=dev)
+    rgb = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    g_env = torch.zeros(env.shape, dtype=torch.float32, device=dev)
+    g_tex = torch.zeros(tex.shape, dtype=torch.float32, device=dev)
+
+    bake_plan = sop.BakePlan(g_mean, g_scale, g_rot, g_op, g_col)
+    plan = sop.Plan(probes, sc.bounds_lo, sc.bounds_hi)
+    ws_f = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE, N, K, S, True), dev)
+    ws_b = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE_BACKWARD, N, K, S, True), dev)
+
+    names = ["bake", "probe_grid", "knn", "shade_fwd", "shade_bwd"]
+    ev = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for n in names}
+    acc = {n: 0.0 for n in names}
+
+    def step(timed: bool):
+        def mark(n, i):
+            if timed:
+                ev[n][i].record()
+        mark("bake", 0)
+        bake_plan.update(g_mean, g_scale, g_rot, g_op, g_col)
+        sop.sop_bake(bake_plan, probes, R, texels=tex, depth_out=dep)
+        mark("bake", 1)
+        mark("probe_grid", 0)
+        plan.rebuild(probes)
+        mark("probe_grid", 1)
+        mark("knn", 0)
+        nb = sop.sop_knn(plan, pts, K)
+        mark("knn", 1)
+        mark("shade_fwd", 0)
+        sop.sop_shade(plan, tex, env, pts, S, nb=nb, ws=ws_f, out=rgb)
+        mark("shade_fwd", 1)
+        g_env.zero_()
+        g_tex.zero_()
+        mark("shade_bwd", 0)
+        sop.sop_shade_backward(plan, tex, env, pts, grad, S, nb=nb, g_env=g_env, g_tex=g_tex,
+                               ws=ws_b)
+        mark("shade_bwd", 1)
+        if timed:
+            torch.cuda.synchronize()
+            for n in names:
+                acc[n] += ev[n][0].elapsed_time(ev[n][1])
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    bake_plan.check()
+    assert bool(torch.isfinite(rgb).all()), "non-finite shading output"
+
+    # whole-step timing (no per-phase synchronisation inside)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step(False)
+    end.record()
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / args.steps
+
+    # per-phase timing in separate passes
+    for _ in range(args.steps):
+        step(True)
+    phase = {n: acc[n] / args.steps for n in names}
+    print(f"# phases (ms): {json.dumps({k: round(v, 4) for k, v in phase.items()})}",
+          file=sys.stderr, flush=True)
+
+    samples = N * S
+    value = samples / (ms_per_step * 1e-3)
+    fb_rate = samples / ((phase["shade_fwd"] + phase["shade_bwd"]) * 1e-3)
+
+    # roofline of the dominant kernel
+    dom = max(("shade_fwd", "shade_bwd", "bake"), key=lambda n: phase[n])
+    if dom == "bake":
+        roof = {"bound": "alu", "kernel": "k_bake", "achieved": None, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None,
+                "note": "data-dependent work per ray; see DESIGN.md"}
+    else:
+        f = flops_fwd(K) if dom == "shade_fwd" else flops_bwd(K)
+        achieved = samples * f / (phase[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_" + dom, "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "flops_per_sample": f, "samples_per_launch": samples}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sc, gs, probes_np, R, args.cpu_seconds, samples)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "object_scene: bake 100k Gaussians into 4096 probes x 32x32 "
+                               "texels, probe grid, kNN (K=8), shade fwd+bwd of 200k points "
+                               "x 128 directions, env 256x512",
+                   "points": N, "dirs": S, "k": K, "probes": P, "res": R, "gaussians": G},
+        "fwd_bwd_samples_per_s": round(fb_rate, 1),
+        "phase_ms": {k: round(v, 4) for k, v in phase.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
+    """The oracle on a bounded sample of the same workload, scaled to a whole step:
+    shade fwd+bwd (with its brute-force kNN) on a subset of points and the brute-force bake
+    on a subset of rays, each timed, then extrapolated to 200k points and 4.19M rays."""
+    import numpy as np
+
+    import oracle
+    threads = oracle.max_threads()
+    rng = np.random.default_rng(7)
+    # calibrate the shading sample on a small subset, then size it to about half the budget
+    def shade_time(m):
+        rows = rng.choice(sc.n, m, replace=False)
+        sub = sc.subset(rows)
+        grad = rng.standard_normal((m, 3))
+        t = time.time()
+        idx, w = oracle.knn(sub.probe_pos, sub.bounds_lo, sub.bounds_hi, sub.pos, sub.normal,
+                            sub.k)
+        oracle.shade(sub, idx, w)
+        oracle.shade_backward(sub, idx, w, grad)
+        return time.time() - t
+
+    t_small = shade_time(256)
+    m = int(min(sc.n, max(256, 256 * (0.5 * seconds) / max(t_small, 1e-3))))
+    t_shade = shade_time(m)
+    per_point = t_shade / m
+
+    P = probes_np.shape[0]
+    def bake_time(n):
+        rp = rng.integers(0, P, n).astype(np.int32)
+        rt = rng.integers(0, R * R, n).astype(np.int32)
+        t = time.time()
+        oracle.bake_rays(gs, probes_np.astype(np.float64), R, rp, rt)
+        return time.time() - t
+
+    t_b_small = bake_time(16)
+    nr = int(max(16, 16 * (0.5 * seconds) / max(t_b_small, 1e-3)))
+    t_bake = bake_time(nr)
+    per_ray = t_bake / nr
+
+    t_step = per_point * sc.n + per_ray * P * R * R
+    return {"value": round(sc.n * sc.n_dirs / t_step, 3), "unit": "samples/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"shade fwd+bwd with kNN on {m} of {sc.n} points ({t_shade:.1f}s) and "
+                      f"brute-force bake of {nr} of {P * R * R} rays ({t_bake:.1f}s), "
+                      f"extrapolated to one step; host CPU: {cpu_model()}",
+            "fwd_bwd_samples_per_s": round(sc.n_dirs / per_point, 1)}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

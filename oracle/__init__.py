@@ -77,7 +77,7 @@ def _sig(lib):
     lib.orc_shade_backward.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
                                        dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, iptr,
                                        dptr, C.c_int, C.c_int, u32, C.c_int, dptr, dptr, dptr,
-                                       dptr, dptr, dptr]
+                                       dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr]
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dptr, iptr]
@@ -314,9 +314,10 @@ def shade(sc, idx, w, albedo=None, rough=None, metal=None, texels=None, env=None
 
 
 def shade_backward(sc, idx, w, grad, albedo=None, rough=None, metal=None, texels=None,
-                   env=None, n_dirs=None, seed=None, per_point=False):
+                   env=None, n_dirs=None, seed=None, per_point=False, mass=False):
     """Analytic adjoint: dict with g_albedo [N,3], g_rough [N], g_metal [N],
-    g_tex [P,R,R,4], g_env [H,W,3] (texture gradients start from zero)."""
+    g_tex [P,R,R,4], g_env [H,W,3] (texture gradients start from zero). With mass=True
+    also m_* arrays of the same shapes: the sum of |term| of every gradient entry."""
     keep, a = _scene_args(sc, albedo, rough, metal, texels, env)
     idx, pi = _i(idx)
     w, pw = _d(w)
@@ -327,11 +328,16 @@ def shade_backward(sc, idx, w, grad, albedo=None, rough=None, metal=None, texels
         "g_tex": np.zeros(sc.texels.shape, np.float64),
         "g_env": np.zeros((sc.env if env is None else env).shape, np.float64),
     }
+    keys = ("albedo", "rough", "metal", "tex", "env")
+    if mass:
+        for k in keys:
+            out["m_" + k] = np.zeros_like(out["g_" + k])
     S = sc.n_dirs if n_dirs is None else n_dirs
     sd = sc.seed if seed is None else seed
     lib().orc_shade_backward(*a, pi, pw, idx.shape[1], S, sd, int(per_point), pg,
-                             *(out[k].ctypes.data_as(dptr) for k in
-                               ("g_albedo", "g_rough", "g_metal", "g_tex", "g_env")))
+                             *(out["g_" + k].ctypes.data_as(dptr) for k in keys),
+                             *((out["m_" + k].ctypes.data_as(dptr) if mass else None)
+                               for k in keys))
     del keep
     return out
 

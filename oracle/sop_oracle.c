@@ -252,7 +252,7 @@ void orc_quantize(const float x[3], const float lo[3], float sc, int32_t q[3]) {
     volatile float d = x[a] - lo[a];   /* single-precision subtract ...            */
     volatile float s = d * sc;         /* ... then single-precision multiply        */
     float f = floorf(s);
-    int32_t v = (f < 0.0f) ? 0 : (f > 32767.0f ? 32767 : (int32_t)f);
+    int32_t v = (f >= 0.0f) ? (f > 32767.0f ? 32767 : (int32_t)f) : 0;
     q[a] = v;
   }
 }
@@ -434,13 +434,17 @@ void orc_shade(long N, const double* pos, const double* normal, const double* vi
  *   d rgb_c / d O_k[t]     = -(2pi/S) f_c cos Lenv_c w_k b_t
  *   d rgb_c / d env[t',c]  = (2pi/S) f_c cos (1-O) b'_t'
  * Per-point outputs are overwritten; g_tex [P][R][R][4] and g_env [H][W][3] accumulate.
+ * The optional m_* outputs receive the sum of |term| of each gradient entry: the natural
+ * scale against which the rounding error of a sum of signed terms is measured.
  * ----------------------------------------------------------------------------------*/
 void orc_shade_backward(long N, const double* pos, const double* normal, const double* view,
                         const double* cam, long ppf, const double* albedo, const double* rough,
                         const double* metal, const double* tex, int R, const double* env,
                         int H, int W, const int32_t* idx, const double* wts, int K, int S,
                         uint32_t seed, int per_point, const double* grad, double* g_albedo,
-                        double* g_rough, double* g_metal, double* g_tex, double* g_env) {
+                        double* g_rough, double* g_metal, double* g_tex, double* g_env,
+                        double* m_albedo, double* m_rough, double* m_metal, double* m_tex,
+                        double* m_env) {
   orc_points pts = {N, pos, normal, view, cam, ppf, albedo, rough, metal};
   const double scale = 2.0 * OR_PI / S;
 #pragma omp parallel for schedule(dynamic, 16)
@@ -456,6 +460,7 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
     const int32_t* nb_idx = idx + i * K;
     const double* nb_w = wts + i * K;
     double ga[3] = {0, 0, 0}, gr = 0.0, gm = 0.0;
+    double ma[3] = {0, 0, 0}, mr = 0.0, mm = 0.0;   /* sums of |term| (summation scale) */
     for (int j = 0; j < S; ++j) {
       double w[3];
       double ct = orc_direction(j, S, rho, n, w);
@@ -488,9 +493,11 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
         double F0 = 0.04 * (1.0 - m) + a[c] * m;
         double F = F0 + (1.0 - F0) * x5;
         double common = g[c] * scale * Li[c] * ct;
-        ga[c] += common * ((1.0 - m) / OR_PI + D * G * spec * m * (1.0 - x5));
-        gm += common * (-a[c] / OR_PI + D * G * spec * (a[c] - 0.04) * (1.0 - x5));
-        gr += common * F * spec * (dD * G + D * dG) * 2.0 * r;
+        double ta = common * ((1.0 - m) / OR_PI + D * G * spec * m * (1.0 - x5));
+        double tm = common * (-a[c] / OR_PI + D * G * spec * (a[c] - 0.04) * (1.0 - x5));
+        double tr = common * F * spec * (dD * G + D * dG) * 2.0 * r;
+        ga[c] += ta; gm += tm; gr += tr;
+        ma[c] += fabs(ta); mm += fabs(tm); mr += fabs(tr);
       }
       /* texture adjoints */
       double gl[3], go = 0.0, ge[3];
@@ -508,14 +515,23 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
         for (int s = 0; s < K; ++s) {
           if (nb_idx[s] < 0) continue;
           double* G_T = g_tex + (size_t)nb_idx[s] * R * R * 4;
+          double* M_T = m_tex ? m_tex + (size_t)nb_idx[s] * R * R * 4 : NULL;
           for (int t = 0; t < 4; ++t) {
             double cw = nb_w[s] * bt[t];
             for (int c = 0; c < 3; ++c) {
 #pragma omp atomic
               G_T[(size_t)tap[t] * 4 + c] += cw * gl[c];
+              if (M_T) {
+#pragma omp atomic
+                M_T[(size_t)tap[t] * 4 + c] += fabs(cw * gl[c]);
+              }
             }
 #pragma omp atomic
             G_T[(size_t)tap[t] * 4 + 3] += cw * go;
+            if (M_T) {
+#pragma omp atomic
+              M_T[(size_t)tap[t] * 4 + 3] += fabs(cw * go);
+            }
           }
         }
       }
@@ -527,12 +543,19 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
           for (int c = 0; c < 3; ++c) {
 #pragma omp atomic
             g_env[(size_t)tap[t] * 3 + c] += bt[t] * ge[c];
+            if (m_env) {
+#pragma omp atomic
+              m_env[(size_t)tap[t] * 3 + c] += fabs(bt[t] * ge[c]);
+            }
           }
       }
     }
     if (g_albedo) for (int c = 0; c < 3; ++c) g_albedo[3 * i + c] = ga[c];
     if (g_rough) g_rough[i] = gr;
     if (g_metal) g_metal[i] = gm;
+    if (m_albedo) for (int c = 0; c < 3; ++c) m_albedo[3 * i + c] = ma[c];
+    if (m_rough) m_rough[i] = mr;
+    if (m_metal) m_metal[i] = mm;
   }
 }
 
@@ -546,7 +569,8 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
  * stops before a Gaussian that would take T (1 - alpha) below T_min.
  * A ray is flagged ambiguous when a decision lies within a float32 margin of its cut:
  * alpha within 1e-3 (relative) of alpha_min, t* within 1e-5 of t_min, T (1 - alpha)
- * within 1e-2 (relative) of T_min, or two consecutive composited t* closer than 1e-5.
+ * within 1e-2 (relative) of T_min, or two consecutive composited t* closer than
+ * 1e-6 max(1, t*) (about ten times the float32 rounding of t*).
  * ----------------------------------------------------------------------------------*/
 static void quat_to_rot(const double q_in[4], double Rm[3][3]) {
   double q[4] = {q_in[0], q_in[1], q_in[2], q_in[3]};
@@ -624,7 +648,7 @@ static int trace_ray(int G, const double* mean, const double* SI, const double* 
     double Tn = T * (1.0 - al);
     if (fabs(Tn - T_min) <= 1e-2 * T_min) amb = 1;
     if (Tn < T_min) { t_stop = hits[s].t; break; }
-    if (s > 0 && hits[s].t - hits[s - 1].t < 1e-5) amb = 1;
+    if (s > 0 && hits[s].t - hits[s - 1].t < 1e-6 * fmax(1.0, hits[s].t)) amb = 1;
     int g = hits[s].idx;
     for (int c = 0; c < 3; ++c) C[c] += T * al * color[3 * g + c];
     Dp += T * al * hits[s].t;

@@ -1,0 +1,810 @@
+// api.cpp - host side of the SOP C ABI: argument validation before any device work,
+// plan objects, workspace carving and stream-ordered dispatch of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sop_internal.hpp"
+
+using sopk::Bump;
+
+namespace {
+
+thread_local std::string g_err;
+
+sop_status fail(sop_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+sop_status hip_fail(hipError_t e, const char* where) {
+  return fail(SOP_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SOP_HIP(expr, where)                      \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// lattice scale: 32768 / max_axis(hi - lo) in IEEE single precision
+float lattice_scale(const float lo[3], const float hi[3]) {
+  float ext = hi[0] - lo[0];
+  const float e1 = hi[1] - lo[1], e2 = hi[2] - lo[2];
+  if (e1 > ext) ext = e1;
+  if (e2 > ext) ext = e2;
+  return 32768.0f / ext;
+}
+
+uint32_t radius_limit(float radius, float sc) {
+  const double rq = (double)radius * (double)sc;
+  const double r2 = rq * rq;
+  if (!(r2 < 4294967295.0)) return 0xFFFFFFFFu;
+  return (uint32_t)std::floor(r2);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// probe plan
+// ------------------------------------------------------------------------------------------
+struct sop_plan {
+  int32_t P = 0;
+  float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  float sc = 0.0f;
+  int32_t bits = 1;
+  size_t C = 0;
+  int4* qsorted = nullptr;
+  int4* qtmp = nullptr;
+  int32_t* counts = nullptr;
+  int32_t* cell_start = nullptr;
+  int32_t* cursor = nullptr;
+  float* pos = nullptr;
+  int32_t* scan_tmp = nullptr;
+
+  sopk::ProbeGrid view() const {
+    sopk::ProbeGrid g;
+    g.P = P;
+    g.bits = bits;
+    g.shift = 15 - bits;
+    for (int a = 0; a < 3; ++a) g.lo[a] = lo[a];
+    g.sc = sc;
+    g.qsorted = qsorted;
+    g.cell_start = cell_start;
+    g.pos = pos;
+    return g;
+  }
+  void release() {
+    void* ptrs[] = {qsorted, qtmp, counts, cell_start, cursor, pos, scan_tmp};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    qsorted = qtmp = nullptr;
+    counts = cell_start = cursor = scan_tmp = nullptr;
+    pos = nullptr;
+  }
+};
+
+static int32_t grid_bits_for(int32_t P) {
+  // about one grid cell per probe along a surface: cbrt(P) cells per axis, doubled
+  const double c = std::cbrt((double)(P > 1 ? P : 1));
+  int b = (int)std::lround(std::log2(c)) + 1;
+  if (b < 1) b = 1;
+  if (b > 7) b = 7;
+  return b;
+}
+
+static sop_status validate_probe_set(const sop_probe_set* probes) {
+  if (!probes) return fail(SOP_ERR_INVALID_ARGUMENT, "probes is NULL");
+  if (probes->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "probes->count < 0");
+  if (probes->count > 0 && (!probes->pos || !aligned(probes->pos, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "probes->pos is NULL or misaligned");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(probes->bounds_lo[a]) || !std::isfinite(probes->bounds_hi[a]) ||
+        !(probes->bounds_hi[a] > probes->bounds_lo[a]))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "bounds must be finite with hi > lo on every axis");
+  }
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_plan_create(const sop_probe_set* probes, sop_stream stream,
+                                      sop_plan** out) {
+  if (!out) return fail(SOP_ERR_INVALID_ARGUMENT, "out is NULL");
+  sop_status st = validate_probe_set(probes);
+  if (st != SOP_OK) return st;
+  sop_plan* pl = new (std::nothrow) sop_plan();
+  if (!pl) return fail(SOP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  pl->P = probes->count;
+  for (int a = 0; a < 3; ++a) {
+    pl->lo[a] = probes->bounds_lo[a];
+    pl->hi[a] = probes->bounds_hi[a];
+  }
+  pl->sc = lattice_scale(pl->lo, pl->hi);
+  pl->bits = grid_bits_for(pl->P);
+  pl->C = (size_t)1 << (3 * pl->bits);
+  const size_t P1 = pl->P > 0 ? (size_t)pl->P : 1;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  alloc((void**)&pl->qsorted, P1 * sizeof(int4));
+  alloc((void**)&pl->qtmp, P1 * sizeof(int4));
+  alloc((void**)&pl->counts, pl->C * sizeof(int32_t));
+  alloc((void**)&pl->cell_start, (pl->C + 1) * sizeof(int32_t));
+  alloc((void**)&pl->cursor, pl->C * sizeof(int32_t));
+  alloc((void**)&pl->pos, P1 * 3 * sizeof(float));
+  alloc((void**)&pl->scan_tmp, sopk::scan_tmp_elems(pl->C) * sizeof(int32_t));
+  if (e != hipSuccess) {
+    pl->release();
+    delete pl;
+    (void)hipGetLastError();
+    return fail(SOP_ERR_OUT_OF_MEMORY, std::string("plan allocation: ") + hipGetErrorString(e));
+  }
+  e = sopk::launch_probe_grid_build(probes->pos, pl->P, pl->lo, pl->sc, pl->bits, pl->qtmp,
+                                    pl->counts, pl->cell_start, pl->cursor, pl->qsorted, pl->pos,
+                                    pl->scan_tmp, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    pl->release();
+    delete pl;
+    return hip_fail(e, "sop_plan_create");
+  }
+  *out = pl;
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_plan_rebuild(sop_plan* plan, const float* pos, sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (plan->P > 0 && (!pos || !aligned(pos, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "pos is NULL or misaligned");
+  SOP_HIP(sopk::launch_probe_grid_build(pos, plan->P, plan->lo, plan->sc, plan->bits,
+                                        plan->qtmp, plan->counts, plan->cell_start,
+                                        plan->cursor, plan->qsorted, plan->pos, plan->scan_tmp,
+                                        (hipStream_t)stream),
+          "sop_plan_rebuild");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_plan_destroy(sop_plan* plan) {
+  if (!plan) return SOP_OK;
+  plan->release();
+  delete plan;
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_plan_info(const sop_plan* plan, int32_t* n_probes,
+                                    int32_t grid_dims[3], float* lattice_scale_out) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (n_probes) *n_probes = plan->P;
+  if (grid_dims)
+    for (int a = 0; a < 3; ++a) grid_dims[a] = 1 << plan->bits;
+  if (lattice_scale_out) *lattice_scale_out = plan->sc;
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// workspace
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct KnnScratch {
+  int32_t* point_cell;
+  int32_t* counts;
+  int32_t* offsets;
+  int32_t* scan_tmp;
+};
+
+KnnScratch carve_knn(Bump& b, const sop_plan* plan, int64_t N) {
+  KnnScratch k;
+  k.point_cell = b.take<int32_t>((size_t)N);
+  k.counts = b.take<int32_t>(plan->C);
+  k.offsets = b.take<int32_t>(plan->C + 1);
+  k.scan_tmp = b.take<int32_t>(sopk::scan_tmp_elems(plan->C));
+  return k;
+}
+
+struct NbScratch {
+  int32_t* order;
+  int32_t* idx;
+  float* w;
+};
+
+NbScratch carve_nb(Bump& b, int64_t N, int32_t k) {
+  NbScratch s;
+  s.order = b.take<int32_t>((size_t)N);
+  s.idx = b.take<int32_t>((size_t)N * k);
+  s.w = b.take<float>((size_t)N * k);
+  return s;
+}
+
+// Workspace layout: [direction table (shade ops)] [order, idx, w] [search scratch]
+size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool with_nb,
+                 int32_t n_dirs) {
+  Bump b{nullptr, 0, 0};
+  if (op == SOP_OP_KNN) {
+    (void)b.take<int32_t>((size_t)N);   // order when the caller passes none
+    carve_knn(b, plan, N);
+    return b.used;
+  }
+  if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD) (void)b.take<double4>((size_t)n_dirs);
+  if (!with_nb) {
+    carve_nb(b, N, k);
+    carve_knn(b, plan, N);
+  }
+  return b.used;
+}
+
+sop_status validate_points(const sop_points* pts) {
+  if (!pts) return fail(SOP_ERR_INVALID_ARGUMENT, "pts is NULL");
+  if (pts->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "pts->count < 0");
+  if (pts->count > INT32_MAX) return fail(SOP_ERR_UNSUPPORTED, "more than 2^31-1 points");
+  if (pts->count == 0) return SOP_OK;
+  const void* req[] = {pts->pos, pts->normal, pts->albedo, pts->roughness, pts->metallic};
+  for (const void* p : req)
+    if (!p || !aligned(p, 4))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "a point array is NULL or misaligned");
+  if (pts->view) {
+    if (!aligned(pts->view, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "view misaligned");
+  } else {
+    if (!pts->cam_pos || !aligned(pts->cam_pos, 4) || pts->points_per_frame < 1 ||
+        pts->n_frames < 1 || (int64_t)pts->n_frames * pts->points_per_frame != pts->count)
+      return fail(SOP_ERR_INVALID_ARGUMENT,
+                  "view is NULL: need cam_pos and n_frames * points_per_frame == count");
+  }
+  return SOP_OK;
+}
+
+sop_status validate_maps(const sop_plan* plan, const sop_probe_maps* maps) {
+  if (!maps) return fail(SOP_ERR_INVALID_ARGUMENT, "maps is NULL");
+  if (maps->res < 2 || maps->res > SOP_MAX_RES)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "maps->res out of [2, 256]");
+  if (maps->format != SOP_TEXEL_F32 && maps->format != SOP_TEXEL_F16)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "unknown texel format");
+  const size_t al = maps->format == SOP_TEXEL_F32 ? 16 : 8;
+  if (plan->P > 0 && (!maps->texels || !aligned(maps->texels, al)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "maps->texels is NULL or misaligned");
+  return SOP_OK;
+}
+
+sop_status validate_env(const sop_envmap* env) {
+  if (!env) return fail(SOP_ERR_INVALID_ARGUMENT, "env is NULL");
+  if (env->height < 1 || env->width < 1 || env->height > (1 << 16) || env->width > (1 << 16))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "env size out of range");
+  if (!env->texels || !aligned(env->texels, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "env->texels is NULL or misaligned");
+  return SOP_OK;
+}
+
+sop_status validate_nb(const sop_neighbors* nb) {
+  if (nb->k < 1 || nb->k > SOP_MAX_K) return fail(SOP_ERR_INVALID_ARGUMENT, "nb->k out of [1,16]");
+  if (!nb->idx || !nb->weight || !aligned(nb->idx, 4) || !aligned(nb->weight, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "nb->idx/weight NULL or misaligned");
+  if (nb->order && !aligned(nb->order, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "nb->order misaligned");
+  return SOP_OK;
+}
+
+sop_status validate_k_radius(int32_t k, float radius) {
+  if (k < 1 || k > SOP_MAX_K) return fail(SOP_ERR_INVALID_ARGUMENT, "k out of [1, 16]");
+  if (std::isnan(radius) || !(radius > 0.0f))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "radius must be > 0 (or +inf)");
+  return SOP_OK;
+}
+
+sop_status validate_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return SOP_OK;
+  if (!ws || !aligned(ws, 256))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(SOP_ERR_WORKSPACE_TOO_SMALL,
+                "workspace too small: need " + std::to_string(need) + " bytes");
+  return SOP_OK;
+}
+
+// neighbour search into caller- or workspace-provided buffers
+hipError_t run_knn(const sop_plan* plan, const sop_points* pts, int32_t k, float radius,
+                   int32_t* order, int32_t* idx, float* w, KnnScratch ks, hipStream_t s) {
+  const sopk::ProbeGrid g = plan->view();
+  hipError_t e = sopk::launch_point_order(g, pts->pos, pts->count, ks.point_cell, ks.counts,
+                                          ks.offsets, ks.scan_tmp, order, s);
+  if (e != hipSuccess) return e;
+  return sopk::launch_knn(g, pts->pos, pts->normal, pts->count, order, k,
+                          radius_limit(radius, plan->sc), idx, w, s);
+}
+
+}  // namespace
+
+extern "C" size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points,
+                                     int32_t k, int32_t n_dirs, int32_t with_neighbors) {
+  (void)n_dirs;
+  if (!plan || n_points < 0 || k < 1 || k > SOP_MAX_K) return 0;
+  if (op < SOP_OP_KNN || op > SOP_OP_SHADE_BACKWARD) return 0;
+  size_t need = ws_needed(plan, op, n_points, k, with_neighbors != 0, n_dirs > 0 ? n_dirs : 1);
+  return need > 0 ? need : 256;
+}
+
+// ------------------------------------------------------------------------------------------
+// neighbour search and query
+// ------------------------------------------------------------------------------------------
+extern "C" sop_status sop_knn(const sop_plan* plan, const sop_points* pts, int32_t k,
+                              float radius, int32_t* order, int32_t* idx, float* w, void* ws,
+                              size_t ws_bytes, sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  sop_status st = validate_points(pts);
+  if (st != SOP_OK) return st;
+  if ((st = validate_k_radius(k, radius)) != SOP_OK) return st;
+  if (pts->count > 0 && (!idx || !w || !aligned(idx, 4) || !aligned(w, 4) ||
+                         (order && !aligned(order, 4))))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "idx/w NULL or misaligned");
+  const size_t need = ws_needed(plan, SOP_OP_KNN, pts->count, k, false, 1);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  Bump b{(char*)ws, 0, ws_bytes};
+  int32_t* ws_order = b.take<int32_t>((size_t)pts->count);
+  KnnScratch ks = carve_knn(b, plan, pts->count);
+  SOP_HIP(run_knn(plan, pts, k, radius, order ? order : ws_order, idx, w, ks,
+                  (hipStream_t)stream),
+          "sop_knn");
+  return SOP_OK;
+}
+
+namespace {
+
+sopk::ShadeArgs base_args(const sop_plan* plan, const sop_probe_maps* maps, const sop_points* pts) {
+  sopk::ShadeArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = pts->count;
+  a.pos = pts->pos;
+  a.nrm = pts->normal;
+  a.view = pts->view;
+  a.cam = pts->cam_pos;
+  a.ppf = pts->points_per_frame > 0 ? pts->points_per_frame : 1;
+  a.albedo = pts->albedo;
+  a.rough = pts->roughness;
+  a.metal = pts->metallic;
+  a.P = plan->P;
+  a.tex = maps->texels;
+  a.R = maps->res;
+  a.halfR = 0.5f * (float)maps->res;
+  return a;
+}
+
+// resolves the neighbour lists: the caller's, or a search into the workspace
+sop_status resolve_nb(const sop_plan* plan, const sop_points* pts, const sop_neighbors* nb,
+                      int32_t k, float radius, Bump& b, hipStream_t s,
+                      const int32_t** order, const int32_t** idx, const float** w,
+                      int32_t* k_out) {
+  if (nb) {
+    *order = nb->order;
+    *idx = nb->idx;
+    *w = nb->weight;
+    *k_out = nb->k;
+    return SOP_OK;
+  }
+  NbScratch ns = carve_nb(b, pts->count, k);
+  KnnScratch ks = carve_knn(b, plan, pts->count);
+  SOP_HIP(run_knn(plan, pts, k, radius, ns.order, ns.idx, ns.w, ks, s), "neighbour search");
+  *order = ns.order;
+  *idx = ns.idx;
+  *w = ns.w;
+  *k_out = k;
+  return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps,
+                                const sop_points* pts, const sop_neighbors* nb,
+                                const float* dirs, int32_t n_dirs, int32_t k, float radius,
+                                float* L_in, float* O, void* ws, size_t ws_bytes,
+                                sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  sop_status st = validate_points(pts);
+  if (st != SOP_OK) return st;
+  if ((st = validate_maps(plan, maps)) != SOP_OK) return st;
+  if (nb) {
+    if ((st = validate_nb(nb)) != SOP_OK) return st;
+  } else if ((st = validate_k_radius(k, radius)) != SOP_OK) {
+    return st;
+  }
+  if (n_dirs < 1 || n_dirs > SOP_MAX_DIRS)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
+  if (pts->count > 0 && (!dirs || !L_in || !O || !aligned(dirs, 4) || !aligned(L_in, 4) ||
+                         !aligned(O, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "dirs/L_in/O NULL or misaligned");
+  const size_t need =
+      ws_needed(plan, SOP_OP_QUERY, pts->count, nb ? nb->k : k, nb != nullptr, n_dirs);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a = base_args(plan, maps, pts);
+  int32_t kk;
+  Bump b{(char*)ws, 0, ws_bytes};
+  if ((st = resolve_nb(plan, pts, nb, k, radius, b, s, &a.order, &a.nb_idx, &a.nb_w, &kk)) !=
+      SOP_OK)
+    return st;
+  SOP_HIP(sopk::launch_query(a, kk, maps->format, dirs, n_dirs, L_in, O, s), "sop_query");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// shading
+// ------------------------------------------------------------------------------------------
+namespace {
+
+sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
+                          const sop_envmap* env, const sop_points* pts,
+                          const sop_neighbors* nb, const sop_shade_opts* o) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!o) return fail(SOP_ERR_INVALID_ARGUMENT, "opts is NULL");
+  sop_status st = validate_points(pts);
+  if (st != SOP_OK) return st;
+  if ((st = validate_maps(plan, maps)) != SOP_OK) return st;
+  if ((st = validate_env(env)) != SOP_OK) return st;
+  if (nb) {
+    if ((st = validate_nb(nb)) != SOP_OK) return st;
+  } else if ((st = validate_k_radius(o->k, o->radius)) != SOP_OK) {
+    return st;
+  }
+  if (o->n_dirs < 1 || o->n_dirs > SOP_MAX_DIRS)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
+  if (o->sampler != SOP_SAMPLER_HAMMERSLEY)
+    return fail(SOP_ERR_UNSUPPORTED, "unknown sampler");
+  if (o->out_irradiance && !aligned(o->out_irradiance, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "out_irradiance misaligned");
+  return SOP_OK;
+}
+
+void set_dirs(sopk::ShadeArgs& a, const sop_envmap* env, const sop_shade_opts* o) {
+  a.env = env->texels;
+  a.H = env->height;
+  a.W = env->width;
+  a.u_scale = (float)((double)env->width / (2.0 * M_PI));
+  a.v_scale = (float)((double)env->height / M_PI);
+  a.S = o->n_dirs;
+  a.inv2S = (float)(1.0 / (2.0 * o->n_dirs));
+  a.scale = (float)(2.0 * M_PI / o->n_dirs);
+  a.seed = o->seed;
+  a.per_point = o->rotate_per_point ? 1 : 0;
+}
+
+// the call's direction table, first piece of the workspace
+sop_status setup_dirs(sopk::ShadeArgs& a, Bump& b, const sop_shade_opts* o, hipStream_t s) {
+  double4* tab = b.take<double4>((size_t)o->n_dirs);
+  a.dir_tab = tab;
+  SOP_HIP(sopk::launch_dir_table(o->n_dirs, o->seed, o->rotate_per_point ? 1 : 0, tab, s),
+          "direction table");
+  return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps,
+                                const sop_envmap* env, const sop_points* pts,
+                                const sop_neighbors* nb, const sop_shade_opts* opts,
+                                float* rgb, void* ws, size_t ws_bytes, sop_stream stream) {
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts);
+  if (st != SOP_OK) return st;
+  if (pts->count > 0 && (!rgb || !aligned(rgb, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "rgb is NULL or misaligned");
+  const int32_t k = nb ? nb->k : opts->k;
+  const size_t need = ws_needed(plan, SOP_OP_SHADE, pts->count, k, nb != nullptr, opts->n_dirs);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a = base_args(plan, maps, pts);
+  set_dirs(a, env, opts);
+  a.rgb = rgb;
+  a.irr = opts->out_irradiance;
+  int32_t kk;
+  Bump b{(char*)ws, 0, ws_bytes};
+  if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
+  if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
+                       &a.nb_w, &kk)) != SOP_OK)
+    return st;
+  SOP_HIP(sopk::launch_shade_fwd(a, kk, maps->format, s), "sop_shade");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_maps* maps,
+                                         const sop_envmap* env, const sop_points* pts,
+                                         const sop_neighbors* nb, const sop_shade_opts* opts,
+                                         const float* grad_rgb, float* g_albedo,
+                                         float* g_rough, float* g_metal, float* g_env,
+                                         float* g_tex, void* ws, size_t ws_bytes,
+                                         sop_stream stream) {
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts);
+  if (st != SOP_OK) return st;
+  if (pts->count > 0 && (!grad_rgb || !aligned(grad_rgb, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "grad_rgb is NULL or misaligned");
+  const void* outs[] = {g_albedo, g_rough, g_metal, g_env, g_tex};
+  for (const void* p : outs)
+    if (p && !aligned(p, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "a gradient is misaligned");
+  const int32_t k = nb ? nb->k : opts->k;
+  const size_t need =
+      ws_needed(plan, SOP_OP_SHADE_BACKWARD, pts->count, k, nb != nullptr, opts->n_dirs);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a = base_args(plan, maps, pts);
+  set_dirs(a, env, opts);
+  a.grad = grad_rgb;
+  a.g_albedo = g_albedo;
+  a.g_rough = g_rough;
+  a.g_metal = g_metal;
+  a.g_env = g_env;
+  a.g_tex = g_tex;
+  int32_t kk;
+  Bump b{(char*)ws, 0, ws_bytes};
+  if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
+  if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
+                       &a.nb_w, &kk)) != SOP_OK)
+    return st;
+  SOP_HIP(sopk::launch_shade_bwd(a, kk, maps->format, s), "sop_shade_backward");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// bake
+// ------------------------------------------------------------------------------------------
+struct sop_bake_plan {
+  int32_t G = 0;
+  sop_bake_opts opts{};
+  float4* gdata = nullptr;
+  float4* aabb = nullptr;
+  int32_t* counts = nullptr;
+  int32_t* cell_start = nullptr;
+  int32_t* cursor = nullptr;
+  int32_t* entries = nullptr;
+  int32_t capacity = 0;
+  int32_t* scan_tmp = nullptr;
+  int32_t* misc = nullptr;   // [0..5] bounds (ordered ints), [6] n_reg, [7] overflow, [8] ext (float)
+  sopk::BakeGrid grid{};
+  size_t ncell = 0;
+
+  void release() {
+    void* ptrs[] = {gdata, aabb, counts, cell_start, cursor, entries, scan_tmp, misc};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    gdata = aabb = nullptr;
+    counts = cell_start = cursor = entries = scan_tmp = misc = nullptr;
+  }
+};
+
+namespace {
+
+float ord2f(int32_t v) {
+  const int32_t b = v >= 0 ? v : v ^ 0x7FFFFFFF;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+sop_status validate_gaussians(const sop_gaussians* g) {
+  if (!g) return fail(SOP_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+  if (g->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "gaussians->count < 0");
+  if (g->count == 0) return SOP_OK;
+  const void* req[] = {g->mean, g->scale, g->rotation, g->opacity, g->color};
+  for (const void* p : req)
+    if (!p || !aligned(p, 4))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "a Gaussian array is NULL or misaligned");
+  return SOP_OK;
+}
+
+sop_bake_opts resolve_bake_opts(const sop_bake_opts* o) {
+  sop_bake_opts r;
+  r.t_min = 0.0f;
+  r.alpha_min = 1.0f / 255.0f;
+  r.alpha_max = 0.99f;
+  r.T_min = 1e-4f;
+  if (o) r = *o;
+  return r;
+}
+
+hipError_t register_gaussians(sop_bake_plan* pl, hipStream_t s) {
+  hipError_t e = sopk::launch_fill_i32(pl->counts, 0, pl->ncell, s);
+  if (e == hipSuccess) e = sopk::launch_fill_i32(pl->cursor, 0, pl->ncell, s);
+  if (e == hipSuccess) e = sopk::launch_gauss_count(pl->grid, pl->aabb, pl->counts, pl->misc + 7, s);
+  if (e == hipSuccess)
+    e = sopk::launch_exclusive_scan(pl->counts, pl->cell_start, pl->ncell, pl->scan_tmp, s);
+  return e;
+}
+
+}  // namespace
+
+extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bake_opts* opts,
+                                           sop_stream stream, sop_bake_plan** out) {
+  if (!out) return fail(SOP_ERR_INVALID_ARGUMENT, "out is NULL");
+  sop_status st = validate_gaussians(g);
+  if (st != SOP_OK) return st;
+  const sop_bake_opts o = resolve_bake_opts(opts);
+  if (!(o.alpha_min > 0.0f) || !(o.alpha_max >= o.alpha_min) || !(o.alpha_max < 1.0f) ||
+      !(o.T_min > 0.0f) || !std::isfinite(o.t_min))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "bake options out of range");
+  const hipStream_t s = (hipStream_t)stream;
+  sop_bake_plan* pl = new (std::nothrow) sop_bake_plan();
+  if (!pl) return fail(SOP_ERR_OUT_OF_MEMORY, "host allocation failed");
+  pl->G = g->count;
+  pl->opts = o;
+  const size_t G1 = g->count > 0 ? (size_t)g->count : 1;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+  };
+  alloc((void**)&pl->gdata, G1 * 4 * sizeof(float4));
+  alloc((void**)&pl->aabb, G1 * 2 * sizeof(float4));
+  alloc((void**)&pl->misc, 16 * sizeof(int32_t));
+  auto bail = [&](sop_status code, const std::string& msg) {
+    pl->release();
+    delete pl;
+    return fail(code, msg);
+  };
+  if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake plan allocation");
+  int32_t init[16] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0,
+                      0, 0, 0, 0, 0, 0, 0, 0};
+  e = hipMemcpyAsync(pl->misc, init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = sopk::launch_gauss_prep(*g, o.alpha_min, pl->gdata, pl->aabb, pl->misc,
+                                reinterpret_cast<float*>(pl->misc + 8), pl->misc + 6, s);
+  int32_t host[16];
+  if (e == hipSuccess) e = hipMemcpyAsync(host, pl->misc, sizeof(host), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(SOP_ERR_DEVICE, std::string("bake plan: ") + hipGetErrorString(e));
+
+  // grid geometry: the box around all cut-off boxes, cells about one Gaussian box wide
+  sopk::BakeGrid& G = pl->grid;
+  G.G = g->count;
+  const int32_t n_reg = host[6];
+  float ext_sum;
+  std::memcpy(&ext_sum, &host[8], 4);
+  if (n_reg > 0) {
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = ord2f(host[a]);
+      hi[a] = ord2f(host[3 + a]);
+      const float pad = 1e-4f * (hi[a] - lo[a]) + 1e-5f;
+      lo[a] -= pad;
+      hi[a] += pad;
+    }
+    double h = (double)ext_sum / n_reg;
+    if (!(h > 0)) h = 1.0;
+    for (;;) {
+      size_t cells = 1;
+      for (int a = 0; a < 3; ++a) {
+        const double n = std::ceil((hi[a] - lo[a]) / h);
+        G.dims[a] = (int32_t)std::max(1.0, std::min(n, 1024.0));
+        cells *= (size_t)G.dims[a];
+      }
+      if (cells <= ((size_t)1 << 24)) break;
+      h *= 1.25;
+    }
+    for (int a = 0; a < 3; ++a) {
+      G.origin[a] = lo[a];
+      G.cell[a] = (hi[a] - lo[a]) / (float)G.dims[a];
+      G.inv_cell[a] = 1.0f / G.cell[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      G.dims[a] = 0;
+      G.origin[a] = 0.0f;
+      G.cell[a] = 1.0f;
+      G.inv_cell[a] = 1.0f;
+    }
+  }
+  G.t_min = o.t_min;
+  G.alpha_min = o.alpha_min;
+  G.alpha_max = o.alpha_max;
+  G.T_min = o.T_min;
+  pl->ncell = (size_t)G.dims[0] * G.dims[1] * G.dims[2];
+  const size_t C1 = pl->ncell > 0 ? pl->ncell : 1;
+  alloc((void**)&pl->counts, C1 * sizeof(int32_t));
+  alloc((void**)&pl->cell_start, (C1 + 1) * sizeof(int32_t));
+  alloc((void**)&pl->cursor, C1 * sizeof(int32_t));
+  alloc((void**)&pl->scan_tmp, sopk::scan_tmp_elems(C1) * sizeof(int32_t));
+  if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake grid allocation");
+  int32_t total = 0;
+  e = register_gaussians(pl, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&total, pl->cell_start + pl->ncell, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(SOP_ERR_DEVICE, std::string("bake grid: ") + hipGetErrorString(e));
+  const int64_t cap = (int64_t)total + total / 4 + 1024;
+  if (cap > INT32_MAX) return bail(SOP_ERR_UNSUPPORTED, "too many grid registrations");
+  pl->capacity = (int32_t)cap;
+  alloc((void**)&pl->entries, (size_t)pl->capacity * sizeof(int32_t));
+  if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake entries allocation");
+  e = sopk::launch_gauss_fill(G, pl->aabb, pl->cell_start, pl->cursor, pl->entries,
+                              pl->capacity, pl->misc + 7, s);
+  if (e != hipSuccess) return bail(SOP_ERR_DEVICE, std::string("bake fill: ") + hipGetErrorString(e));
+  G.gdata = pl->gdata;
+  G.cell_start = pl->cell_start;
+  G.entries = pl->entries;
+  G.capacity = pl->capacity;
+  G.overflow = pl->misc + 7;
+  *out = pl;
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_bake_plan_update(sop_bake_plan* plan, const sop_gaussians* g,
+                                           sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  sop_status st = validate_gaussians(g);
+  if (st != SOP_OK) return st;
+  if (g->count != plan->G)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "update needs the Gaussian count of the plan");
+  const hipStream_t s = (hipStream_t)stream;
+  SOP_HIP(sopk::launch_fill_i32(plan->misc + 7, 0, 1, s), "sop_bake_plan_update");
+  SOP_HIP(sopk::launch_gauss_prep(*g, plan->opts.alpha_min, plan->gdata, plan->aabb, nullptr,
+                                  nullptr, nullptr, s),
+          "sop_bake_plan_update");
+  if (plan->ncell == 0) {
+    if (plan->G > 0) SOP_HIP(sopk::launch_fill_i32(plan->misc + 7, 4, 1, s), "sop_bake_plan_update");
+    return SOP_OK;
+  }
+  SOP_HIP(register_gaussians(plan, s), "sop_bake_plan_update");
+  SOP_HIP(sopk::launch_gauss_fill(plan->grid, plan->aabb, plan->cell_start, plan->cursor,
+                                  plan->entries, plan->capacity, plan->misc + 7, s),
+          "sop_bake_plan_update");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_bake_plan_check(const sop_bake_plan* plan, sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  int32_t flag = 0;
+  SOP_HIP(hipMemcpyAsync(&flag, plan->misc + 7, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         (hipStream_t)stream),
+          "sop_bake_plan_check");
+  SOP_HIP(hipStreamSynchronize((hipStream_t)stream), "sop_bake_plan_check");
+  if (flag)
+    return fail(SOP_ERR_WORKSPACE_TOO_SMALL,
+                "Gaussian update exceeded the grid built at plan creation (flag " +
+                    std::to_string(flag) + ")");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_bake_plan_destroy(sop_bake_plan* plan) {
+  if (!plan) return SOP_OK;
+  plan->release();
+  delete plan;
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos,
+                               int32_t n_probes, int32_t res, float* texels, float* depth,
+                               sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (n_probes < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "n_probes < 0");
+  if (res < 2 || res > SOP_MAX_RES) return fail(SOP_ERR_INVALID_ARGUMENT, "res out of [2, 256]");
+  if (n_probes > 0 && (!probe_pos || !texels || !aligned(probe_pos, 4) || !aligned(texels, 16) ||
+                       (depth && !aligned(depth, 4))))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "probe_pos/texels NULL or misaligned");
+  if (n_probes == 0) return SOP_OK;
+  SOP_HIP(sopk::launch_bake(plan->grid, probe_pos, n_probes, res, texels, depth,
+                            (hipStream_t)stream),
+          "sop_bake");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+extern "C" const char* sop_status_string(sop_status s) {
+  switch (s) {
+    case SOP_OK: return "ok";
+    case SOP_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SOP_ERR_UNSUPPORTED: return "unsupported";
+    case SOP_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case SOP_ERR_DEVICE: return "device error";
+    case SOP_ERR_OUT_OF_MEMORY: return "out of memory";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* sop_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t sop_version(void) { return 100; }

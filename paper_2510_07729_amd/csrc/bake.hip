@@ -1,0 +1,349 @@
+// bake.hip - probe textures by ray tracing 3D Gaussians (ComGS Sec. 3.1.2: SOP textures
+// initialised by ray tracing; the compositing of Eq. 1).
+//
+// Every Gaussian is turned into its whitening map M = S^-1 R^T (ray in Gaussian units) and
+// registered in the cells of a uniform grid overlapped by the box around its cut-off
+// ellipsoid (where opacity * exp(-m^2/2) can reach alpha_min), padded for FP32 rounding.
+// One thread traces one texel's ray; a wavefront covers an 8x8 texel tile of one probe so
+// that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
+// composited in the cell whose t-window [t_enter, t_exit) holds its t*, and within a cell
+// candidates are taken in ascending (t*, index) through a small sorted register buffer
+// (refilled from the cell when it overflows), so the global order is ascending (t*, index).
+#include <float.h>
+
+#include "sop_device.hpp"
+#include "sop_internal.hpp"
+
+namespace sopk {
+
+__device__ __forceinline__ int f2ord(float f) {
+  const int b = __float_as_int(f);
+  return b >= 0 ? b : b ^ 0x7FFFFFFF;
+}
+
+// ------------------------------------------------------------------------------------------
+// per-Gaussian preparation
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gauss_prep(sop_gaussians g, float alpha_min,
+                                                    float4* gdata, float4* aabb,
+                                                    int32_t* bounds_ord, float* ext_sum,
+                                                    int32_t* n_reg) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.count) return;
+  float qw = g.rotation[4 * i], qx = g.rotation[4 * i + 1], qy = g.rotation[4 * i + 2],
+        qz = g.rotation[4 * i + 3];
+  const float ql = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= ql; qx *= ql; qy *= ql; qz *= ql;
+  // rotation matrix R (columns are the Gaussian's axes in world space)
+  const float R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz),
+              R02 = 2 * (qx * qz + qw * qy);
+  const float R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz),
+              R12 = 2 * (qy * qz - qw * qx);
+  const float R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx),
+              R22 = 1 - 2 * (qx * qx + qy * qy);
+  const float s0 = g.scale[3 * i], s1 = g.scale[3 * i + 1], s2 = g.scale[3 * i + 2];
+  const float i0 = 1.0f / s0, i1 = 1.0f / s1, i2 = 1.0f / s2;
+  const float mx = g.mean[3 * i], my = g.mean[3 * i + 1], mz = g.mean[3 * i + 2];
+  const float op = g.opacity[i];
+  // M = S^-1 R^T: row k is axis k divided by s_k
+  gdata[4 * i + 0] = make_float4(R00 * i0, R10 * i0, R20 * i0, mx);
+  gdata[4 * i + 1] = make_float4(R01 * i1, R11 * i1, R21 * i1, my);
+  gdata[4 * i + 2] = make_float4(R02 * i2, R12 * i2, R22 * i2, mz);
+  gdata[4 * i + 3] = make_float4(g.color[3 * i], g.color[3 * i + 1], g.color[3 * i + 2], op);
+  // cut-off: alpha >= alpha_min needs m^2 <= 2 ln(opacity / alpha_min)
+  const float m2max = op > alpha_min ? 2.0f * logf(op / alpha_min) : -1.0f;
+  if (!(m2max >= 0.0f)) {
+    aabb[2 * i] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);   // empty (lo > hi): not registered
+    aabb[2 * i + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
+  const float mm = sqrtf(m2max);
+  float hx = mm * sqrtf(R00 * R00 * s0 * s0 + R01 * R01 * s1 * s1 + R02 * R02 * s2 * s2);
+  float hy = mm * sqrtf(R10 * R10 * s0 * s0 + R11 * R11 * s1 * s1 + R12 * R12 * s2 * s2);
+  float hz = mm * sqrtf(R20 * R20 * s0 * s0 + R21 * R21 * s1 * s1 + R22 * R22 * s2 * s2);
+  // pad for FP32 decisions near the cut-off and cell boundaries
+  hx = hx * 1.002f + 1e-5f;
+  hy = hy * 1.002f + 1e-5f;
+  hz = hz * 1.002f + 1e-5f;
+  const float4 lo = make_float4(mx - hx, my - hy, mz - hz, 0.0f);
+  const float4 hi = make_float4(mx + hx, my + hy, mz + hz, 0.0f);
+  aabb[2 * i] = lo;
+  aabb[2 * i + 1] = hi;
+  if (bounds_ord) {
+    atomicMin(&bounds_ord[0], f2ord(lo.x));
+    atomicMin(&bounds_ord[1], f2ord(lo.y));
+    atomicMin(&bounds_ord[2], f2ord(lo.z));
+    atomicMax(&bounds_ord[3], f2ord(hi.x));
+    atomicMax(&bounds_ord[4], f2ord(hi.y));
+    atomicMax(&bounds_ord[5], f2ord(hi.z));
+    atomicAdd(ext_sum, (2.0f / 3.0f) * (hx + hy + hz));
+    atomicAdd(n_reg, 1);
+  }
+}
+
+__device__ __forceinline__ bool cell_range(const BakeGrid& G, float4 lo, float4 hi, int c0[3],
+                                           int c1[3]) {
+  const float l[3] = {lo.x, lo.y, lo.z}, h[3] = {hi.x, hi.y, hi.z};
+  if (G.dims[0] <= 0 || G.dims[1] <= 0 || G.dims[2] <= 0) return false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!(l[a] <= h[a])) return false;
+    const float f0 = floorf((l[a] - G.origin[a]) * G.inv_cell[a]);
+    const float f1 = floorf((h[a] - G.origin[a]) * G.inv_cell[a]);
+    c0[a] = (int)fminf(fmaxf(f0, 0.0f), (float)(G.dims[a] - 1));
+    c1[a] = (int)fminf(fmaxf(f1, 0.0f), (float)(G.dims[a] - 1));
+  }
+  return true;
+}
+
+// flags Gaussians whose box leaves the grid (possible after an update)
+__device__ __forceinline__ bool inside_grid(const BakeGrid& G, float4 lo, float4 hi) {
+  return lo.x >= G.origin[0] && lo.y >= G.origin[1] && lo.z >= G.origin[2] &&
+         hi.x <= G.origin[0] + G.dims[0] * G.cell[0] &&
+         hi.y <= G.origin[1] + G.dims[1] * G.cell[1] &&
+         hi.z <= G.origin[2] + G.dims[2] * G.cell[2];
+}
+
+__global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* aabb,
+                                                     int32_t* counts, int32_t* overflow) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= G.G) return;
+  const float4 lo = aabb[2 * i], hi = aabb[2 * i + 1];
+  int c0[3], c1[3];
+  if (!cell_range(G, lo, hi, c0, c1)) return;
+  if (!inside_grid(G, lo, hi)) atomicOr(overflow, 1);
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x)
+        atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
+}
+
+__global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aabb,
+                                                    const int32_t* cell_start, int32_t* cursor,
+                                                    int32_t* entries, int32_t capacity,
+                                                    int32_t* overflow) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= G.G) return;
+  const int32_t ncell = G.dims[0] * G.dims[1] * G.dims[2];
+  if (cell_start[ncell] > capacity) {      // more registrations than the plan holds
+    if (i == 0) atomicOr(overflow, 2);
+    return;
+  }
+  const float4 lo = aabb[2 * i], hi = aabb[2 * i + 1];
+  int c0[3], c1[3];
+  if (!cell_range(G, lo, hi, c0, c1)) return;
+  for (int z = c0[2]; z <= c1[2]; ++z)
+    for (int y = c0[1]; y <= c1[1]; ++y)
+      for (int x = c0[0]; x <= c1[0]; ++x) {
+        const int32_t c = (z * G.dims[1] + y) * G.dims[0] + x;
+        const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
+        entries[slot] = i;
+      }
+}
+
+// ------------------------------------------------------------------------------------------
+// per-texel ray traversal
+// ------------------------------------------------------------------------------------------
+constexpr int kBuf = 16;   // sorted candidate buffer per cell pass
+
+__device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
+  float px = 2.0f * u / (float)R - 1.0f, py = 2.0f * v / (float)R - 1.0f;
+  const float z = 1.0f - fabsf(px) - fabsf(py);
+  if (z < 0.0f) {
+    const float fx = (1.0f - fabsf(py)) * sgn1(px);
+    const float fy = (1.0f - fabsf(px)) * sgn1(py);
+    px = fx;
+    py = fy;
+  }
+  const float il = rsqrtf(px * px + py * py + z * z);
+  return mk3(px * il, py * il, z * il);
+}
+
+__global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
+                                              int32_t R, float* texels, float* depth) {
+  // a wavefront covers an 8x8 tile of one probe's texels
+  const int32_t tiles_x = (R + 7) >> 3;
+  const int32_t tiles = tiles_x * tiles_x;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wave >= (int64_t)P * tiles) return;
+  const int32_t p = (int32_t)(wave / tiles);
+  const int32_t tile = (int32_t)(wave % tiles);
+  const int lane = threadIdx.x & 63;
+  const int32_t ti = (tile % tiles_x) * 8 + (lane & 7);
+  const int32_t tj = (tile / tiles_x) * 8 + (lane >> 3);
+  if (ti >= R || tj >= R) return;
+  const size_t texel = (size_t)p * R * R + (size_t)tj * R + ti;
+
+  if (G.overflow && *G.overflow) {
+    const float nan = __int_as_float(0x7FC00000);
+    reinterpret_cast<float4*>(texels)[texel] = make_float4(nan, nan, nan, nan);
+    if (depth) depth[texel] = nan;
+    return;
+  }
+
+  const v3 o = mk3(probe_pos[3 * p], probe_pos[3 * p + 1], probe_pos[3 * p + 2]);
+  const v3 d = oct_decode_dev(ti + 0.5f, tj + 0.5f, R);
+  const float dd[3] = {d.x, d.y, d.z}, oo[3] = {o.x, o.y, o.z};
+
+  float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, Dp = 0.0f, Wt = 0.0f;
+  const int32_t ncell = G.dims[0] * G.dims[1] * G.dims[2];
+
+  // clip to the grid box
+  float t0 = 0.0f, t1 = FLT_MAX;
+  float inv[3];
+  bool hit = ncell > 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = G.origin[a], hi = G.origin[a] + G.dims[a] * G.cell[a];
+    if (dd[a] != 0.0f) {
+      inv[a] = 1.0f / dd[a];
+      float ta = (lo - oo[a]) * inv[a], tb = (hi - oo[a]) * inv[a];
+      if (ta > tb) { const float x = ta; ta = tb; tb = x; }
+      t0 = fmaxf(t0, ta);
+      t1 = fminf(t1, tb);
+    } else {
+      inv[a] = 0.0f;
+      if (oo[a] < lo || oo[a] > hi) hit = false;
+    }
+  }
+  if (hit && t0 <= t1) {
+    int c[3], step[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float pa = oo[a] + t0 * dd[a];
+      const float f = floorf((pa - G.origin[a]) * G.inv_cell[a]);
+      c[a] = (int)fminf(fmaxf(f, 0.0f), (float)(G.dims[a] - 1));
+      step[a] = dd[a] > 0.0f ? 1 : (dd[a] < 0.0f ? -1 : 0);
+    }
+    float t_lo = -FLT_MAX;                  // the first cell takes every t* before its exit
+    bool done = false;
+    const int max_steps = G.dims[0] + G.dims[1] + G.dims[2] + 3;
+    for (int it = 0; it < max_steps && !done; ++it) {
+      // exit parameter of the current cell and the axis that is crossed
+      float t_exit = FLT_MAX;
+      int axis = -1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (step[a] != 0) {
+          const float b = G.origin[a] + (float)(c[a] + (step[a] > 0 ? 1 : 0)) * G.cell[a];
+          const float ta = (b - oo[a]) * inv[a];
+          if (ta < t_exit) { t_exit = ta; axis = a; }
+        }
+      }
+      bool last = axis < 0;
+      if (!last) {
+        const int nc = c[axis] + step[axis];
+        last = nc < 0 || nc >= G.dims[axis];
+      }
+      const float t_hi = last ? FLT_MAX : t_exit;
+      const int32_t cell = (c[2] * G.dims[1] + c[1]) * G.dims[0] + c[0];
+      const int32_t e0 = min(G.cell_start[cell], G.capacity);
+      const int32_t e1 = min(G.cell_start[cell + 1], G.capacity);
+
+      // candidates of this cell in ascending (t*, index), kBuf at a time
+      uint64_t after = 0;      // keys <= after are done
+      for (int round = 0; e1 > e0 && !done; ++round) {
+        uint64_t key[kBuf];
+        float al[kBuf];
+#pragma unroll
+        for (int s = 0; s < kBuf; ++s) { key[s] = ~0ull; al[s] = 0.0f; }
+        for (int32_t e = e0; e < e1; ++e) {
+          const int32_t gi = G.entries[e];
+          const float4 r0 = G.gdata[4 * gi], r1 = G.gdata[4 * gi + 1], r2 = G.gdata[4 * gi + 2];
+          const float op = G.gdata[4 * gi + 3].w;
+          const v3 om = mk3(o.x - r0.w, o.y - r1.w, o.z - r2.w);
+          const v3 ol = mk3(r0.x * om.x + r0.y * om.y + r0.z * om.z,
+                            r1.x * om.x + r1.y * om.y + r1.z * om.z,
+                            r2.x * om.x + r2.y * om.y + r2.z * om.z);
+          const v3 dl = mk3(r0.x * d.x + r0.y * d.y + r0.z * d.z,
+                            r1.x * d.x + r1.y * d.y + r1.z * d.z,
+                            r2.x * d.x + r2.y * d.y + r2.z * d.z);
+          const float ts = -dot(ol, dl) / dot(dl, dl);
+          if (!(ts > G.t_min && ts >= t_lo && ts < t_hi)) continue;
+          const v3 xl = add(ol, mul(dl, ts));
+          const float a = fminf(G.alpha_max, op * expf(-0.5f * dot(xl, xl)));
+          if (!(a >= G.alpha_min)) continue;
+          uint64_t k = ((uint64_t)(uint32_t)__float_as_int(ts) << 32) | (uint32_t)gi;
+          if (k <= after || k >= key[kBuf - 1]) continue;
+          float av = a;
+#pragma unroll
+          for (int s = 0; s < kBuf; ++s) {      // sorted insertion, largest falls out
+            const bool sw = k < key[s];
+            const uint64_t kk = sw ? key[s] : k;
+            const float aa = sw ? al[s] : av;
+            key[s] = sw ? k : key[s];
+            al[s] = sw ? av : al[s];
+            k = kk;
+            av = aa;
+          }
+        }
+        int used = 0;
+#pragma unroll
+        for (int s = 0; s < kBuf; ++s) {
+          if (key[s] == ~0ull || done) continue;
+          const float a = al[s];
+          const float Tn = T * (1.0f - a);
+          if (Tn < G.T_min) { done = true; continue; }
+          const int32_t gi = (int32_t)(key[s] & 0xFFFFFFFFu);
+          const float4 col = G.gdata[4 * gi + 3];
+          const float ts = __int_as_float((int)(key[s] >> 32));
+          const float wgt = T * a;
+          Cr += wgt * col.x;
+          Cg += wgt * col.y;
+          Cb += wgt * col.z;
+          Dp += wgt * ts;
+          Wt += wgt;
+          T = Tn;
+          ++used;
+        }
+        if (key[kBuf - 1] == ~0ull) break;     // the cell had fewer than kBuf left
+        after = key[kBuf - 1];
+        (void)used;
+      }
+      if (last) break;
+      t_lo = t_exit;
+      c[axis] += step[axis];
+    }
+  }
+  reinterpret_cast<float4*>(texels)[texel] = make_float4(Cr, Cg, Cb, Wt);
+  if (depth) depth[texel] = Wt > 0.0f ? Dp / Wt : 0.0f;
+}
+
+// ------------------------------------------------------------------------------------------
+hipError_t launch_gauss_prep(const sop_gaussians& g, float alpha_min, float4* gdata,
+                             float4* aabb, int32_t* bounds_ord, float* ext_sum, int32_t* n_reg,
+                             hipStream_t s) {
+  if (g.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gauss_prep, dim3((g.count + 255) / 256), dim3(256), 0, s, g, alpha_min,
+                     gdata, aabb, bounds_ord, ext_sum, n_reg);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* counts,
+                              int32_t* overflow, hipStream_t s) {
+  if (G.G == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gauss_count, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb, counts,
+                     overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_t* cell_start,
+                             int32_t* cursor, int32_t* entries, int32_t capacity,
+                             int32_t* overflow, hipStream_t s) {
+  if (G.G == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb,
+                     cell_start, cursor, entries, capacity, overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
+                       float* texels, float* depth, hipStream_t s) {
+  const int64_t tiles = (int64_t)((R + 7) / 8) * ((R + 7) / 8);
+  const int64_t waves = (int64_t)P * tiles;
+  if (waves == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bake, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, G, probe_pos,
+                     P, R, texels, depth);
+  return hipGetLastError();
+}
+
+}  // namespace sopk

@@ -1,0 +1,394 @@
+// shade.hip - deferred shading with surface octahedral probes (ComGS Sec. 3.1.2):
+// Monte Carlo estimate of the rendering equation (Eq. 6-7) over S Hammersley directions,
+// incident light (1 - O) L_env + L_in (Eq. 8), O and L_in interpolated from the K nearest
+// probes (Eq. 9-11), and the adjoint of that estimate.
+//
+// Layout: one wavefront per shading point, lane l takes directions l, l+64, ...; the point's
+// data and its neighbour list are wave-uniform (scalar loads), the octahedral taps of a
+// direction are formed once and reused for all K probes, and the per-point sums are reduced
+// across the wavefront with DPP. The backward pass recomputes every sample instead of
+// storing per-sample fetches.
+#include "sop_device.hpp"
+#include "sop_internal.hpp"
+
+namespace sopk {
+
+constexpr int kWavesPerBlock = 4;
+
+struct PointState {
+  int64_t p;
+  double n64[3], v64[3];
+  v3 n, v;
+  Material M;
+  Frame64 F;
+  double cr, sr;   // per-point rotation of the direction table (1, 0 when per call)
+};
+
+__device__ __forceinline__ bool load_point(const ShadeArgs& a, int64_t wv, PointState& ps) {
+  int64_t p = wv;
+  if (a.order) {
+    const int32_t o = __builtin_amdgcn_readfirstlane(a.order[wv]);
+    if ((uint64_t)o >= (uint64_t)a.n) return false;
+    p = o;
+  }
+  ps.p = p;
+  ps.n = mk3(a.nrm[3 * p], a.nrm[3 * p + 1], a.nrm[3 * p + 2]);
+  ps.n64[0] = ps.n.x;
+  ps.n64[1] = ps.n.y;
+  ps.n64[2] = ps.n.z;
+  if (a.view) {
+    ps.v = mk3(a.view[3 * p], a.view[3 * p + 1], a.view[3 * p + 2]);
+    ps.v64[0] = ps.v.x;
+    ps.v64[1] = ps.v.y;
+    ps.v64[2] = ps.v.z;
+  } else {
+    const int64_t f = p / a.ppf;
+    double d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] = (double)a.cam[3 * f + c] - (double)a.pos[3 * p + c];
+    const double il = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ps.v64[c] = d[c] * il;
+    ps.v = mk3((float)ps.v64[0], (float)ps.v64[1], (float)ps.v64[2]);
+  }
+  double nv = ps.n64[0] * ps.v64[0] + ps.n64[1] * ps.v64[1] + ps.n64[2] * ps.v64[2];
+  const float NoV = (float)(nv < 1e-4 ? 1e-4 : nv);
+  const v3 alb = mk3(a.albedo[3 * p], a.albedo[3 * p + 1], a.albedo[3 * p + 2]);
+  ps.M = make_material(NoV, alb, a.rough[p], a.metal[p]);
+  ps.F = make_frame64(ps.n64[0], ps.n64[1], ps.n64[2]);
+  if (a.per_point) {
+    const uint32_t rho = rotation24(a.seed, true, (uint32_t)p);
+    sincospi((double)rho * 0x1p-23, &ps.sr, &ps.cr);
+  } else {
+    ps.cr = 1.0;
+    ps.sr = 0.0;
+  }
+  return true;
+}
+
+// Neighbour list of a point: KT > 0 keeps K entries in registers (scalar), KT == 0 reads the
+// list inside the loop for a run-time K.
+template <int KT>
+struct Neighbors {
+  int32_t idx[KT];
+  float w[KT];
+  __device__ __forceinline__ void load(const ShadeArgs& a, int64_t p, int32_t) {
+#pragma unroll
+    for (int s = 0; s < KT; ++s) {
+      int32_t id = a.nb_idx[p * KT + s];
+      idx[s] = ((uint32_t)id < (uint32_t)a.P) ? id : -1;   // drop out-of-range entries
+      w[s] = a.nb_w[p * KT + s];
+    }
+  }
+  __device__ __forceinline__ int count(int32_t) const { return KT; }
+  __device__ __forceinline__ int32_t id(int s, const ShadeArgs&, int64_t, int32_t) const {
+    return idx[s];
+  }
+  __device__ __forceinline__ float wt(int s, const ShadeArgs&, int64_t, int32_t) const {
+    return w[s];
+  }
+};
+
+template <>
+struct Neighbors<0> {
+  __device__ __forceinline__ void load(const ShadeArgs&, int64_t, int32_t) {}
+  __device__ __forceinline__ int count(int32_t k) const { return k; }
+  __device__ __forceinline__ int32_t id(int s, const ShadeArgs& a, int64_t p, int32_t k) const {
+    const int32_t v = a.nb_idx[p * k + s];
+    return ((uint32_t)v < (uint32_t)a.P) ? v : -1;
+  }
+  __device__ __forceinline__ float wt(int s, const ShadeArgs& a, int64_t p, int32_t k) const {
+    return a.nb_w[p * k + s];
+  }
+};
+
+// per-sample quantities shared by forward and backward
+struct Sample {
+  double w64[3];
+  v3 w;
+  float ct;
+  EnvTaps et;
+  Taps tt;
+  float Le[3];
+  float Lin[3];
+  float O;
+};
+
+template <int KT, typename TexT>
+__device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState& ps,
+                                            const Neighbors<KT>& nb, int32_t k, int j,
+                                            Sample& s) {
+  const double4 e = a.dir_tab[j];
+  const double da = e.x * ps.cr - e.y * ps.sr;
+  const double db = e.x * ps.sr + e.y * ps.cr;
+  world_dir64(ps.F, da, db, e.z, s.w64);
+  s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+  s.ct = (float)e.z;
+  s.et = env_taps(s.w, a.H, a.W, a.u_scale, a.v_scale);
+  s.Le[0] = s.Le[1] = s.Le[2] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float* e = a.env + 3 * (size_t)s.et.off[t];
+    s.Le[0] += s.et.w[t] * e[0];
+    s.Le[1] += s.et.w[t] * e[1];
+    s.Le[2] += s.et.w[t] * e[2];
+  }
+  s.tt = oct_taps(s.w, a.R, a.halfR);
+  s.Lin[0] = s.Lin[1] = s.Lin[2] = 0.0f;
+  s.O = 0.0f;
+  const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
+  const size_t RR = (size_t)a.R * a.R;
+  const int kn = KT > 0 ? KT : nb.count(k);
+#pragma unroll
+  for (int s2 = 0; s2 < kn; ++s2) {
+    const int32_t id = nb.id(s2, a, ps.p, k);
+    if (id < 0) continue;
+    const float wk = nb.wt(s2, a, ps.p, k);
+    const TexT* T = tex + (size_t)id * RR;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float4 x = load_texel(T, (size_t)s.tt.off[t]);
+      const float c = wk * s.tt.w[t];
+      s.Lin[0] += c * x.x;
+      s.Lin[1] += c * x.y;
+      s.Lin[2] += c * x.z;
+      s.O += c * x.w;
+    }
+  }
+}
+
+template <int KT, typename TexT>
+__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
+  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  if (wv >= a.n) return;
+  const int lane = threadIdx.x & 63;
+  PointState ps;
+  if (!load_point(a, wv, ps)) return;
+  Neighbors<KT> nb;
+  nb.load(a, ps.p, k);
+
+  float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
+  for (int j0 = 0; j0 < a.S; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < a.S) {
+      Sample s;
+      eval_sample<KT, TexT>(a, ps, nb, k, j, s);
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+      const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+        acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li;
+        acc_e[c] += Li * s.ct;
+      }
+    }
+  }
+  float r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = wave_sum(acc[c]) * a.scale;
+  if (lane == 0) {
+    a.rgb[3 * ps.p] = r[0];
+    a.rgb[3 * ps.p + 1] = r[1];
+    a.rgb[3 * ps.p + 2] = r[2];
+  }
+  if (a.irr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = wave_sum(acc_e[c]) * a.scale;
+    if (lane == 0) {
+      a.irr[3 * ps.p] = r[0];
+      a.irr[3 * ps.p + 1] = r[1];
+      a.irr[3 * ps.p + 2] = r[2];
+    }
+  }
+}
+
+// Adjoint. With g the upstream gradient of the point and s = 2 pi / S:
+//   d/da_c  = s sum g_c L_i,c [ (1-m) cos/pi + spec m (1 - x^5) ]
+//   d/dm    = s sum_c g_c L_i,c [ -a_c cos/pi + spec (a_c - 0.04)(1 - x^5) ]
+//   d/dr    = s sum_c g_c L_i,c F_c/(4 NoV) (dD/dalpha G + D dG/dalpha) 2 r
+//   d/dLin_k[t,c] = s g_c fcos_c w_k b_t,   d/dO_k[t] = -s sum_c g_c fcos_c Le_c w_k b_t
+//   d/denv[t',c]  = s g_c fcos_c (1 - O) b'_t'
+// where spec = D G1(NoL) G1(NoV) / (4 NoV) and x = 1 - v.h.
+template <int KT, typename TexT>
+__global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
+  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  if (wv >= a.n) return;
+  const int lane = threadIdx.x & 63;
+  PointState ps;
+  if (!load_point(a, wv, ps)) return;
+  Neighbors<KT> nb;
+  nb.load(a, ps.p, k);
+  const float g[3] = {a.grad[3 * ps.p], a.grad[3 * ps.p + 1], a.grad[3 * ps.p + 2]};
+  const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+  const Material& M = ps.M;
+  const size_t RR = (size_t)a.R * a.R;
+  const int kc = KT > 0 ? KT : nb.count(k);
+
+  float ga[3] = {0.0f, 0.0f, 0.0f}, gr = 0.0f, gm = 0.0f;
+  for (int j0 = 0; j0 < a.S; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < a.S) {
+      Sample s;
+      eval_sample<KT, TexT>(a, ps, nb, k, j, s);
+      const BrdfTerms bt = brdf_terms(M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+      const float om5 = 1.0f - bt.x5;
+      // dD/dalpha = 2 alpha (1 - NoH^2 - alpha^2 NoH^2) / (pi q^3)
+      const float dD = 2.0f * M.alpha * (bt.one_m - M.a2 * bt.NoH2) / (kPi * bt.q * bt.q * bt.q);
+      const float denL = s.ct * M.one_m_k + M.k, denV = M.NoV * M.one_m_k + M.k;
+      const float dG1L = -s.ct * (1.0f - s.ct) / (denL * denL);
+      const float dG1V = -M.NoV * (1.0f - M.NoV) / (denV * denV);
+      const float G = bt.G1L * M.g1v;
+      const float dG = 0.5f * (dG1L * M.g1v + bt.G1L * dG1V);
+      const float i4nv = 1.0f / (4.0f * M.NoV);
+      const float drough = i4nv * (dD * G + bt.D * dG) * 2.0f * M.r;
+      float gl[3], go = 0.0f, ge[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+        const float F0 = 0.04f * (1.0f - M.m) + al[c] * M.m;
+        const float F = F0 + (1.0f - F0) * bt.x5;
+        const float fc = (1.0f - M.m) * al[c] * kInvPi * s.ct + bt.spec * F;
+        const float cm = g[c] * Li;
+        ga[c] += cm * ((1.0f - M.m) * kInvPi * s.ct + bt.spec * M.m * om5);
+        gm += cm * (-al[c] * kInvPi * s.ct + bt.spec * (al[c] - 0.04f) * om5);
+        gr += cm * F * drough;
+        const float gf = g[c] * fc * a.scale;
+        gl[c] = gf;
+        go -= gf * s.Le[c];
+        ge[c] = gf * (1.0f - s.O);
+      }
+      if (a.g_tex) {
+        for (int s2 = 0; s2 < kc; ++s2) {
+          const int32_t id = nb.id(s2, a, ps.p, k);
+          if (id < 0) continue;
+          const float wk = nb.wt(s2, a, ps.p, k);
+          float* GT = a.g_tex + (size_t)id * RR * 4;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float cw = wk * s.tt.w[t];
+            float* dst = GT + (size_t)s.tt.off[t] * 4;
+            unsafeAtomicAdd(dst + 0, cw * gl[0]);
+            unsafeAtomicAdd(dst + 1, cw * gl[1]);
+            unsafeAtomicAdd(dst + 2, cw * gl[2]);
+            unsafeAtomicAdd(dst + 3, cw * go);
+          }
+        }
+      }
+      if (a.g_env) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          float* dst = a.g_env + (size_t)s.et.off[t] * 3;
+          unsafeAtomicAdd(dst + 0, s.et.w[t] * ge[0]);
+          unsafeAtomicAdd(dst + 1, s.et.w[t] * ge[1]);
+          unsafeAtomicAdd(dst + 2, s.et.w[t] * ge[2]);
+        }
+      }
+    }
+  }
+  const float r0 = wave_sum(ga[0]) * a.scale, r1 = wave_sum(ga[1]) * a.scale,
+              r2 = wave_sum(ga[2]) * a.scale;
+  const float rr = wave_sum(gr) * a.scale, rm = wave_sum(gm) * a.scale;
+  if (lane == 0) {
+    if (a.g_albedo) {
+      a.g_albedo[3 * ps.p] = r0;
+      a.g_albedo[3 * ps.p + 1] = r1;
+      a.g_albedo[3 * ps.p + 2] = r2;
+    }
+    if (a.g_rough) a.g_rough[ps.p] = rr;
+    if (a.g_metal) a.g_metal[ps.p] = rm;
+  }
+}
+
+// Eq. 9 at caller-given world directions: one thread per (point, direction).
+template <typename TexT>
+__global__ __launch_bounds__(256) void k_query(ShadeArgs a, int32_t k, const float* dirs,
+                                               int32_t D, float* Lin, float* O) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.n * (int64_t)D) return;
+  const int64_t i = t / D;
+  const v3 w = mk3(dirs[3 * t], dirs[3 * t + 1], dirs[3 * t + 2]);
+  const Taps tt = oct_taps(w, a.R, a.halfR);
+  const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
+  const size_t RR = (size_t)a.R * a.R;
+  float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, oc = 0.0f;
+  for (int s = 0; s < k; ++s) {
+    const int32_t id = a.nb_idx[i * k + s];
+    if ((uint32_t)id >= (uint32_t)a.P) continue;
+    const float wk = a.nb_w[i * k + s];
+    const TexT* T = tex + (size_t)id * RR;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 x = load_texel(T, (size_t)tt.off[q]);
+      const float c = wk * tt.w[q];
+      L0 += c * x.x;
+      L1 += c * x.y;
+      L2 += c * x.z;
+      oc += c * x.w;
+    }
+  }
+  Lin[3 * t] = L0;
+  Lin[3 * t + 1] = L1;
+  Lin[3 * t + 2] = L2;
+  O[t] = oc;
+}
+
+template <int KT>
+static void launch_kt(bool fwd, const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
+                      hipStream_t s) {
+  if (fwd) {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_fwd<KT, uint2>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_fwd<KT, float4>), grid, dim3(256), 0, s, a, k);
+  } else {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_bwd<KT, uint2>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_bwd<KT, float4>), grid, dim3(256), 0, s, a, k);
+  }
+}
+
+static hipError_t dispatch(bool fwd, const ShadeArgs& a, int32_t k, int32_t format,
+                           hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.n + kWavesPerBlock - 1) / kWavesPerBlock));
+  switch (k) {
+    case 4: launch_kt<4>(fwd, a, k, format, grid, s); break;
+    case 8: launch_kt<8>(fwd, a, k, format, grid, s); break;
+    default: launch_kt<0>(fwd, a, k, format, grid, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  return dispatch(true, a, k, format, s);
+}
+hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  return dispatch(false, a, k, format, s);
+}
+
+__global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, double4* tab) {
+  const int32_t j = blockIdx.x * 256 + threadIdx.x;
+  if (j < S) tab[j] = dir_entry(j, S, rho);
+}
+
+hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, double4* tab,
+                            hipStream_t s) {
+  const uint32_t rho = per_point ? 0u : rotation24(seed, false, 0u);
+  hipLaunchKernelGGL(k_dir_table, dim3((S + 255) / 256), dim3(256), 0, s, S, rho, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
+                        int32_t D, float* Lin, float* O, hipStream_t s) {
+  const int64_t total = a.n * (int64_t)D;
+  if (total == 0) return hipSuccess;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL(k_query<uint2>, grid, dim3(256), 0, s, a, k, dirs, D, Lin, O);
+  else
+    hipLaunchKernelGGL(k_query<float4>, grid, dim3(256), 0, s, a, k, dirs, D, Lin, O);
+  return hipGetLastError();
+}
+
+}  // namespace sopk

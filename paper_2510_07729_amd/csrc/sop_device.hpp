@@ -1,0 +1,312 @@
+// sop_device.hpp - device functions of the SOP shading path (gfx950, wave64, FP32).
+//
+// Each function implements one step of ComGS (arXiv 2510.07729) Sec. 3.1.2 in single
+// precision, arranged for the GPU: octahedral taps are formed once per direction and shared
+// by the K probes, the GGX denominator uses |n x h|^2 instead of 1 - (n.h)^2 so that sharp
+// lobes keep their relative precision, and direction sums are reduced across the wavefront
+// with DPP row operations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace sopk {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+
+struct v3 {
+  float x, y, z;
+};
+__device__ __forceinline__ v3 mk3(float x, float y, float z) { return v3{x, y, z}; }
+__device__ __forceinline__ float dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ v3 add(v3 a, v3 b) { return v3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ v3 sub(v3 a, v3 b) { return v3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ v3 mul(v3 a, float s) { return v3{a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ v3 cross(v3 a, v3 b) {
+  return v3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float sgn1(float x) { return x < 0.0f ? -1.0f : 1.0f; }
+
+// ----------------------------------------------------------------------------------------
+// Direction set (Eq. 7: S_r rays from a Hammersley set). Rotation: pcg hash of Jarzynski &
+// Olano (JCGT 2020), 24 bits.
+// ----------------------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+  uint32_t state = v * 747796405u + 2891336453u;
+  uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+  return (word >> 22u) ^ word;
+}
+
+__host__ __device__ __forceinline__ uint32_t rotation24(uint32_t seed, bool per_point,
+                                                       uint32_t i) {
+  return (per_point ? pcg_hash(seed ^ pcg_hash(i)) : pcg_hash(seed)) >> 8;
+}
+
+// Orthonormal frame around the normal (Duff et al., JCGT 2017), sign(0) = +1, in FP64.
+struct Frame64 {
+  double t[3], b[3], n[3];
+};
+__device__ __forceinline__ Frame64 make_frame64(double nx, double ny, double nz) {
+  const double sg = nz < 0.0 ? -1.0 : 1.0;
+  const double a = -1.0 / (sg + nz);
+  const double b = nx * ny * a;
+  Frame64 f;
+  f.t[0] = 1.0 + sg * nx * nx * a;
+  f.t[1] = sg * b;
+  f.t[2] = -sg * nx;
+  f.b[0] = b;
+  f.b[1] = sg + ny * ny * a;
+  f.b[2] = -ny;
+  f.n[0] = nx;
+  f.n[1] = ny;
+  f.n[2] = nz;
+  return f;
+}
+
+// Direction table entry j of S (local frame, FP64): (sin(theta) cos(phi), sin(theta)
+// sin(phi), cos(theta)) with cos(theta) = 1 - (j + 0.5)/S and
+// phi = 2 pi ((bitrev(j) >> 8) + rho) mod 2^24 / 2^24. The sample directions are the same
+// for every point of a call (one rotation per call), so they are formed once per call.
+__device__ __forceinline__ double4 dir_entry(int j, int S, uint32_t rho) {
+  const double ct = (double)(2 * S - 2 * j - 1) / (2.0 * (double)S);
+  const double st = sqrt((1.0 - ct) * (1.0 + ct));
+  const uint32_t u24 = ((__builtin_bitreverse32((uint32_t)j) >> 8) + rho) & 0xFFFFFFu;
+  double sp, cp;
+  sincospi((double)u24 * 0x1p-23, &sp, &cp);
+  return make_double4(st * cp, st * sp, ct, 0.0);
+}
+
+// world direction t*a + b*b + n*ct in FP64
+__device__ __forceinline__ void world_dir64(const Frame64& F, double a, double b, double ct,
+                                            double w[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[c] = fma(F.t[c], a, fma(F.b[c], b, F.n[c] * ct));
+}
+
+// ----------------------------------------------------------------------------------------
+// Octahedral probe texture (Sec. 3.1.2): +z at the centre, lower hemisphere folded to the
+// corners; bilinear taps with mirror wrap across the border.
+// ----------------------------------------------------------------------------------------
+struct Taps {
+  int off[4];    // texel index j*R + i of each tap
+  float w[4];    // bilinear weights
+};
+
+__device__ __forceinline__ void oct_wrap(int i, int j, int R, int& oi, int& oj) {
+  if (i < 0) { i = 0; j = R - 1 - j; }
+  else if (i >= R) { i = R - 1; j = R - 1 - j; }
+  if (j < 0) { j = 0; i = R - 1 - i; }
+  else if (j >= R) { j = R - 1; i = R - 1 - i; }
+  oi = i;
+  oj = j;
+}
+
+__device__ __forceinline__ Taps oct_taps(v3 w, int R, float halfR) {
+  const float s = fabsf(w.x) + fabsf(w.y) + fabsf(w.z);
+  const float inv = 1.0f / s;
+  float px = w.x * inv, py = w.y * inv;
+  if (w.z < 0.0f) {
+    const float fx = (1.0f - fabsf(py)) * sgn1(px);
+    const float fy = (1.0f - fabsf(px)) * sgn1(py);
+    px = fx;
+    py = fy;
+  }
+  // clamp to [-0.5, R-0.5] (also maps NaN there): every tap index stays in [-1, R]
+  const float hi = 2.0f * halfR - 0.5f;
+  const float cu = fminf(fmaxf((px + 1.0f) * halfR - 0.5f, -0.5f), hi);
+  const float cv = fminf(fmaxf((py + 1.0f) * halfR - 0.5f, -0.5f), hi);
+  const float i0f = floorf(cu), j0f = floorf(cv);
+  const float fx = cu - i0f, fy = cv - j0f;
+  const int i0 = (int)i0f, j0 = (int)j0f;
+  Taps t;
+  int ii, jj;
+  oct_wrap(i0, j0, R, ii, jj);
+  t.off[0] = jj * R + ii;
+  oct_wrap(i0 + 1, j0, R, ii, jj);
+  t.off[1] = jj * R + ii;
+  oct_wrap(i0, j0 + 1, R, ii, jj);
+  t.off[2] = jj * R + ii;
+  oct_wrap(i0 + 1, j0 + 1, R, ii, jj);
+  t.off[3] = jj * R + ii;
+  t.w[0] = (1.0f - fx) * (1.0f - fy);
+  t.w[1] = fx * (1.0f - fy);
+  t.w[2] = (1.0f - fx) * fy;
+  t.w[3] = fx * fy;
+  return t;
+}
+
+__device__ __forceinline__ float4 load_texel(const float4* tex, size_t i) { return tex[i]; }
+__device__ __forceinline__ float4 load_texel(const uint2* tex, size_t i) {
+  const uint2 u = tex[i];
+  const __half2 a = *reinterpret_cast<const __half2*>(&u.x);
+  const __half2 b = *reinterpret_cast<const __half2*>(&u.y);
+  const float2 fa = __half22float2(a), fb = __half22float2(b);
+  return make_float4(fa.x, fa.y, fb.x, fb.y);
+}
+
+// ----------------------------------------------------------------------------------------
+// Equirectangular environment map (Eq. 8, L_dir): theta from +z down the rows,
+// phi = atan2(y, x) along the columns, bilinear, columns wrap, rows clamp.
+// ----------------------------------------------------------------------------------------
+struct EnvTaps {
+  int off[4];
+  float w[4];
+};
+
+__device__ __forceinline__ EnvTaps env_taps(v3 w, int H, int W, float u_scale, float v_scale) {
+  const float theta = atan2f(sqrtf(w.x * w.x + w.y * w.y), w.z);
+  const float phi = atan2f(w.y, w.x);
+  // u = (phi + pi) W / (2 pi) = phi * W/(2pi) + W/2, one rounding
+  // clamped to [-0.5, W-0.5] x [-0.5, H-0.5] (NaN included) so every tap is in range
+  const float cu = fminf(fmaxf(fmaf(phi, u_scale, 0.5f * (float)W) - 0.5f, -0.5f),
+                         (float)W - 0.5f);
+  const float cv = fminf(fmaxf(theta * v_scale - 0.5f, -0.5f), (float)H - 0.5f);
+  const float i0f = floorf(cu), j0f = floorf(cv);
+  const float fx = cu - i0f, fy = cv - j0f;
+  int i0 = (int)i0f, j0 = (int)j0f;
+  int i1 = i0 + 1, j1 = j0 + 1;
+  i0 = i0 < 0 ? i0 + W : (i0 >= W ? i0 - W : i0);
+  i1 = i1 < 0 ? i1 + W : (i1 >= W ? i1 - W : i1);
+  j0 = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
+  j1 = j1 < 0 ? 0 : (j1 > H - 1 ? H - 1 : j1);
+  EnvTaps t;
+  t.off[0] = j0 * W + i0;
+  t.off[1] = j0 * W + i1;
+  t.off[2] = j1 * W + i0;
+  t.off[3] = j1 * W + i1;
+  t.w[0] = (1.0f - fx) * (1.0f - fy);
+  t.w[1] = fx * (1.0f - fy);
+  t.w[2] = (1.0f - fx) * fy;
+  t.w[3] = fx * fy;
+  return t;
+}
+
+// ----------------------------------------------------------------------------------------
+// BRDF (Eq. 6, read as Lambert + GGX/Smith-Schlick/Schlick). Returns f*cos(theta) per
+// channel and, when asked, the pieces the adjoint needs.
+// ----------------------------------------------------------------------------------------
+struct Material {
+  v3 a;          // albedo
+  float r, m;    // roughness, metallic
+  float alpha, a2, k;
+  float NoV;     // clamped n.v
+  float one_m_k; // 1 - k
+  float g1v;     // Smith G1(NoV)
+};
+
+// NoV is formed in FP64 by the caller: for grazing views n.v is a small difference of
+// O(1) products.
+__device__ __forceinline__ Material make_material(float NoV_clamped, v3 albedo, float r,
+                                                  float m) {
+  Material M;
+  M.a = albedo;
+  M.r = r;
+  M.m = m;
+  M.alpha = r * r;
+  M.a2 = M.alpha * M.alpha;
+  M.k = 0.5f * M.alpha;
+  M.one_m_k = 1.0f - M.k;
+  M.NoV = NoV_clamped;
+  M.g1v = M.NoV / (M.NoV * M.one_m_k + M.k);
+  return M;
+}
+
+// Half-vector geometry in FP64. A sharp GGX lobe (alpha ~ 1e-3) turns a direction error
+// of 1e-7 into a relative error of ~1e-4 in D, and 1 - (n.h)^2 cancels; both are formed
+// here from FP64 directions, then rounded once to FP32.
+struct HalfGeom {
+  float NoH2;    // (n.h)^2 with h normalised
+  float one_m;   // 1 - (n.h)^2
+  float VoH;     // v.h
+};
+__device__ __forceinline__ HalfGeom half_geom(const double n[3], const double v[3],
+                                              const double w[3]) {
+  const double h0 = w[0] + v[0], h1 = w[1] + v[1], h2 = w[2] + v[2];
+  const double hh = fma(h0, h0, fma(h1, h1, h2 * h2));
+  const double c = fma(n[0], h0, fma(n[1], h1, n[2] * h2));
+  const double vh = fma(v[0], h0, fma(v[1], h1, v[2] * h2));
+  const double NoH2 = c * c / hh;
+  HalfGeom g;
+  g.NoH2 = (float)NoH2;
+  g.one_m = (float)(1.0 - NoH2);
+  g.VoH = (float)vh * rsqrtf((float)hh);
+  return g;
+}
+
+struct BrdfTerms {
+  float D, G1L, q, one_m, NoH2, x5;   // GGX pieces
+  float spec;                         // D * G / (4 NoV) (times cos cancels 1/NoL)
+};
+
+__device__ __forceinline__ BrdfTerms brdf_terms(const Material& M, const HalfGeom& hg,
+                                                float NoL) {
+  BrdfTerms T;
+  T.one_m = hg.one_m;
+  T.NoH2 = hg.NoH2;
+  T.q = fmaf(M.a2, T.NoH2, T.one_m);       // = NoH^2 (alpha^2 - 1) + 1
+  T.D = M.a2 / (kPi * T.q * T.q);
+  T.G1L = NoL / (NoL * M.one_m_k + M.k);
+  const float x = 1.0f - hg.VoH;
+  const float x2 = x * x;
+  T.x5 = x2 * x2 * x;
+  T.spec = T.D * T.G1L * M.g1v / (4.0f * M.NoV);
+  return T;
+}
+
+// f(w) * cos(theta) for channel albedo ac
+__device__ __forceinline__ float fcos(const Material& M, const BrdfTerms& T, float ac,
+                                      float ct) {
+  const float F0 = 0.04f * (1.0f - M.m) + ac * M.m;
+  const float F = F0 + (1.0f - F0) * T.x5;
+  return (1.0f - M.m) * ac * kInvPi * ct + T.spec * F;
+}
+
+// ----------------------------------------------------------------------------------------
+// Wavefront sum with DPP row operations; the total is returned to every lane.
+// All 64 lanes must be active.
+// ----------------------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int src = __float_as_int(v);
+  const int moved = __builtin_amdgcn_update_dpp(0, src, CTRL, ROW_MASK, 0xF, false);
+  return v + __int_as_float(moved);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  v = dpp_add<0xB1>(v);          // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);          // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);         // row_half_mirror
+  v = dpp_add<0x140>(v);         // row_mirror
+  v = dpp_add<0x142, 0xA>(v);    // row_bcast15 into rows 1,3
+  v = dpp_add<0x143, 0xC>(v);    // row_bcast31 into rows 2,3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ int wave_id_uniform() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+// ----------------------------------------------------------------------------------------
+// Neighbour-search lattice: q = clamp(floor((x - lo) * sc), 0, 32767) in FP32.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ int quantize1(float x, float lo, float sc) {
+  const float d = __fsub_rn(x, lo);
+  const float s = __fmul_rn(d, sc);
+  const float f = floorf(s);
+  return f >= 0.0f ? (f > 32767.0f ? 32767 : (int)f) : 0;   // NaN -> 0
+}
+
+__host__ __device__ __forceinline__ uint32_t morton_spread(uint32_t v) {
+  v &= 0x3FF;
+  v = (v | (v << 16)) & 0x030000FF;
+  v = (v | (v << 8)) & 0x0300F00F;
+  v = (v | (v << 4)) & 0x030C30C3;
+  v = (v | (v << 2)) & 0x09249249;
+  return v;
+}
+__host__ __device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return morton_spread(x) | (morton_spread(y) << 1) | (morton_spread(z) << 2);
+}
+
+}  // namespace sopk

@@ -1,0 +1,129 @@
+// sop_internal.hpp - types and kernel launchers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/sop.h"
+
+namespace sopk {
+
+// Device view of a probe grid: the probes' lattice coordinates sorted by the Morton index
+// of their cell, with cell ranges, over a cube of 2^bits cells per axis covering the
+// 2^15 lattice (cell side 2^(15-bits) lattice units).
+struct ProbeGrid {
+  int32_t P;
+  int32_t bits;
+  int32_t shift;          // 15 - bits
+  float lo[3];
+  float sc;               // lattice scale (cells per world unit * 2^shift)
+  const int4* qsorted;    // [P] (qx, qy, qz, probe index), cell-major
+  const int32_t* cell_start;  // [8^bits + 1]
+  const float* pos;       // [P,3] probe positions, original order
+};
+
+// Bump allocator over a caller workspace (256-byte aligned pieces).
+struct Bump {
+  char* base;
+  size_t used, cap;
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + used : nullptr);
+    used += bytes;
+    return p;
+  }
+};
+
+// grid.hip ---------------------------------------------------------------------------------
+size_t scan_tmp_elems(size_t n);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s);
+// out[0..n] = exclusive scan of in[0..n), out[n] = total; tmp holds scan_tmp_elems(n) ints
+hipError_t launch_exclusive_scan(const int32_t* in, int32_t* out, size_t n, int32_t* tmp,
+                                 hipStream_t s);
+hipError_t launch_probe_grid_build(const float* pos, int32_t P, const float lo[3], float sc,
+                                   int32_t bits, int4* qtmp, int32_t* counts,
+                                   int32_t* cell_start, int32_t* cursor, int4* qsorted,
+                                   float* pos_copy, int32_t* scan_tmp, hipStream_t s);
+// points -> processing order grouped by grid cell (counting sort by Morton cell)
+hipError_t launch_point_order(const ProbeGrid& g, const float* pts, int64_t N,
+                              int32_t* point_cell, int32_t* counts, int32_t* offsets,
+                              int32_t* scan_tmp, int32_t* order, hipStream_t s);
+hipError_t launch_knn(const ProbeGrid& g, const float* pts, const float* normals, int64_t N,
+                      const int32_t* order, int32_t k, uint32_t radius_limit, int32_t* idx,
+                      float* w, hipStream_t s);
+
+// shade.hip --------------------------------------------------------------------------------
+struct ShadeArgs {
+  int64_t n;
+  const float* pos;
+  const float* nrm;
+  const float* view;
+  const float* cam;
+  int64_t ppf;
+  const float* albedo;
+  const float* rough;
+  const float* metal;
+  const int32_t* order;
+  const int32_t* nb_idx;
+  const float* nb_w;
+  int32_t P;
+  const void* tex;
+  int32_t R;
+  float halfR;
+  const float* env;
+  int32_t H, W;
+  float u_scale, v_scale;
+  int32_t S;
+  const double4* dir_tab;   // [S] local directions of the call (see dir_entry)
+  float inv2S;
+  float scale;            // 2 pi / S
+  uint32_t seed;
+  int32_t per_point;
+  float* rgb;
+  float* irr;
+  // adjoint
+  const float* grad;
+  float* g_albedo;
+  float* g_rough;
+  float* g_metal;
+  float* g_env;
+  float* g_tex;
+};
+
+// per-call direction table: dir_entry(j, S, rho) with rho of the call (0 when per point)
+hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, double4* tab,
+                            hipStream_t s);
+hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
+                        int32_t D, float* Lin, float* O, hipStream_t s);
+
+// bake.hip ---------------------------------------------------------------------------------
+struct BakeGrid {
+  int32_t G;
+  int32_t dims[3];
+  float origin[3];
+  float cell[3];           // cell size per axis
+  float inv_cell[3];
+  const float4* gdata;     // [G][4]: (M row0 | mu.x) (M row1 | mu.y) (M row2 | mu.z)
+                           //          (color rgb | opacity)
+  const int32_t* cell_start;  // [cells + 1]
+  const int32_t* entries;     // [capacity] Gaussian indices, cell-major
+  int32_t capacity;
+  const int32_t* overflow;    // device flag
+  float t_min, alpha_min, alpha_max, T_min;
+};
+
+hipError_t launch_gauss_prep(const sop_gaussians& g, float alpha_min, float4* gdata,
+                             float4* aabb, int32_t* bounds_ord, float* ext_sum, int32_t* n_reg,
+                             hipStream_t s);
+hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* counts,
+                              int32_t* overflow, hipStream_t s);
+hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_t* cell_start,
+                             int32_t* cursor, int32_t* entries, int32_t capacity,
+                             int32_t* overflow, hipStream_t s);
+hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
+                       float* texels, float* depth, hipStream_t s);
+
+}  // namespace sopk

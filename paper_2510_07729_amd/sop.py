@@ -1,0 +1,334 @@
+"""Python binding of the SOP C ABI (include/sop.h) over torch tensors.
+
+Argument marshalling only: tensors' device pointers and the current HIP stream go to
+libsop.so, which does every step on the GPU. Tensors must be CUDA (HIP) tensors,
+contiguous, float32 (texels may be float16). Names follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, what: str = "tensor") -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{what} has dtype {t.dtype}")
+    return t.data_ptr()
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A 256-byte-aligned byte buffer of at least nbytes (the tensor may be larger)."""
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off: off + max(int(nbytes), 1)]
+
+
+# ------------------------------------------------------------------------------------------
+@dataclasses.dataclass
+class Points:
+    """Shading points: pos/normal/albedo [N,3], rough/metal [N]; view [N,3] or camera
+    positions cam_pos [F,3] with points_per_frame points per frame."""
+    pos: torch.Tensor
+    normal: torch.Tensor
+    albedo: torch.Tensor
+    rough: torch.Tensor
+    metal: torch.Tensor
+    view: Optional[torch.Tensor] = None
+    cam_pos: Optional[torch.Tensor] = None
+    points_per_frame: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def c(self) -> L.sop_points:
+        f = torch.float32
+        s = L.sop_points()
+        s.count = self.n
+        s.pos = _ptr(self.pos, f, "pos")
+        s.normal = _ptr(self.normal, f, "normal")
+        s.view = _ptr(self.view, f, "view")
+        s.cam_pos = _ptr(self.cam_pos, f, "cam_pos")
+        s.points_per_frame = int(self.points_per_frame)
+        s.n_frames = int(self.cam_pos.shape[0]) if self.cam_pos is not None else 0
+        s.albedo = _ptr(self.albedo, f, "albedo")
+        s.roughness = _ptr(self.rough, f, "rough")
+        s.metallic = _ptr(self.metal, f, "metal")
+        return s
+
+
+@dataclasses.dataclass
+class Neighbors:
+    order: torch.Tensor   # [N] int32
+    idx: torch.Tensor     # [N,K] int32
+    w: torch.Tensor       # [N,K] float32
+
+    @property
+    def k(self) -> int:
+        return int(self.idx.shape[1])
+
+    def c(self) -> L.sop_neighbors:
+        s = L.sop_neighbors()
+        s.k = self.k
+        s.order = _ptr(self.order, torch.int32, "order")
+        s.idx = _ptr(self.idx, torch.int32, "idx")
+        s.weight = _ptr(self.w, torch.float32, "w")
+        return s
+
+
+def _maps(tex: torch.Tensor) -> L.sop_probe_maps:
+    m = L.sop_probe_maps()
+    if tex.dim() != 4 or tex.shape[1] != tex.shape[2] or tex.shape[3] != 4:
+        raise ValueError("probe textures must be [P,R,R,4]")
+    m.res = int(tex.shape[1])
+    if tex.dtype == torch.float32:
+        m.format = L.SOP_TEXEL_F32
+    elif tex.dtype == torch.float16:
+        m.format = L.SOP_TEXEL_F16
+    else:
+        raise ValueError("probe textures must be float32 or float16")
+    m.texels = _ptr(tex, None, "texels")
+    return m
+
+
+def _env(env: torch.Tensor) -> L.sop_envmap:
+    if env.dim() != 3 or env.shape[2] != 3:
+        raise ValueError("env must be [H,W,3]")
+    e = L.sop_envmap()
+    e.height, e.width = int(env.shape[0]), int(env.shape[1])
+    e.texels = _ptr(env, torch.float32, "env")
+    return e
+
+
+# ------------------------------------------------------------------------------------------
+class Plan:
+    """Probe grid for the neighbour search (sop_plan_create / sop_plan_destroy)."""
+
+    def __init__(self, probe_pos: torch.Tensor, bounds_lo, bounds_hi):
+        self._lib = L.load()
+        ps = L.sop_probe_set()
+        ps.count = int(probe_pos.shape[0])
+        ps.pos = _ptr(probe_pos, torch.float32, "probe_pos")
+        ps.bounds_lo = (C.c_float * 3)(*[float(x) for x in bounds_lo])
+        ps.bounds_hi = (C.c_float * 3)(*[float(x) for x in bounds_hi])
+        h = C.c_void_p()
+        L.check(self._lib.sop_plan_create(C.byref(ps), _stream(), C.byref(h)), "sop_plan_create")
+        self.handle = h
+        self.n_probes = ps.count
+        self.device = probe_pos.device
+
+    def rebuild(self, probe_pos: torch.Tensor) -> None:
+        L.check(self._lib.sop_plan_rebuild(self.handle, _ptr(probe_pos, torch.float32, "pos"),
+                                           _stream()), "sop_plan_rebuild")
+
+    def info(self):
+        n = C.c_int32()
+        dims = (C.c_int32 * 3)()
+        sc = C.c_float()
+        L.check(self._lib.sop_plan_info(self.handle, C.byref(n), dims, C.byref(sc)),
+                "sop_plan_info")
+        return n.value, tuple(dims), sc.value
+
+    def workspace_size(self, op: int, n: int, k: int, n_dirs: int = 1,
+                       with_neighbors: bool = False) -> int:
+        return int(self._lib.sop_workspace_size(self.handle, op, n, k, n_dirs,
+                                                int(with_neighbors)))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self._lib.sop_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sop_knn(plan: Plan, pts: Points, k: int, radius: float = math.inf) -> Neighbors:
+    dev = pts.pos.device
+    n = pts.n
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+    w = torch.empty((n, k), dtype=torch.float32, device=dev)
+    ws = workspace(plan.workspace_size(L.SOP_OP_KNN, n, k), dev)
+    cp = pts.c()
+    L.check(plan._lib.sop_knn(plan.handle, C.byref(cp), k, radius, order.data_ptr(),
+                              idx.data_ptr(), w.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream()), "sop_knn")
+    return Neighbors(order, idx, w)
+
+
+def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
+              nb: Optional[Neighbors] = None, k: int = 4, radius: float = math.inf):
+    """Eq. 9 at given world directions dirs [N,D,3]: returns (L_in [N,D,3], O [N,D])."""
+    n, D = int(dirs.shape[0]), int(dirs.shape[1])
+    dev = dirs.device
+    Lin = torch.empty((n, D, 3), dtype=torch.float32, device=dev)
+    O = torch.empty((n, D), dtype=torch.float32, device=dev)
+    kk = nb.k if nb is not None else k
+    ws = workspace(plan.workspace_size(L.SOP_OP_QUERY, n, kk, D, nb is not None), dev)
+    m, cp = _maps(texels), pts.c()
+    nbc = nb.c() if nb is not None else None
+    L.check(plan._lib.sop_query(plan.handle, C.byref(m), C.byref(cp),
+                                C.byref(nbc) if nbc is not None else None,
+                                _ptr(dirs, torch.float32, "dirs"), D, k, radius, Lin.data_ptr(),
+                                O.data_ptr(), ws.data_ptr(), ws.numel(), _stream()), "sop_query")
+    return Lin, O
+
+
+def shade_opts(n_dirs: int, k: int, seed: int = 0, radius: float = math.inf,
+               rotate_per_point: bool = False, irradiance: Optional[torch.Tensor] = None):
+    o = L.sop_shade_opts()
+    o.n_dirs, o.k, o.radius, o.seed = int(n_dirs), int(k), float(radius), int(seed) & 0xFFFFFFFF
+    o.rotate_per_point = int(rotate_per_point)
+    o.sampler = L.SOP_SAMPLER_HAMMERSLEY
+    o.out_irradiance = _ptr(irradiance, torch.float32, "irradiance")
+    return o
+
+
+def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, n_dirs: int,
+              k: int = 4, nb: Optional[Neighbors] = None, seed: int = 0,
+              radius: float = math.inf, rotate_per_point: bool = False,
+              irradiance: bool = False, ws: Optional[torch.Tensor] = None,
+              out: Optional[torch.Tensor] = None):
+    """Forward shading: rgb [N,3] (and irradiance [N,3] when asked)."""
+    dev = pts.pos.device
+    n = pts.n
+    rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
+    kk = nb.k if nb is not None else k
+    if ws is None:
+        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, nb is not None), dev)
+    o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr)
+    m, e, cp = _maps(texels), _env(env), pts.c()
+    nbc = nb.c() if nb is not None else None
+    L.check(plan._lib.sop_shade(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+                                C.byref(nbc) if nbc is not None else None, C.byref(o),
+                                _ptr(rgb, torch.float32, "rgb"), ws.data_ptr(), ws.numel(),
+                                _stream()), "sop_shade")
+    return (rgb, irr) if irradiance else rgb
+
+
+def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points,
+                       grad_rgb: torch.Tensor, n_dirs: int, k: int = 4,
+                       nb: Optional[Neighbors] = None, seed: int = 0,
+                       radius: float = math.inf, rotate_per_point: bool = False,
+                       want=("albedo", "rough", "metal", "env", "tex"),
+                       g_env: Optional[torch.Tensor] = None,
+                       g_tex: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None):
+    """Adjoint: dict of gradients. g_env/g_tex accumulate into the given tensors (zeroed
+    new ones otherwise); per-point gradients are fresh tensors."""
+    dev = pts.pos.device
+    n = pts.n
+    out = {}
+    if "albedo" in want:
+        out["albedo"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    if "rough" in want:
+        out["rough"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if "metal" in want:
+        out["metal"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if "env" in want:
+        out["env"] = g_env if g_env is not None else torch.zeros(env.shape, dtype=torch.float32,
+                                                                 device=dev)
+    if "tex" in want:
+        out["tex"] = g_tex if g_tex is not None else torch.zeros(
+            texels.shape, dtype=torch.float32, device=dev)
+    kk = nb.k if nb is not None else k
+    if ws is None:
+        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, n, kk, n_dirs,
+                                           nb is not None), dev)
+    o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point)
+    m, e, cp = _maps(texels), _env(env), pts.c()
+    nbc = nb.c() if nb is not None else None
+    g = grad_rgb.contiguous()
+    L.check(plan._lib.sop_shade_backward(
+        plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+        C.byref(nbc) if nbc is not None else None, C.byref(o), _ptr(g, torch.float32, "grad"),
+        _ptr(out.get("albedo")), _ptr(out.get("rough")), _ptr(out.get("metal")),
+        _ptr(out.get("env")), _ptr(out.get("tex")), ws.data_ptr(), ws.numel(), _stream()),
+        "sop_shade_backward")
+    return out
+
+
+# ------------------------------------------------------------------------------------------
+class BakePlan:
+    """Gaussian grid for sop_bake (sop_bake_plan_create / _update / _destroy)."""
+
+    def __init__(self, mean, scale, rotation, opacity, color, t_min=0.0, alpha_min=1.0 / 255.0,
+                 alpha_max=0.99, T_min=1e-4):
+        self._lib = L.load()
+        self._keep = None
+        g = self._gaussians(mean, scale, rotation, opacity, color)
+        o = L.sop_bake_opts(float(t_min), float(alpha_min), float(alpha_max), float(T_min))
+        h = C.c_void_p()
+        L.check(self._lib.sop_bake_plan_create(C.byref(g), C.byref(o), _stream(), C.byref(h)),
+                "sop_bake_plan_create")
+        self.handle = h
+
+    @staticmethod
+    def _gaussians(mean, scale, rotation, opacity, color) -> L.sop_gaussians:
+        f = torch.float32
+        g = L.sop_gaussians()
+        g.count = int(mean.shape[0])
+        g.mean = _ptr(mean, f, "mean")
+        g.scale = _ptr(scale, f, "scale")
+        g.rotation = _ptr(rotation, f, "rotation")
+        g.opacity = _ptr(opacity, f, "opacity")
+        g.color = _ptr(color, f, "color")
+        return g
+
+    def update(self, mean, scale, rotation, opacity, color) -> None:
+        g = self._gaussians(mean, scale, rotation, opacity, color)
+        L.check(self._lib.sop_bake_plan_update(self.handle, C.byref(g), _stream()),
+                "sop_bake_plan_update")
+
+    def check(self) -> None:
+        L.check(self._lib.sop_bake_plan_check(self.handle, _stream()), "sop_bake_plan_check")
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self._lib.sop_bake_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sop_bake(plan: BakePlan, probe_pos: torch.Tensor, res: int, depth: bool = True,
+             texels: Optional[torch.Tensor] = None, depth_out: Optional[torch.Tensor] = None):
+    """Probe textures [P,res,res,4] (R,G,B,O) and depth [P,res,res] by ray tracing."""
+    P = int(probe_pos.shape[0])
+    dev = probe_pos.device
+    tex = texels if texels is not None else torch.empty((P, res, res, 4), dtype=torch.float32,
+                                                        device=dev)
+    dep = None
+    if depth:
+        dep = depth_out if depth_out is not None else torch.empty((P, res, res),
+                                                                  dtype=torch.float32,
+                                                                  device=dev)
+    L.check(plan._lib.sop_bake(plan.handle, _ptr(probe_pos, torch.float32, "probe_pos"), P,
+                               int(res), _ptr(tex, torch.float32, "texels"), _ptr(dep),
+                               _stream()), "sop_bake")
+    return tex, dep

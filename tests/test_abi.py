@@ -1,0 +1,128 @@
+"""C-ABI checks that need no GPU: every symbol of include/sop.h is exported, the Python
+binding declares exactly those symbols, and argument validation returns its status codes
+before any device work."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2510_07729_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sop.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(sop_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_parses_to_functions():
+    names = declared_functions()
+    for must in ("sop_shade", "sop_shade_backward", "sop_bake", "sop_knn", "sop_query",
+                 "sop_plan_create", "sop_workspace_size"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_exactly_the_header():
+    assert sorted(L.SIGNATURES) == declared_functions()
+
+
+def test_misc_entry_points():
+    lib = L.load()
+    assert lib.sop_version() == 100
+    assert lib.sop_status_string(L.SOP_OK) == b"ok"
+    assert lib.sop_status_string(L.SOP_ERR_WORKSPACE_TOO_SMALL) == b"workspace too small"
+    assert lib.sop_status_string(99) == b"unknown status"
+
+
+def probe_set(count=4, lo=(-1, -1, -1), hi=(1, 1, 1), pos=0x1000):
+    ps = L.sop_probe_set()
+    ps.count = count
+    ps.pos = pos
+    ps.bounds_lo = (C.c_float * 3)(*lo)
+    ps.bounds_hi = (C.c_float * 3)(*hi)
+    return ps
+
+
+@pytest.mark.parametrize("kwargs,msg", [
+    (dict(count=-1), "count"),
+    (dict(pos=0), "pos"),
+    (dict(pos=0x1001), "misaligned"),
+    (dict(lo=(0, 0, 0), hi=(1, 0, 1)), "hi > lo"),
+    (dict(lo=(0, 0, float("nan"))), "finite"),
+])
+def test_plan_create_validation(kwargs, msg):
+    lib = L.load()
+    h = C.c_void_p()
+    st = lib.sop_plan_create(C.byref(probe_set(**kwargs)), None, C.byref(h))
+    assert st == L.SOP_ERR_INVALID_ARGUMENT
+    assert msg in lib.sop_last_error().decode()
+    assert not h.value
+
+
+def test_null_plan_and_null_out_are_rejected():
+    lib = L.load()
+    assert lib.sop_plan_create(C.byref(probe_set()), None, None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_plan_rebuild(None, None, None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_plan_destroy(None) == L.SOP_OK
+    assert lib.sop_bake_plan_destroy(None) == L.SOP_OK
+    assert lib.sop_workspace_size(None, 0, 10, 4, 64, 0) == 0
+    pts = L.sop_points()
+    assert lib.sop_knn(None, C.byref(pts), 4, math.inf, None, None, None, None, 0,
+                       None) == L.SOP_ERR_INVALID_ARGUMENT
+    o = L.sop_shade_opts()
+    assert lib.sop_shade(None, None, None, None, None, C.byref(o), None, None, 0,
+                         None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_shade_backward(None, None, None, None, None, C.byref(o), None, None, None,
+                                  None, None, None, None, 0, None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_bake(None, None, 0, 16, None, None, None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_bake_plan_check(None, None) == L.SOP_ERR_INVALID_ARGUMENT
+
+
+def test_bake_plan_validation():
+    lib = L.load()
+    g = L.sop_gaussians()
+    g.count = 10
+    h = C.c_void_p()
+    assert lib.sop_bake_plan_create(C.byref(g), None, None, C.byref(h)) == \
+        L.SOP_ERR_INVALID_ARGUMENT
+    assert "Gaussian" in lib.sop_last_error().decode()
+    g.count = -3
+    assert lib.sop_bake_plan_create(C.byref(g), None, None, C.byref(h)) == \
+        L.SOP_ERR_INVALID_ARGUMENT
+    g.count = 1
+    for p in ("mean", "scale", "rotation", "opacity", "color"):
+        setattr(g, p, 0x1000)
+    o = L.sop_bake_opts(0.0, 0.5, 0.4, 1e-4)     # alpha_max < alpha_min
+    assert lib.sop_bake_plan_create(C.byref(g), C.byref(o), None, C.byref(h)) == \
+        L.SOP_ERR_INVALID_ARGUMENT
+    assert "bake options" in lib.sop_last_error().decode()
+
+
+def test_errors_are_thread_local():
+    import threading
+    lib = L.load()
+    h = C.c_void_p()
+    lib.sop_plan_create(C.byref(probe_set(count=-1)), None, C.byref(h))
+    other = {}
+
+    def worker():
+        lib.sop_plan_create(C.byref(probe_set(pos=0)), None, C.byref(h))
+        other["msg"] = lib.sop_last_error().decode()
+
+    t = threading.Thread(target=worker)
+    t.start()
+    t.join()
+    assert "count" in lib.sop_last_error().decode()
+    assert "pos" in other["msg"]

@@ -1,0 +1,116 @@
+"""GPU parity of the bake (probe textures by ray tracing 3D Gaussians) against the
+oracle's brute-force trace; rays whose float32 decisions sit on a cut are excluded."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_07729_amd import scenes
+from tests.gpu_util import TOL, dev, log, parity_err, report
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def gpu_bake(gs, probe_pos, res, **opts):
+    from paper_2510_07729_amd import sop
+    plan = sop.BakePlan(dev(gs.mean), dev(gs.scale), dev(gs.rotation), dev(gs.opacity),
+                        dev(gs.color), **opts)
+    tex, dep = sop.sop_bake(plan, dev(probe_pos), res)
+    return plan, tex.cpu().numpy(), dep.cpu().numpy()
+
+
+def compare(gs, probe_pos, res, tex, dep, rays_p, rays_t, label):
+    ref, amb = oracle.bake_rays(gs, probe_pos.astype(np.float64), res, rays_p, rays_t)
+    keep = ~amb
+    log(f"{label}: {amb.sum()} of {len(amb)} rays ambiguous (excluded)")
+    flat = tex.reshape(-1, res * res, 4)[rays_p, rays_t]
+    d = dep.reshape(-1, res * res)[rays_p, rays_t]
+    e1 = report(f"{label} rgbo", parity_err(flat[keep], ref[keep, :4]))
+    e2 = report(f"{label} depth", parity_err(d[keep], ref[keep, 4]))
+    assert keep.mean() > 0.9
+    return max(e1, e2)
+
+
+def test_bake_small_scene_all_rays(torch_gpu):
+    log("bake: 300 Gaussians, 6 probes, 8x8")
+    rng = np.random.default_rng(1)
+    gs = scenes.random_gaussians(rng, 300)
+    probes = rng.uniform(-0.5, 0.5, (6, 3)).astype(np.float32)
+    _, tex, dep = gpu_bake(gs, probes, 8)
+    rp = np.repeat(np.arange(6), 64).astype(np.int32)
+    rt = np.tile(np.arange(64), 6).astype(np.int32)
+    assert compare(gs, probes, 8, tex, dep, rp, rt, "small") <= TOL
+
+
+def test_bake_object_scene_sampled(torch_gpu):
+    log("bake: object scene 100k Gaussians, 4096 probes at 32x32 (4.19M rays); 400 on oracle")
+    gs = scenes.object_gaussians()
+    probes = scenes.object_probes()
+    _, tex, dep = gpu_bake(gs, probes, 32)
+    assert np.all(np.isfinite(tex))
+    rng = np.random.default_rng(2)
+    rp = rng.integers(0, probes.shape[0], 400).astype(np.int32)
+    rt = rng.integers(0, 32 * 32, 400).astype(np.int32)
+    assert compare(gs, probes, 32, tex, dep, rp, rt, "object") <= TOL
+
+
+def test_bake_single_gaussian_closed_form(torch_gpu):
+    log("bake: one Gaussian on the axis of a texel")
+    R = 4
+    d = oracle.oct_decode(2.5, 2.5, R)
+    gs = scenes.GaussianScene(np.array([0.7 * d], np.float32),
+                              np.array([[0.05, 0.05, 0.05]], np.float32),
+                              np.array([[1, 0, 0, 0]], np.float32),
+                              np.array([0.6], np.float32), np.array([[0.2, 0.4, 0.8]], np.float32))
+    _, tex, dep = gpu_bake(gs, np.zeros((1, 3), np.float32), R)
+    t = tex[0, 2, 2]
+    assert abs(t[3] - 0.6) < 1e-5 and abs(dep[0, 2, 2] - 0.7) < 1e-5
+    assert np.allclose(t[:3], 0.6 * np.array([0.2, 0.4, 0.8]), rtol=1e-5)
+
+
+def test_bake_empty_and_transparent(torch_gpu):
+    log("bake: no Gaussians; Gaussians below alpha_min")
+    rng = np.random.default_rng(3)
+    gs = scenes.random_gaussians(rng, 0)
+    _, tex, dep = gpu_bake(gs, np.zeros((2, 3), np.float32), 8)
+    assert np.all(tex == 0) and np.all(dep == 0)
+    gs = scenes.random_gaussians(rng, 50)
+    gs.opacity[:] = 0.001
+    _, tex, dep = gpu_bake(gs, np.zeros((2, 3), np.float32), 8)
+    assert np.all(tex == 0)
+
+
+def test_bake_plan_update_and_overflow(torch_gpu):
+    log("bake: plan update equals a fresh plan; escaping Gaussians are reported")
+    import torch
+    from paper_2510_07729_amd import sop
+    rng = np.random.default_rng(4)
+    gs = scenes.random_gaussians(rng, 400)
+    probes = rng.uniform(-0.4, 0.4, (5, 3)).astype(np.float32)
+    plan, _, _ = gpu_bake(gs, probes, 8)
+    moved = scenes.GaussianScene(gs.mean * np.float32(0.98), gs.scale, gs.rotation, gs.opacity,
+                                 gs.color)
+    plan.update(dev(moved.mean), dev(moved.scale), dev(moved.rotation), dev(moved.opacity),
+                dev(moved.color))
+    plan.check()
+    t1, _ = sop.sop_bake(plan, dev(probes), 8)
+    _, t2, _ = gpu_bake(moved, probes, 8)
+    rp = np.repeat(np.arange(5), 64).astype(np.int32)
+    rt = np.tile(np.arange(64), 5).astype(np.int32)
+    ref, amb = oracle.bake_rays(moved, probes.astype(np.float64), 8, rp, rt)
+    flat = t1.cpu().numpy().reshape(-1, 64, 4)[rp, rt]
+    assert report("updated plan", parity_err(flat[~amb], ref[~amb, :4])) <= TOL
+    far = scenes.GaussianScene(gs.mean * np.float32(3.0), gs.scale, gs.rotation, gs.opacity,
+                               gs.color)
+    plan.update(dev(far.mean), dev(far.scale), dev(far.rotation), dev(far.opacity),
+                dev(far.color))
+    with pytest.raises(sop.L.SopError):
+        plan.check()
+    t3, _ = sop.sop_bake(plan, dev(probes), 8)
+    assert torch.isnan(t3).all()

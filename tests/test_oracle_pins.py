@@ -596,3 +596,17 @@ def test_bake_alpha_clamp_cutoff_and_stop():
                        [[1, 1, 1]] * 5)
     out, amb = oracle.bake_rays(gs, np.zeros((1, 3)), R_BAKE, [0], [Z_TEXEL])
     assert out[0, 3] == pytest.approx(1 - 1.25e-4, rel=1e-9) and not amb[0]
+
+
+def test_adjoint_summation_scale():
+    # the m_* outputs hold sum |term|: never below |gradient|, and equal to it when no term
+    # can be negative (albedo gradient with a non-negative upstream gradient and metallic 0)
+    sc, idx, w = small_diff_scene()
+    g = np.abs(np.random.default_rng(23).standard_normal((sc.n, 3)))
+    ad = oracle.shade_backward(sc, idx, w, g, metal=np.zeros(sc.n), mass=True)
+    for k in ("albedo", "rough", "metal", "tex", "env"):
+        assert np.all(ad["m_" + k] >= np.abs(ad["g_" + k]) * (1 - 1e-12))
+    assert np.allclose(ad["m_albedo"], ad["g_albedo"], rtol=1e-12)
+    ad2 = oracle.shade_backward(sc, idx, w, g, metal=np.zeros(sc.n))
+    assert np.array_equal(ad2["g_tex"], ad["g_tex"]) or np.allclose(ad2["g_tex"], ad["g_tex"],
+                                                                       rtol=1e-12, atol=1e-15)
