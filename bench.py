@@ -102,8 +102,9 @@ def main() -> int:
 
     bake_plan = sop.BakePlan(g_mean, g_scale, g_rot, g_op, g_col)
     plan = sop.Plan(probes, sc.bounds_lo, sc.bounds_hi)
-    ws_f = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE, N, K, S, True), dev)
-    ws_b = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE_BACKWARD, N, K, S, True), dev)
+    ws_f = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE, N, K, S, env.shape[:2], True), dev)
+    ws_b = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE_BACKWARD, N, K, S, env.shape[:2],
+                                             True), dev)
 
     names = ["bake", "probe_grid", "knn", "shade_fwd", "shade_bwd"]
     ev = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

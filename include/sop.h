@@ -227,12 +227,14 @@ typedef enum sop_op {
   SOP_OP_SHADE_BACKWARD = 3
 } sop_op;
 
-/* Workspace bytes that `op` needs for n_points points with k neighbours and n_dirs
- * directions on `plan`, assuming the neighbour search runs inside the call (nb == NULL);
- * with_neighbors != 0 gives the smaller figure for calls that receive nb. Returns 0 on an
- * invalid argument. */
+/* Workspace bytes that `op` needs for n_points points with k neighbours, n_dirs directions
+ * and an environment map of env_height x env_width texels (shading ops keep per-call
+ * direction and environment reference tables there) on `plan`, assuming the neighbour
+ * search runs inside the call (nb == NULL); with_neighbors != 0 gives the smaller figure
+ * for calls that receive nb. Returns 0 on an invalid argument. */
 size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points, int32_t k,
-                          int32_t n_dirs, int32_t with_neighbors);
+                          int32_t n_dirs, int32_t env_height, int32_t env_width,
+                          int32_t with_neighbors);
 
 /* ----------------------------------------------------------------------------------------
  * Bake: probe textures by ray tracing through 3D Gaussians (Sec. 3.1.2, the SOP texture
@@ -260,6 +262,8 @@ typedef struct sop_bake_opts {
   float alpha_min;               /* default 1/255                                         */
   float alpha_max;               /* default 0.99                                          */
   float T_min;                   /* default 1e-4                                          */
+  float cell_scale;              /* grid cell side relative to the mean cut-off box of the
+                                    Gaussians; 0 selects the library default (0.35)       */
 } sop_bake_opts;
 
 typedef struct sop_bake_plan sop_bake_plan;   /* Gaussian grid (opaque)                   */

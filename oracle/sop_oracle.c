@@ -500,10 +500,11 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
         ma[c] += fabs(ta); mm += fabs(tm); mr += fabs(tr);
       }
       /* texture adjoints */
-      double gl[3], go = 0.0, ge[3];
+      double gl[3], go = 0.0, go_mass = 0.0, ge[3];
       for (int c = 0; c < 3; ++c) {
         gl[c] = g[c] * scale * f[c] * ct;
         go -= g[c] * scale * f[c] * ct * Lenv[c];
+        go_mass += fabs(g[c] * scale * f[c] * ct * Lenv[c]);
         ge[c] = g[c] * scale * f[c] * ct * (1.0 - O);
       }
       if (g_tex) {
@@ -530,7 +531,7 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
             G_T[(size_t)tap[t] * 4 + 3] += cw * go;
             if (M_T) {
 #pragma omp atomic
-              M_T[(size_t)tap[t] * 4 + 3] += fabs(cw * go);
+              M_T[(size_t)tap[t] * 4 + 3] += fabs(cw) * go_mass;
             }
           }
         }
@@ -568,9 +569,10 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
  * front to back in ascending (t*, index) with the transmittance of Eq. 1; compositing
  * stops before a Gaussian that would take T (1 - alpha) below T_min.
  * A ray is flagged ambiguous when a decision lies within a float32 margin of its cut:
- * alpha within 1e-3 (relative) of alpha_min, t* within 1e-5 of t_min, T (1 - alpha)
- * within 1e-2 (relative) of T_min, or two consecutive composited t* closer than
- * 1e-6 max(1, t*) (about ten times the float32 rounding of t*).
+ * alpha within 2e-5 (relative) of alpha_min, t* within 1e-5 of t_min, T (1 - alpha)
+ * within 1e-3 (relative) of T_min (each about ten times the float32 rounding of that
+ * quantity), or two consecutive composited t* closer than 2.5e-7 t* (twice the float32
+ * spacing at t*: a GPU that sorts by float32 keys can order them by index instead).
  * ----------------------------------------------------------------------------------*/
 static void quat_to_rot(const double q_in[4], double Rm[3][3]) {
   double q[4] = {q_in[0], q_in[1], q_in[2], q_in[3]};
@@ -633,9 +635,13 @@ static int trace_ray(int G, const double* mean, const double* SI, const double* 
     double m2 = dot3(x, Sx);
     double al = opacity[g] * exp(-0.5 * m2);
     if (al > alpha_max) al = alpha_max;
-    int near_alpha = fabs(al - alpha_min) <= 1e-3 * alpha_min;
+    /* acceptance is (t > t_min) and (alpha >= alpha_min); it can flip under float32
+       rounding when one condition is near its cut and the other holds (or is near too) */
+    int near_alpha = fabs(al - alpha_min) <= 2e-5 * alpha_min;
     int near_t = fabs(t - t_min) <= 1e-5;
-    if ((near_alpha || near_t) && t < first_near) first_near = t;
+    int flip = (near_t && al >= alpha_min * (1.0 - 2e-5)) ||
+               (near_alpha && t > t_min - 1e-5);
+    if (flip && t < first_near) first_near = t;
     if (t <= t_min || al < alpha_min) continue;
     hits[nh].t = t; hits[nh].idx = g; hits[nh].alpha = al;
     ++nh;
@@ -646,9 +652,9 @@ static int trace_ray(int G, const double* mean, const double* SI, const double* 
   for (int s = 0; s < nh; ++s) {
     double al = hits[s].alpha;
     double Tn = T * (1.0 - al);
-    if (fabs(Tn - T_min) <= 1e-2 * T_min) amb = 1;
+    if (fabs(Tn - T_min) <= 1e-3 * T_min) amb = 1;
     if (Tn < T_min) { t_stop = hits[s].t; break; }
-    if (s > 0 && hits[s].t - hits[s - 1].t < 1e-6 * fmax(1.0, hits[s].t)) amb = 1;
+    if (s > 0 && hits[s].t - hits[s - 1].t < 2.5e-7 * hits[s].t) amb = 1;
     int g = hits[s].idx;
     for (int c = 0; c < 3; ++c) C[c] += T * al * color[3 * g + c];
     Dp += T * al * hits[s].t;

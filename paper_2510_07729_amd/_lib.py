@@ -61,7 +61,8 @@ class sop_gaussians(C.Structure):
 
 
 class sop_bake_opts(C.Structure):
-    _fields_ = [("t_min", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32), ("T_min", c_f32)]
+    _fields_ = [("t_min", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32), ("T_min", c_f32),
+                ("cell_scale", c_f32)]
 
 
 P = C.POINTER
@@ -81,7 +82,7 @@ SIGNATURES = {
     "sop_shade_backward": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
                                    P(sop_neighbors), P(sop_shade_opts), c_vp, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
-    "sop_workspace_size": (C.c_size_t, [c_vp, c_i32, c_i64, c_i32, c_i32, c_i32]),
+    "sop_workspace_size": (C.c_size_t, [c_vp, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32]),
     "sop_bake_plan_create": (c_i32, [P(sop_gaussians), P(sop_bake_opts), c_vp, P(c_vp)]),
     "sop_bake_plan_update": (c_i32, [c_vp, P(sop_gaussians), c_vp]),
     "sop_bake_plan_check": (c_i32, [c_vp, c_vp]),

@@ -225,14 +225,18 @@ NbScratch carve_nb(Bump& b, int64_t N, int32_t k) {
 
 // Workspace layout: [direction table (shade ops)] [order, idx, w] [search scratch]
 size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool with_nb,
-                 int32_t n_dirs) {
+                 int32_t n_dirs, int32_t env_h = 0, int32_t env_w = 0) {
   Bump b{nullptr, 0, 0};
   if (op == SOP_OP_KNN) {
     (void)b.take<int32_t>((size_t)N);   // order when the caller passes none
     carve_knn(b, plan, N);
     return b.used;
   }
-  if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD) (void)b.take<double4>((size_t)n_dirs);
+  if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD) {
+    (void)b.take<double4>((size_t)n_dirs);
+    (void)b.take<double2>((size_t)env_w + 2);
+    (void)b.take<double2>((size_t)env_h + 2);
+  }
   if (!with_nb) {
     carve_nb(b, N, k);
     carve_knn(b, plan, N);
@@ -321,11 +325,13 @@ hipError_t run_knn(const sop_plan* plan, const sop_points* pts, int32_t k, float
 }  // namespace
 
 extern "C" size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points,
-                                     int32_t k, int32_t n_dirs, int32_t with_neighbors) {
-  (void)n_dirs;
+                                     int32_t k, int32_t n_dirs, int32_t env_height,
+                                     int32_t env_width, int32_t with_neighbors) {
   if (!plan || n_points < 0 || k < 1 || k > SOP_MAX_K) return 0;
   if (op < SOP_OP_KNN || op > SOP_OP_SHADE_BACKWARD) return 0;
-  size_t need = ws_needed(plan, op, n_points, k, with_neighbors != 0, n_dirs > 0 ? n_dirs : 1);
+  if (env_height < 0 || env_width < 0) return 0;
+  size_t need = ws_needed(plan, op, n_points, k, with_neighbors != 0, n_dirs > 0 ? n_dirs : 1,
+                          env_height, env_width);
   return need > 0 ? need : 256;
 }
 
@@ -477,8 +483,13 @@ void set_dirs(sopk::ShadeArgs& a, const sop_envmap* env, const sop_shade_opts* o
 // the call's direction table, first piece of the workspace
 sop_status setup_dirs(sopk::ShadeArgs& a, Bump& b, const sop_shade_opts* o, hipStream_t s) {
   double4* tab = b.take<double4>((size_t)o->n_dirs);
+  double2* col = b.take<double2>((size_t)a.W + 2);
+  double2* row = b.take<double2>((size_t)a.H + 2);
   a.dir_tab = tab;
-  SOP_HIP(sopk::launch_dir_table(o->n_dirs, o->seed, o->rotate_per_point ? 1 : 0, tab, s),
+  a.col_ref = col;
+  a.row_ref = row;
+  SOP_HIP(sopk::launch_dir_table(o->n_dirs, o->seed, o->rotate_per_point ? 1 : 0, a.H, a.W, tab,
+                                 col, row, s),
           "direction table");
   return SOP_OK;
 }
@@ -494,7 +505,8 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   if (pts->count > 0 && (!rgb || !aligned(rgb, 4)))
     return fail(SOP_ERR_INVALID_ARGUMENT, "rgb is NULL or misaligned");
   const int32_t k = nb ? nb->k : opts->k;
-  const size_t need = ws_needed(plan, SOP_OP_SHADE, pts->count, k, nb != nullptr, opts->n_dirs);
+  const size_t need = ws_needed(plan, SOP_OP_SHADE, pts->count, k, nb != nullptr, opts->n_dirs,
+                                env->height, env->width);
   if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
   if (pts->count == 0) return SOP_OK;
   const hipStream_t s = (hipStream_t)stream;
@@ -527,8 +539,8 @@ extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_m
   for (const void* p : outs)
     if (p && !aligned(p, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "a gradient is misaligned");
   const int32_t k = nb ? nb->k : opts->k;
-  const size_t need =
-      ws_needed(plan, SOP_OP_SHADE_BACKWARD, pts->count, k, nb != nullptr, opts->n_dirs);
+  const size_t need = ws_needed(plan, SOP_OP_SHADE_BACKWARD, pts->count, k, nb != nullptr,
+                                opts->n_dirs, env->height, env->width);
   if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
   if (pts->count == 0) return SOP_OK;
   const hipStream_t s = (hipStream_t)stream;
@@ -603,6 +615,7 @@ sop_bake_opts resolve_bake_opts(const sop_bake_opts* o) {
   r.alpha_min = 1.0f / 255.0f;
   r.alpha_max = 0.99f;
   r.T_min = 1e-4f;
+  r.cell_scale = 0.0f;
   if (o) r = *o;
   return r;
 }
@@ -625,7 +638,7 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   if (st != SOP_OK) return st;
   const sop_bake_opts o = resolve_bake_opts(opts);
   if (!(o.alpha_min > 0.0f) || !(o.alpha_max >= o.alpha_min) || !(o.alpha_max < 1.0f) ||
-      !(o.T_min > 0.0f) || !std::isfinite(o.t_min))
+      !(o.T_min > 0.0f) || !std::isfinite(o.t_min) || !(o.cell_scale >= 0.0f))
     return fail(SOP_ERR_INVALID_ARGUMENT, "bake options out of range");
   const hipStream_t s = (hipStream_t)stream;
   sop_bake_plan* pl = new (std::nothrow) sop_bake_plan();
@@ -637,7 +650,7 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   auto alloc = [&](void** p, size_t bytes) {
     if (e == hipSuccess) e = hipMalloc(p, bytes);
   };
-  alloc((void**)&pl->gdata, G1 * 4 * sizeof(float4));
+  alloc((void**)&pl->gdata, G1 * 5 * sizeof(float4));
   alloc((void**)&pl->aabb, G1 * 2 * sizeof(float4));
   alloc((void**)&pl->misc, 16 * sizeof(int32_t));
   auto bail = [&](sop_status code, const std::string& msg) {
@@ -672,7 +685,8 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
       lo[a] -= pad;
       hi[a] += pad;
     }
-    double h = (double)ext_sum / n_reg;
+    const double cs = o.cell_scale > 0.0f ? (double)o.cell_scale : 0.35;
+    double h = cs * (double)ext_sum / n_reg;
     if (!(h > 0)) h = 1.0;
     for (;;) {
       size_t cells = 1;

@@ -16,6 +16,8 @@
 
 namespace sopk {
 
+constexpr int kGRows = 5;   // float4 rows per Gaussian record
+
 __device__ __forceinline__ int f2ord(float f) {
   const int b = __float_as_int(f);
   return b >= 0 ? b : b ^ 0x7FFFFFFF;
@@ -46,10 +48,12 @@ __global__ __launch_bounds__(256) void k_gauss_prep(sop_gaussians g, float alpha
   const float mx = g.mean[3 * i], my = g.mean[3 * i + 1], mz = g.mean[3 * i + 2];
   const float op = g.opacity[i];
   // M = S^-1 R^T: row k is axis k divided by s_k
-  gdata[4 * i + 0] = make_float4(R00 * i0, R10 * i0, R20 * i0, mx);
-  gdata[4 * i + 1] = make_float4(R01 * i1, R11 * i1, R21 * i1, my);
-  gdata[4 * i + 2] = make_float4(R02 * i2, R12 * i2, R22 * i2, mz);
-  gdata[4 * i + 3] = make_float4(g.color[3 * i], g.color[3 * i + 1], g.color[3 * i + 2], op);
+  float4* gd = gdata + (size_t)kGRows * i;
+  gd[0] = make_float4(R00 * i0, R10 * i0, R20 * i0, mx);
+  gd[1] = make_float4(R01 * i1, R11 * i1, R21 * i1, my);
+  gd[2] = make_float4(R02 * i2, R12 * i2, R22 * i2, mz);
+  gd[3] = make_float4(g.color[3 * i], g.color[3 * i + 1], g.color[3 * i + 2], op);
+  gd[4] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // cut-off: alpha >= alpha_min needs m^2 <= 2 ln(opacity / alpha_min)
   const float m2max = op > alpha_min ? 2.0f * logf(op / alpha_min) : -1.0f;
   if (!(m2max >= 0.0f)) {
@@ -58,6 +62,9 @@ __global__ __launch_bounds__(256) void k_gauss_prep(sop_gaussians g, float alpha
     return;
   }
   const float mm = sqrtf(m2max);
+  // bounding sphere of the cut-off ellipsoid, padded like the box below
+  const float rb = (mm * fmaxf(s0, fmaxf(s1, s2))) * 1.002f + 1e-5f;
+  gd[4] = make_float4(rb * rb, rb, 0.0f, 0.0f);
   float hx = mm * sqrtf(R00 * R00 * s0 * s0 + R01 * R01 * s1 * s1 + R02 * R02 * s2 * s2);
   float hy = mm * sqrtf(R10 * R10 * s0 * s0 + R11 * R11 * s1 * s1 + R12 * R12 * s2 * s2);
   float hz = mm * sqrtf(R20 * R20 * s0 * s0 + R21 * R21 * s1 * s1 + R22 * R22 * s2 * s2);
@@ -144,7 +151,7 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
 // ------------------------------------------------------------------------------------------
 // per-texel ray traversal
 // ------------------------------------------------------------------------------------------
-constexpr int kBuf = 16;   // sorted candidate buffer per cell pass
+constexpr int kBuf = 32;   // sorted candidate buffer per cell pass
 
 __device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
   float px = 2.0f * u / (float)R - 1.0f, py = 2.0f * v / (float)R - 1.0f;
@@ -182,7 +189,25 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
   }
 
   const v3 o = mk3(probe_pos[3 * p], probe_pos[3 * p + 1], probe_pos[3 * p + 2]);
-  const v3 d = oct_decode_dev(ti + 0.5f, tj + 0.5f, R);
+  // ray direction in FP64 (the candidate test below runs in FP64: a Gaussian of scale 0.01
+  // one unit away turns a 1e-7 direction error into 1e-5 in its Mahalanobis distance);
+  // the grid walk uses its FP32 rounding
+  double d64[3];
+  {
+    double px = 2.0 * (ti + 0.5) / (double)R - 1.0, py = 2.0 * (tj + 0.5) / (double)R - 1.0;
+    const double z = 1.0 - fabs(px) - fabs(py);
+    if (z < 0.0) {
+      const double fx = (1.0 - fabs(py)) * (px < 0.0 ? -1.0 : 1.0);
+      const double fy = (1.0 - fabs(px)) * (py < 0.0 ? -1.0 : 1.0);
+      px = fx;
+      py = fy;
+    }
+    const double il = 1.0 / sqrt(px * px + py * py + z * z);
+    d64[0] = px * il;
+    d64[1] = py * il;
+    d64[2] = z * il;
+  }
+  const v3 d = mk3((float)d64[0], (float)d64[1], (float)d64[2]);
   const float dd[3] = {d.x, d.y, d.z}, oo[3] = {o.x, o.y, o.z};
 
   float T = 1.0f, Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, Dp = 0.0f, Wt = 0.0f;
@@ -249,20 +274,35 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
         for (int s = 0; s < kBuf; ++s) { key[s] = ~0ull; al[s] = 0.0f; }
         for (int32_t e = e0; e < e1; ++e) {
           const int32_t gi = G.entries[e];
-          const float4 r0 = G.gdata[4 * gi], r1 = G.gdata[4 * gi + 1], r2 = G.gdata[4 * gi + 2];
-          const float op = G.gdata[4 * gi + 3].w;
+          const float4* gd = G.gdata + (size_t)kGRows * gi;
+          const float4 r0 = gd[0], r1 = gd[1], r2 = gd[2];
           const v3 om = mk3(o.x - r0.w, o.y - r1.w, o.z - r2.w);
-          const v3 ol = mk3(r0.x * om.x + r0.y * om.y + r0.z * om.z,
-                            r1.x * om.x + r1.y * om.y + r1.z * om.z,
-                            r2.x * om.x + r2.y * om.y + r2.z * om.z);
-          const v3 dl = mk3(r0.x * d.x + r0.y * d.y + r0.z * d.z,
-                            r1.x * d.x + r1.y * d.y + r1.z * d.z,
-                            r2.x * d.x + r2.y * d.y + r2.z * d.z);
-          const float ts = -dot(ol, dl) / dot(dl, dl);
-          if (!(ts > G.t_min && ts >= t_lo && ts < t_hi)) continue;
-          const v3 xl = add(ol, mul(dl, ts));
-          const float a = fminf(G.alpha_max, op * expf(-0.5f * dot(xl, xl)));
+          // conservative pre-test: the accepted point o + t* d lies inside the cut-off
+          // ellipsoid, so within rb of the mean, and |t* - tc| <= rb
+          const float4 bs = gd[4];
+          const float tc = -dot(om, d);
+          if (dot(om, om) - tc * tc > bs.x) continue;
+          if (tc + bs.y < t_lo || tc - bs.y >= t_hi) continue;
+          const float op = gd[3].w;
+          // exact test in FP64: t* and the Mahalanobis distance m^2 at t*
+          const double ox = (double)o.x - (double)r0.w, oy = (double)o.y - (double)r1.w,
+                       oz = (double)o.z - (double)r2.w;
+          const double olx = fma((double)r0.x, ox, fma((double)r0.y, oy, (double)r0.z * oz));
+          const double oly = fma((double)r1.x, ox, fma((double)r1.y, oy, (double)r1.z * oz));
+          const double olz = fma((double)r2.x, ox, fma((double)r2.y, oy, (double)r2.z * oz));
+          const double dlx =
+              fma((double)r0.x, d64[0], fma((double)r0.y, d64[1], (double)r0.z * d64[2]));
+          const double dly =
+              fma((double)r1.x, d64[0], fma((double)r1.y, d64[1], (double)r1.z * d64[2]));
+          const double dlz =
+              fma((double)r2.x, d64[0], fma((double)r2.y, d64[1], (double)r2.z * d64[2]));
+          const double tsd = -(olx * dlx + oly * dly + olz * dlz) / (dlx * dlx + dly * dly + dlz * dlz);
+          if (!(tsd > (double)G.t_min && tsd >= (double)t_lo && tsd < (double)t_hi)) continue;
+          const double xx = fma(dlx, tsd, olx), xy = fma(dly, tsd, oly), xz = fma(dlz, tsd, olz);
+          const float m2 = (float)(xx * xx + xy * xy + xz * xz);
+          const float a = fminf(G.alpha_max, op * expf(-0.5f * m2));
           if (!(a >= G.alpha_min)) continue;
+          const float ts = (float)tsd;
           uint64_t k = ((uint64_t)(uint32_t)__float_as_int(ts) << 32) | (uint32_t)gi;
           if (k <= after || k >= key[kBuf - 1]) continue;
           float av = a;
@@ -285,7 +325,7 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
           const float Tn = T * (1.0f - a);
           if (Tn < G.T_min) { done = true; continue; }
           const int32_t gi = (int32_t)(key[s] & 0xFFFFFFFFu);
-          const float4 col = G.gdata[4 * gi + 3];
+          const float4 col = G.gdata[(size_t)kGRows * gi + 3];
           const float ts = __int_as_float((int)(key[s] >> 32));
           const float wgt = T * a;
           Cr += wgt * col.x;

@@ -124,7 +124,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
   world_dir64(ps.F, da, db, e.z, s.w64);
   s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
   s.ct = (float)e.z;
-  s.et = env_taps(s.w, a.H, a.W, a.u_scale, a.v_scale);
+  s.et = env_taps64(s.w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
   s.Le[0] = s.Le[1] = s.Le[2] = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -133,7 +133,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
     s.Le[1] += s.et.w[t] * e[1];
     s.Le[2] += s.et.w[t] * e[2];
   }
-  s.tt = oct_taps(s.w, a.R, a.halfR);
+  s.tt = oct_taps64(s.w64, a.R);
   s.Lin[0] = s.Lin[1] = s.Lin[2] = 0.0f;
   s.O = 0.0f;
   const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_query(ShadeArgs a, int32_t k, const flo
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= a.n * (int64_t)D) return;
   const int64_t i = t / D;
-  const v3 w = mk3(dirs[3 * t], dirs[3 * t + 1], dirs[3 * t + 2]);
-  const Taps tt = oct_taps(w, a.R, a.halfR);
+  const double w[3] = {dirs[3 * t], dirs[3 * t + 1], dirs[3 * t + 2]};
+  const Taps tt = oct_taps64(w, a.R);
   const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
   const size_t RR = (size_t)a.R * a.R;
   float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, oc = 0.0f;
@@ -367,15 +367,32 @@ hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipSt
   return dispatch(false, a, k, format, s);
 }
 
-__global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, double4* tab) {
+// per-call tables: directions, and reference directions of the environment's texel
+// columns (phi_i = 2 pi (i + 0.5)/W - pi, i in [-1, W]) and rows (theta_j = pi (j + 0.5)/H,
+// j in [-1, H]), all in FP64
+__global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, double4* tab,
+                                                   int32_t H, int32_t W, double2* col_ref,
+                                                   double2* row_ref) {
   const int32_t j = blockIdx.x * 256 + threadIdx.x;
   if (j < S) tab[j] = dir_entry(j, S, rho);
+  if (j < W + 2) {
+    double sn, cs;
+    sincospi(2.0 * ((double)(j - 1) + 0.5) / (double)W - 1.0, &sn, &cs);
+    col_ref[j] = make_double2(cs, sn);
+  }
+  if (j < H + 2) {
+    double sn, cs;
+    sincospi(((double)(j - 1) + 0.5) / (double)H, &sn, &cs);
+    row_ref[j] = make_double2(cs, sn);
+  }
 }
 
-hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, double4* tab,
-                            hipStream_t s) {
+hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,
+                            double4* tab, double2* col_ref, double2* row_ref, hipStream_t s) {
   const uint32_t rho = per_point ? 0u : rotation24(seed, false, 0u);
-  hipLaunchKernelGGL(k_dir_table, dim3((S + 255) / 256), dim3(256), 0, s, S, rho, tab);
+  const int32_t n = max(S, max(W + 2, H + 2));
+  hipLaunchKernelGGL(k_dir_table, dim3((n + 255) / 256), dim3(256), 0, s, S, rho, tab, H, W,
+                     col_ref, row_ref);
   return hipGetLastError();
 }
 

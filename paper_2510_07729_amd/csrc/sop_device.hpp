@@ -136,6 +136,43 @@ __device__ __forceinline__ Taps oct_taps(v3 w, int R, float halfR) {
   return t;
 }
 
+// Same taps from an FP64 direction: the bilinear weights of the probe textures then carry
+// no FP32 coordinate rounding (it would be amplified in the texture gradient of entries
+// that receive only small weights).
+__device__ __forceinline__ Taps oct_taps64(const double w[3], int R) {
+  const double s = fabs(w[0]) + fabs(w[1]) + fabs(w[2]);
+  const double inv = 1.0 / s;
+  double px = w[0] * inv, py = w[1] * inv;
+  if (w[2] < 0.0) {
+    const double fx = (1.0 - fabs(py)) * (px < 0.0 ? -1.0 : 1.0);
+    const double fy = (1.0 - fabs(px)) * (py < 0.0 ? -1.0 : 1.0);
+    px = fx;
+    py = fy;
+  }
+  const double halfR = 0.5 * (double)R, hi = (double)R - 0.5;
+  const double cu = fmin(fmax((px + 1.0) * halfR - 0.5, -0.5), hi);
+  const double cv = fmin(fmax((py + 1.0) * halfR - 0.5, -0.5), hi);
+  const double i0f = floor(cu), j0f = floor(cv);
+  const double fx = cu - i0f, fy = cv - j0f;
+  const int i0 = (int)i0f, j0 = (int)j0f;
+  Taps t;
+  int ii, jj;
+  oct_wrap(i0, j0, R, ii, jj);
+  t.off[0] = jj * R + ii;
+  oct_wrap(i0 + 1, j0, R, ii, jj);
+  t.off[1] = jj * R + ii;
+  oct_wrap(i0, j0 + 1, R, ii, jj);
+  t.off[2] = jj * R + ii;
+  oct_wrap(i0 + 1, j0 + 1, R, ii, jj);
+  t.off[3] = jj * R + ii;
+  // weights in FP64: 1 - fx cancels when fx is close to 1
+  t.w[0] = (float)((1.0 - fx) * (1.0 - fy));
+  t.w[1] = (float)(fx * (1.0 - fy));
+  t.w[2] = (float)((1.0 - fx) * fy);
+  t.w[3] = (float)(fx * fy);
+  return t;
+}
+
 __device__ __forceinline__ float4 load_texel(const float4* tex, size_t i) { return tex[i]; }
 __device__ __forceinline__ float4 load_texel(const uint2* tex, size_t i) {
   const uint2 u = tex[i];
@@ -179,6 +216,71 @@ __device__ __forceinline__ EnvTaps env_taps(v3 w, int H, int W, float u_scale, f
   t.w[1] = fx * (1.0f - fy);
   t.w[2] = (1.0f - fx) * fy;
   t.w[3] = fx * fy;
+  return t;
+}
+
+// Accurate variant. The texel is chosen from the FP32 angles; the fraction inside it is the
+// FP64 angle between the direction and the texel's reference direction (the direction
+// at cu = i exactly, from a per-call table), through a small-angle arctangent series.
+// Both angles then carry ~1e-16 instead of ~1e-7 error, so bilinear weights (and the
+// gradients they scatter) are exact to FP32 rounding even when a weight is small.
+//   col_ref[i + 1] = (cos, sin) of phi_i = 2 pi (i + 0.5)/W - pi,   i in [-1, W]
+//   row_ref[j + 1] = (cos, sin) of theta_j = pi (j + 0.5)/H,        j in [-1, H]
+__device__ __forceinline__ double small_atan(double z) {
+  // arctan series; |z| <= 0.2 gives |error| < z^15/15 < 3e-12 relative to the texel width
+  const double z2 = z * z;
+  return z * (1.0 + z2 * (-1.0 / 3 + z2 * (1.0 / 5 + z2 * (-1.0 / 7 + z2 * (1.0 / 9 +
+             z2 * (-1.0 / 11 + z2 * (1.0 / 13)))))));
+}
+
+__device__ __forceinline__ double angle_from(double c, double s, double x, double y) {
+  // signed angle from direction (c, s) to (x, y), both in one plane, |angle| < pi/2
+  const double cr = c * y - s * x, dt = c * x + s * y;
+  const double z = cr / dt;
+  return fabs(z) <= 0.2 ? small_atan(z) : atan2(cr, dt);
+}
+
+__device__ __forceinline__ EnvTaps env_taps64(const double w[3], int H, int W, float u_scale,
+                                              float v_scale, const double2* col_ref,
+                                              const double2* row_ref) {
+  const float xf = (float)w[0], yf = (float)w[1], zf = (float)w[2];
+  const float rhof = sqrtf(xf * xf + yf * yf);
+  const float phif = atan2f(yf, xf), thetaf = atan2f(rhof, zf);
+  float cuf = fminf(fmaxf(fmaf(phif, u_scale, 0.5f * (float)W) - 0.5f, -0.5f), (float)W - 0.5f);
+  float cvf = fminf(fmaxf(thetaf * v_scale - 0.5f, -0.5f), (float)H - 0.5f);
+  int i0 = (int)floorf(cuf), j0 = (int)floorf(cvf);   // i0 in [-1, W-1], j0 in [-1, H-1]
+  // exact fractions relative to the reference directions of i0 and j0
+  const double2 cr = col_ref[i0 + 1];
+  double fx = angle_from(cr.x, cr.y, w[0], w[1]) * ((double)W / (2.0 * 3.14159265358979323846));
+  double rho2 = w[0] * w[0] + w[1] * w[1];
+  double rho = (double)rhof;
+  rho = rho > 0.0 ? 0.5 * (rho + rho2 / rho) : 0.0;     // one Newton step to FP64 accuracy
+  const double2 rr = row_ref[j0 + 1];
+  // angle from theta_ref to theta in the (z, rho) plane, where the direction sits at angle
+  // theta from +z and the reference at theta_ref = (cos, sin)
+  double fy = angle_from(rr.x, rr.y, w[2], rho) * ((double)H / 3.14159265358979323846);
+  // the FP32 choice of texel may be off by one near a boundary
+  if (fx < 0.0) { fx += 1.0; i0 -= 1; } else if (fx >= 1.0) { fx -= 1.0; i0 += 1; }
+  if (fy < 0.0) { fy += 1.0; j0 -= 1; } else if (fy >= 1.0) { fy -= 1.0; j0 += 1; }
+  fx = fmin(fmax(fx, 0.0), 1.0);
+  fy = fmin(fmax(fy, 0.0), 1.0);
+  // wrap columns (i0 may now be -2 .. W) and clamp rows
+  int i1 = i0 + 1, j1 = j0 + 1;
+  i0 = i0 < 0 ? i0 + W : (i0 >= W ? i0 - W : i0);
+  i1 = i1 < 0 ? i1 + W : (i1 >= W ? i1 - W : i1);
+  i0 = min(max(i0, 0), W - 1);
+  i1 = min(max(i1, 0), W - 1);
+  j0 = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
+  j1 = j1 < 0 ? 0 : (j1 > H - 1 ? H - 1 : j1);
+  EnvTaps t;
+  t.off[0] = j0 * W + i0;
+  t.off[1] = j0 * W + i1;
+  t.off[2] = j1 * W + i0;
+  t.off[3] = j1 * W + i1;
+  t.w[0] = (float)((1.0 - fx) * (1.0 - fy));
+  t.w[1] = (float)(fx * (1.0 - fy));
+  t.w[2] = (float)((1.0 - fx) * fy);
+  t.w[3] = (float)(fx * fy);
   return t;
 }
 

@@ -76,6 +76,8 @@ struct ShadeArgs {
   float u_scale, v_scale;
   int32_t S;
   const double4* dir_tab;   // [S] local directions of the call (see dir_entry)
+  const double2* col_ref;   // [W+2] environment column reference directions
+  const double2* row_ref;   // [H+2] environment row reference directions
   float inv2S;
   float scale;            // 2 pi / S
   uint32_t seed;
@@ -92,8 +94,8 @@ struct ShadeArgs {
 };
 
 // per-call direction table: dir_entry(j, S, rho) with rho of the call (0 when per point)
-hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, double4* tab,
-                            hipStream_t s);
+hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,
+                            double4* tab, double2* col_ref, double2* row_ref, hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
@@ -106,8 +108,8 @@ struct BakeGrid {
   float origin[3];
   float cell[3];           // cell size per axis
   float inv_cell[3];
-  const float4* gdata;     // [G][4]: (M row0 | mu.x) (M row1 | mu.y) (M row2 | mu.z)
-                           //          (color rgb | opacity)
+  const float4* gdata;     // [G][5]: (M row0 | mu.x) (M row1 | mu.y) (M row2 | mu.z)
+                           //          (color rgb | opacity) (r^2, r, 0, 0) bounding sphere
   const int32_t* cell_start;  // [cells + 1]
   const int32_t* entries;     // [capacity] Gaussian indices, cell-major
   int32_t capacity;

@@ -145,10 +145,10 @@ class Plan:
                 "sop_plan_info")
         return n.value, tuple(dims), sc.value
 
-    def workspace_size(self, op: int, n: int, k: int, n_dirs: int = 1,
+    def workspace_size(self, op: int, n: int, k: int, n_dirs: int = 1, env_hw=(0, 0),
                        with_neighbors: bool = False) -> int:
-        return int(self._lib.sop_workspace_size(self.handle, op, n, k, n_dirs,
-                                                int(with_neighbors)))
+        return int(self._lib.sop_workspace_size(self.handle, op, n, k, n_dirs, int(env_hw[0]),
+                                                int(env_hw[1]), int(with_neighbors)))
 
     def close(self) -> None:
         if getattr(self, "handle", None):
@@ -184,7 +184,8 @@ def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
     Lin = torch.empty((n, D, 3), dtype=torch.float32, device=dev)
     O = torch.empty((n, D), dtype=torch.float32, device=dev)
     kk = nb.k if nb is not None else k
-    ws = workspace(plan.workspace_size(L.SOP_OP_QUERY, n, kk, D, nb is not None), dev)
+    ws = workspace(plan.workspace_size(L.SOP_OP_QUERY, n, kk, D, with_neighbors=nb is not None),
+                   dev)
     m, cp = _maps(texels), pts.c()
     nbc = nb.c() if nb is not None else None
     L.check(plan._lib.sop_query(plan.handle, C.byref(m), C.byref(cp),
@@ -216,7 +217,8 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
     irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
     kk = nb.k if nb is not None else k
     if ws is None:
-        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, nb is not None), dev)
+        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, env.shape[:2],
+                                           nb is not None), dev)
     o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr)
     m, e, cp = _maps(texels), _env(env), pts.c()
     nbc = nb.c() if nb is not None else None
@@ -254,7 +256,7 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
             texels.shape, dtype=torch.float32, device=dev)
     kk = nb.k if nb is not None else k
     if ws is None:
-        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, n, kk, n_dirs,
+        ws = workspace(plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, n, kk, n_dirs, env.shape[:2],
                                            nb is not None), dev)
     o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point)
     m, e, cp = _maps(texels), _env(env), pts.c()
@@ -274,11 +276,12 @@ class BakePlan:
     """Gaussian grid for sop_bake (sop_bake_plan_create / _update / _destroy)."""
 
     def __init__(self, mean, scale, rotation, opacity, color, t_min=0.0, alpha_min=1.0 / 255.0,
-                 alpha_max=0.99, T_min=1e-4):
+                 alpha_max=0.99, T_min=1e-4, cell_scale=0.0):
         self._lib = L.load()
         self._keep = None
         g = self._gaussians(mean, scale, rotation, opacity, color)
-        o = L.sop_bake_opts(float(t_min), float(alpha_min), float(alpha_max), float(T_min))
+        o = L.sop_bake_opts(float(t_min), float(alpha_min), float(alpha_max), float(T_min),
+                            float(cell_scale))
         h = C.c_void_p()
         L.check(self._lib.sop_bake_plan_create(C.byref(g), C.byref(o), _stream(), C.byref(h)),
                 "sop_bake_plan_create")

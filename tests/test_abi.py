@@ -77,7 +77,7 @@ def test_null_plan_and_null_out_are_rejected():
     assert lib.sop_plan_rebuild(None, None, None) == L.SOP_ERR_INVALID_ARGUMENT
     assert lib.sop_plan_destroy(None) == L.SOP_OK
     assert lib.sop_bake_plan_destroy(None) == L.SOP_OK
-    assert lib.sop_workspace_size(None, 0, 10, 4, 64, 0) == 0
+    assert lib.sop_workspace_size(None, 0, 10, 4, 64, 32, 64, 0) == 0
     pts = L.sop_points()
     assert lib.sop_knn(None, C.byref(pts), 4, math.inf, None, None, None, None, 0,
                        None) == L.SOP_ERR_INVALID_ARGUMENT
@@ -104,7 +104,7 @@ def test_bake_plan_validation():
     g.count = 1
     for p in ("mean", "scale", "rotation", "opacity", "color"):
         setattr(g, p, 0x1000)
-    o = L.sop_bake_opts(0.0, 0.5, 0.4, 1e-4)     # alpha_max < alpha_min
+    o = L.sop_bake_opts(0.0, 0.5, 0.4, 1e-4, 0.0)     # alpha_max < alpha_min
     assert lib.sop_bake_plan_create(C.byref(g), C.byref(o), None, C.byref(h)) == \
         L.SOP_ERR_INVALID_ARGUMENT
     assert "bake options" in lib.sop_last_error().decode()
