@@ -202,13 +202,69 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
   }
 }
 
-// Adjoint. With g the upstream gradient of the point and s = 2 pi / S:
+// Adjoint of one sample. With g the upstream gradient of the point and s = 2 pi / S:
 //   d/da_c  = s sum g_c L_i,c [ (1-m) cos/pi + spec m (1 - x^5) ]
 //   d/dm    = s sum_c g_c L_i,c [ -a_c cos/pi + spec (a_c - 0.04)(1 - x^5) ]
 //   d/dr    = s sum_c g_c L_i,c F_c/(4 NoV) (dD/dalpha G + D dG/dalpha) 2 r
 //   d/dLin_k[t,c] = s g_c fcos_c w_k b_t,   d/dO_k[t] = -s sum_c g_c fcos_c Le_c w_k b_t
 //   d/denv[t',c]  = s g_c fcos_c (1 - O) b'_t'
-// where spec = D G1(NoL) G1(NoV) / (4 NoV) and x = 1 - v.h.
+// where spec = D G1(NoL) G1(NoV) / (4 NoV) and x = 1 - v.h. Material terms are added to
+// ga/gr/gm (without the factor s); gl (RGB) and go (O) are the texture factors before the
+// w_k b_t weights, ge the environment factors before b'.
+struct SampleAdj {
+  float gl[3], go, ge[3];
+};
+
+template <int KT, typename TexT>
+__device__ __forceinline__ void sample_adjoint(const ShadeArgs& a, const PointState& ps,
+                                               const Neighbors<KT>& nb, int32_t k, int j,
+                                               const float g[3], float ga[3], float& gr,
+                                               float& gm, Sample& s, SampleAdj& r) {
+  const Material& M = ps.M;
+  const float al[3] = {M.a.x, M.a.y, M.a.z};
+  eval_sample<KT, TexT>(a, ps, nb, k, j, s);
+  const BrdfTerms bt = brdf_terms(M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+  const float om5 = 1.0f - bt.x5;
+  // dD/dalpha = 2 alpha (1 - NoH^2 - alpha^2 NoH^2) / (pi q^3)
+  const float dD = 2.0f * M.alpha * (bt.one_m - M.a2 * bt.NoH2) / (kPi * bt.q * bt.q * bt.q);
+  const float denL = s.ct * M.one_m_k + M.k, denV = M.NoV * M.one_m_k + M.k;
+  const float dG1L = -s.ct * (1.0f - s.ct) / (denL * denL);
+  const float dG1V = -M.NoV * (1.0f - M.NoV) / (denV * denV);
+  const float G = bt.G1L * M.g1v;
+  const float dG = 0.5f * (dG1L * M.g1v + bt.G1L * dG1V);
+  const float i4nv = 1.0f / (4.0f * M.NoV);
+  const float drough = i4nv * (dD * G + bt.D * dG) * 2.0f * M.r;
+  r.go = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+    const float F0 = 0.04f * (1.0f - M.m) + al[c] * M.m;
+    const float F = F0 + (1.0f - F0) * bt.x5;
+    const float fc = (1.0f - M.m) * al[c] * kInvPi * s.ct + bt.spec * F;
+    const float cm = g[c] * Li;
+    ga[c] += cm * ((1.0f - M.m) * kInvPi * s.ct + bt.spec * M.m * om5);
+    gm += cm * (-al[c] * kInvPi * s.ct + bt.spec * (al[c] - 0.04f) * om5);
+    gr += cm * F * drough;
+    const float gf = g[c] * fc * a.scale;
+    r.gl[c] = gf;
+    r.go -= gf * s.Le[c];
+    r.ge[c] = gf * (1.0f - s.O);
+  }
+}
+
+__device__ __forceinline__ void scatter_env(const ShadeArgs& a, const Sample& s,
+                                            const SampleAdj& r) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float* dst = a.g_env + (size_t)s.et.off[t] * 3;
+    unsafeAtomicAdd(dst + 0, s.et.w[t] * r.ge[0]);
+    unsafeAtomicAdd(dst + 1, s.et.w[t] * r.ge[1]);
+    unsafeAtomicAdd(dst + 2, s.et.w[t] * r.ge[2]);
+  }
+}
+
+// General adjoint: one wavefront per point, texture gradients scattered with atomics.
+// Used when the grouped kernel below does not apply (res > 32, more than 16384 probes).
 template <int KT, typename TexT>
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
   const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
@@ -219,8 +275,6 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
   Neighbors<KT> nb;
   nb.load(a, ps.p, k);
   const float g[3] = {a.grad[3 * ps.p], a.grad[3 * ps.p + 1], a.grad[3 * ps.p + 2]};
-  const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
-  const Material& M = ps.M;
   const size_t RR = (size_t)a.R * a.R;
   const int kc = KT > 0 ? KT : nb.count(k);
 
@@ -229,34 +283,8 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
     const int j = j0 + lane;
     if (j < a.S) {
       Sample s;
-      eval_sample<KT, TexT>(a, ps, nb, k, j, s);
-      const BrdfTerms bt = brdf_terms(M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
-      const float om5 = 1.0f - bt.x5;
-      // dD/dalpha = 2 alpha (1 - NoH^2 - alpha^2 NoH^2) / (pi q^3)
-      const float dD = 2.0f * M.alpha * (bt.one_m - M.a2 * bt.NoH2) / (kPi * bt.q * bt.q * bt.q);
-      const float denL = s.ct * M.one_m_k + M.k, denV = M.NoV * M.one_m_k + M.k;
-      const float dG1L = -s.ct * (1.0f - s.ct) / (denL * denL);
-      const float dG1V = -M.NoV * (1.0f - M.NoV) / (denV * denV);
-      const float G = bt.G1L * M.g1v;
-      const float dG = 0.5f * (dG1L * M.g1v + bt.G1L * dG1V);
-      const float i4nv = 1.0f / (4.0f * M.NoV);
-      const float drough = i4nv * (dD * G + bt.D * dG) * 2.0f * M.r;
-      float gl[3], go = 0.0f, ge[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
-        const float F0 = 0.04f * (1.0f - M.m) + al[c] * M.m;
-        const float F = F0 + (1.0f - F0) * bt.x5;
-        const float fc = (1.0f - M.m) * al[c] * kInvPi * s.ct + bt.spec * F;
-        const float cm = g[c] * Li;
-        ga[c] += cm * ((1.0f - M.m) * kInvPi * s.ct + bt.spec * M.m * om5);
-        gm += cm * (-al[c] * kInvPi * s.ct + bt.spec * (al[c] - 0.04f) * om5);
-        gr += cm * F * drough;
-        const float gf = g[c] * fc * a.scale;
-        gl[c] = gf;
-        go -= gf * s.Le[c];
-        ge[c] = gf * (1.0f - s.O);
-      }
+      SampleAdj r;
+      sample_adjoint<KT, TexT>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
       if (a.g_tex) {
         for (int s2 = 0; s2 < kc; ++s2) {
           const int32_t id = nb.id(s2, a, ps.p, k);
@@ -267,22 +295,14 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
           for (int t = 0; t < 4; ++t) {
             const float cw = wk * s.tt.w[t];
             float* dst = GT + (size_t)s.tt.off[t] * 4;
-            unsafeAtomicAdd(dst + 0, cw * gl[0]);
-            unsafeAtomicAdd(dst + 1, cw * gl[1]);
-            unsafeAtomicAdd(dst + 2, cw * gl[2]);
-            unsafeAtomicAdd(dst + 3, cw * go);
+            unsafeAtomicAdd(dst + 0, cw * r.gl[0]);
+            unsafeAtomicAdd(dst + 1, cw * r.gl[1]);
+            unsafeAtomicAdd(dst + 2, cw * r.gl[2]);
+            unsafeAtomicAdd(dst + 3, cw * r.go);
           }
         }
       }
-      if (a.g_env) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          float* dst = a.g_env + (size_t)s.et.off[t] * 3;
-          unsafeAtomicAdd(dst + 0, s.et.w[t] * ge[0]);
-          unsafeAtomicAdd(dst + 1, s.et.w[t] * ge[1]);
-          unsafeAtomicAdd(dst + 2, s.et.w[t] * ge[2]);
-        }
-      }
+      if (a.g_env) scatter_env(a, s, r);
     }
   }
   const float r0 = wave_sum(ga[0]) * a.scale, r1 = wave_sum(ga[1]) * a.scale,
@@ -296,6 +316,162 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
     }
     if (a.g_rough) a.g_rough[ps.p] = rr;
     if (a.g_metal) a.g_metal[ps.p] = rm;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched adjoint: a workgroup of kBatch wavefronts takes kBatch points that are
+// consecutive in the processing order (they share most of their probes), one wavefront per
+// point. Every point's texture adjoint H_p (its samples' factors spread over their 4 taps)
+// is accumulated densely in LDS. Then, for each distinct probe k of the batch, each thread
+// forms sum_p w_{p,k} H_p over the flattened texel-channel values it owns
+// (v = t + kBatchThreads * i) and adds it to g_tex[k] with atomics that are coalesced
+// (consecutive lanes, consecutive words). This replaces K*4*4 scattered atomics per
+// sample by about (distinct probes / kBatch) * res^2 * 4 coalesced atomics per point.
+// ------------------------------------------------------------------------------------------
+constexpr int kBatch = 8;
+constexpr int kBatchThreads = kBatch * 64;
+constexpr int kMaxRes = 32;
+constexpr int kVPT = kMaxRes * kMaxRes * 4 / kBatchThreads;   // values per thread (8)
+constexpr int kMaxEntries = kBatch * 16;                      // (point, neighbour) pairs
+
+template <int KT, typename TexT>
+__global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a, int32_t k) {
+  extern __shared__ float lds[];
+  const int MV = a.R * a.R * 4;                         // values per map
+  float* H = lds;                                       // [kBatch][MV]
+  int32_t* eid = reinterpret_cast<int32_t*>(H + kBatch * MV);   // [kMaxEntries] probe ids
+  float* ew = reinterpret_cast<float*>(eid + kMaxEntries);      // [kMaxEntries] weights
+  int32_t* eslot = reinterpret_cast<int32_t*>(ew + kMaxEntries);  // [kMaxEntries] slot
+  int32_t* uni = eslot + kMaxEntries;                   // [kMaxEntries] probe of slot
+  int32_t* erank = uni + kMaxEntries;                   // [kMaxEntries] slot of a leader
+  float* W = reinterpret_cast<float*>(erank + kMaxEntries);     // [kMaxEntries][kBatch]
+  int32_t* misc = reinterpret_cast<int32_t*>(W + kMaxEntries * kBatch);  // [1]
+
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int64_t g0 = (int64_t)blockIdx.x * kBatch;
+  const int bn = (int)min((int64_t)kBatch, a.n - g0);
+  if (bn <= 0) return;
+  const int ne = kBatch * k;
+
+  for (int i = tid; i < kBatch * MV; i += kBatchThreads) H[i] = 0.0f;
+  for (int i = tid; i < kMaxEntries * kBatch; i += kBatchThreads) W[i] = 0.0f;
+  if (tid < ne) {
+    const int b = tid / k, s2 = tid % k;
+    int32_t id = -1;
+    float w = 0.0f;
+    if (b < bn) {
+      const int32_t o = a.order ? a.order[g0 + b] : (int32_t)(g0 + b);
+      if ((uint64_t)o < (uint64_t)a.n) {
+        id = a.nb_idx[(int64_t)o * k + s2];
+        w = a.nb_w[(int64_t)o * k + s2];
+        if ((uint32_t)id >= (uint32_t)a.P) id = -1;
+      }
+    }
+    eid[tid] = id;
+    ew[tid] = w;
+  }
+  __syncthreads();
+  // distinct probes of the batch: entry e leads if no earlier entry has its probe; slots are
+  // the ranks of the leading entries (each thread scans at most kMaxEntries entries)
+  int32_t lead = -1;
+  if (tid < ne) {
+    const int32_t id = eid[tid];
+    if (id >= 0) {
+      lead = tid;
+      for (int e = 0; e < tid; ++e)
+        if (eid[e] == id) { lead = e; break; }
+    }
+    eslot[tid] = lead;
+  }
+  __syncthreads();
+  if (tid < ne && lead == tid) {
+    int32_t rank = 0;
+    for (int e = 0; e < tid; ++e) rank += (eslot[e] == e) ? 1 : 0;
+    erank[tid] = rank;
+    uni[rank] = eid[tid];
+  }
+  if (tid == 0) {
+    int32_t n = 0;
+    for (int e = 0; e < ne; ++e) n += (eslot[e] == e) ? 1 : 0;
+    misc[0] = n;
+  }
+  __syncthreads();
+  if (tid < ne && lead >= 0) W[erank[lead] * kBatch + tid / k] = ew[tid];
+  __syncthreads();
+
+  // --- splat: wavefront b takes point b, lanes take directions -----------------------------
+  {
+    const int b = wave;
+    if (b < bn) {
+      PointState ps;
+      if (load_point(a, g0 + b, ps)) {
+        Neighbors<KT> nb;
+        nb.load(a, ps.p, k);
+        const float g[3] = {a.grad[3 * ps.p], a.grad[3 * ps.p + 1], a.grad[3 * ps.p + 2]};
+        float ga[3] = {0.0f, 0.0f, 0.0f}, gr = 0.0f, gm = 0.0f;
+        float* Hb = H + b * MV;
+        for (int j0 = 0; j0 < a.S; j0 += 64) {
+          const int j = j0 + lane;
+          if (j < a.S) {
+            Sample s;
+            SampleAdj r;
+            sample_adjoint<KT, TexT>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              float* dst = Hb + s.tt.off[t] * 4;
+              atomicAdd(dst + 0, s.tt.w[t] * r.gl[0]);
+              atomicAdd(dst + 1, s.tt.w[t] * r.gl[1]);
+              atomicAdd(dst + 2, s.tt.w[t] * r.gl[2]);
+              atomicAdd(dst + 3, s.tt.w[t] * r.go);
+            }
+            if (a.g_env) scatter_env(a, s, r);
+          }
+        }
+        const float v0 = wave_sum(ga[0]) * a.scale, v1 = wave_sum(ga[1]) * a.scale,
+                    v2 = wave_sum(ga[2]) * a.scale;
+        const float v3 = wave_sum(gr) * a.scale, v4 = wave_sum(gm) * a.scale;
+        if (lane == 0) {
+          if (a.g_albedo) {
+            a.g_albedo[3 * ps.p] = v0;
+            a.g_albedo[3 * ps.p + 1] = v1;
+            a.g_albedo[3 * ps.p + 2] = v2;
+          }
+          if (a.g_rough) a.g_rough[ps.p] = v3;
+          if (a.g_metal) a.g_metal[ps.p] = v4;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!a.g_tex) return;
+  // --- per distinct probe: sum_b W[u][b] H_b, coalesced flush ------------------------------
+  float h[kBatch][kVPT];
+#pragma unroll
+  for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+    for (int i = 0; i < kVPT; ++i) {
+      const int v = tid + kBatchThreads * i;
+      h[b][i] = (b < bn && v < MV) ? H[b * MV + v] : 0.0f;
+    }
+  const int nu = misc[0];
+  for (int u = 0; u < nu; ++u) {
+    float acc[kVPT];
+#pragma unroll
+    for (int i = 0; i < kVPT; ++i) acc[i] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const float w = W[u * kBatch + b];
+#pragma unroll
+      for (int i = 0; i < kVPT; ++i) acc[i] = fmaf(w, h[b][i], acc[i]);
+    }
+    float* dst = a.g_tex + (size_t)uni[u] * MV;
+#pragma unroll
+    for (int i = 0; i < kVPT; ++i) {
+      const int v = tid + kBatchThreads * i;
+      if (v < MV) unsafeAtomicAdd(dst + v, acc[i]);
+    }
   }
 }
 
@@ -363,8 +539,37 @@ static hipError_t dispatch(bool fwd, const ShadeArgs& a, int32_t k, int32_t form
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   return dispatch(true, a, k, format, s);
 }
+size_t batched_lds_bytes(int32_t R) {
+  return (size_t)kBatch * R * R * 4 * sizeof(float) + 5 * kMaxEntries * 4 +
+         (size_t)kMaxEntries * kBatch * 4 + 4;
+}
+
+template <int KT>
+static void launch_batched_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n + kBatch - 1) / kBatch));
+  const size_t lds = batched_lds_bytes(a.R);
+  // dynamic LDS above 64 KB must be allowed per kernel (gfx950 has 160 KB per CU)
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, uint2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, float4>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, uint2>), grid, dim3(kBatchThreads), lds, s, a,
+                       k);
+  else
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, float4>), grid, dim3(kBatchThreads), lds, s, a,
+                       k);
+}
+
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
-  return dispatch(false, a, k, format, s);
+  if (a.n == 0) return hipSuccess;
+  if (a.R > kMaxRes || k > 16) return dispatch(false, a, k, format, s);
+  switch (k) {
+    case 4: launch_batched_kt<4>(a, k, format, s); break;
+    case 8: launch_batched_kt<8>(a, k, format, s); break;
+    default: launch_batched_kt<0>(a, k, format, s); break;
+  }
+  return hipGetLastError();
 }
 
 // per-call tables: directions, and reference directions of the environment's texel
