@@ -659,6 +659,9 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
     return fail(code, msg);
   };
   if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake plan allocation");
+  // each pointer of the device view is set as soon as its buffer exists
+  pl->grid.gdata = pl->gdata;
+  pl->grid.overflow = pl->misc + 7;
   int32_t init[16] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN, 0, 0,
                       0, 0, 0, 0, 0, 0, 0, 0};
   e = hipMemcpyAsync(pl->misc, init, sizeof(init), hipMemcpyHostToDevice, s);
@@ -722,6 +725,7 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   alloc((void**)&pl->cursor, C1 * sizeof(int32_t));
   alloc((void**)&pl->scan_tmp, sopk::scan_tmp_elems(C1) * sizeof(int32_t));
   if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake grid allocation");
+  G.cell_start = pl->cell_start;
   int32_t total = 0;
   e = register_gaussians(pl, s);
   if (e == hipSuccess)
@@ -734,14 +738,11 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   pl->capacity = (int32_t)cap;
   alloc((void**)&pl->entries, (size_t)pl->capacity * sizeof(int32_t));
   if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake entries allocation");
+  G.entries = pl->entries;
+  G.capacity = pl->capacity;
   e = sopk::launch_gauss_fill(G, pl->aabb, pl->cell_start, pl->cursor, pl->entries,
                               pl->capacity, pl->misc + 7, s);
   if (e != hipSuccess) return bail(SOP_ERR_DEVICE, std::string("bake fill: ") + hipGetErrorString(e));
-  G.gdata = pl->gdata;
-  G.cell_start = pl->cell_start;
-  G.entries = pl->entries;
-  G.capacity = pl->capacity;
-  G.overflow = pl->misc + 7;
   *out = pl;
   return SOP_OK;
 }
