@@ -60,6 +60,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -73,6 +75,8 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        return copy_calibration(torch, dev)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
 
     # ------------------------------------------------------------------ workload (untimed)
@@ -106,7 +110,7 @@ def main() -> int:
     ws_b = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE_BACKWARD, N, K, S, env.shape[:2],
                                              True), dev)
 
-    names = ["bake", "probe_grid", "knn", "shade_fwd", "shade_bwd"]
+    names = ["bake_grid", "bake", "probe_grid", "knn", "shade_fwd", "shade_bwd"]
     ev = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for n in names}
     acc = {n: 0.0 for n in names}
@@ -115,8 +119,10 @@ def main() -> int:
         def mark(n, i):
             if timed:
                 ev[n][i].record()
-        mark("bake", 0)
+        mark("bake_grid", 0)
         bake_plan.update(g_mean, g_scale, g_rot, g_op, g_col)
+        mark("bake_grid", 1)
+        mark("bake", 0)
         sop.sop_bake(bake_plan, probes, R, texels=tex, depth_out=dep)
         mark("bake", 1)
         mark("probe_grid", 0)
@@ -166,19 +172,36 @@ def main() -> int:
     value = samples / (ms_per_step * 1e-3)
     fb_rate = samples / ((phase["shade_fwd"] + phase["shade_bwd"]) * 1e-3)
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel (each phase is one kernel launch except bake_grid)
     dom = max(("shade_fwd", "shade_bwd", "bake"), key=lambda n: phase[n])
     if dom == "bake":
-        roof = {"bound": "alu", "kernel": "k_bake", "achieved": None, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": None, "traffic": None,
-                "note": "data-dependent work per ray; see DESIGN.md"}
+        work = bake_work()
+        rays = P * R * R
+        flops = rays * work["resolved_per_ray_mean"] * work["flops_per_resolved"]
+        achieved = flops / (phase["bake"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "k_bake", "achieved": round(achieved, 5),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 6),
+                "traffic": measured_traffic("k_bake"),
+                "flops_per_unit": work["flops_per_resolved"],
+                "units_per_launch": round(rays * work["resolved_per_ray_mean"]),
+                "unit_def": "Gaussian resolved on a ray (accepted, up to the one ending it)",
+                "launch_ms": round(phase["bake"], 4)}
     else:
         f = flops_fwd(K) if dom == "shade_fwd" else flops_bwd(K)
         achieved = samples * f / (phase[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": "k_" + dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "flops_per_sample": f, "samples_per_launch": samples}
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": measured_traffic("k_" + dom),
+                "flops_per_unit": f, "units_per_launch": samples,
+                "unit_def": "shaded point-direction sample", "launch_ms": round(phase[dom], 4)}
+    # the shading kernels' own figures (the metric's fwd+bwd rate)
+    shade_roof = {}
+    for n, f in (("shade_fwd", flops_fwd(K)), ("shade_bwd", flops_bwd(K))):
+        a = samples * f / (phase[n] * 1e-3) / 1e12
+        shade_roof[n] = {"achieved_tflops": round(a, 3), "frac": round(a / PEAK_FP32_TFLOPS, 4),
+                         "flops_per_sample": f, "launch_ms": round(phase[n], 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -196,10 +219,52 @@ def main() -> int:
         "fwd_bwd_samples_per_s": round(fb_rate, 1),
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "roofline": roof,
+        "shade_roofline": shade_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def copy_calibration(torch, dev) -> int:
+    """A plain device-to-device copy of 1 GiB, three times: its FETCH_SIZE / WRITE_SIZE
+    counters per dispatch give the scale between those counters and HBM bytes."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 3}))
+    return 0
+
+
+def bake_work() -> dict:
+    """Resolved Gaussians per ray on this workload, measured once with the brute-force
+    reference trace (tests/golden/make_bake_work.py) and stored as data."""
+    with open(os.path.join(ROOT, "tests", "golden", "bake_work_object.json")) as f:
+        return json.load(f)
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
+    summary is missing or was taken on a different source of the kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_object_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = vals.get("source")
+    if not src or "bytes_per_launch" not in vals:
+        return None
+    fname, digest = src.split("@")
+    h = hashlib.sha256(open(os.path.join(ROOT, fname), "rb").read()).hexdigest()[:16]
+    return float(vals["bytes_per_launch"]) if h == digest else None
 
 
 def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
@@ -223,9 +288,16 @@ def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
         oracle.shade_backward(sub, idx, w, grad)
         return time.time() - t
 
-    t_small = shade_time(256)
-    m = int(min(sc.n, max(256, 256 * (0.5 * seconds) / max(t_small, 1e-3))))
-    t_shade = shade_time(m)
+    def grow(fn, start, limit, budget):
+        """run fn on growing sample sizes until one takes about `budget` seconds"""
+        m = start
+        t = fn(m)
+        while t < 0.7 * budget and m < limit:
+            m = int(min(limit, m * min(8.0, max(1.5, budget / max(t, 1e-3)))))
+            t = fn(m)
+        return m, t
+
+    m, t_shade = grow(shade_time, 256, sc.n, 0.5 * seconds)
     per_point = t_shade / m
 
     P = probes_np.shape[0]
@@ -236,9 +308,7 @@ def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
         oracle.bake_rays(gs, probes_np.astype(np.float64), R, rp, rt)
         return time.time() - t
 
-    t_b_small = bake_time(16)
-    nr = int(max(16, 16 * (0.5 * seconds) / max(t_b_small, 1e-3)))
-    t_bake = bake_time(nr)
+    nr, t_bake = grow(bake_time, 64, P * R * R, 0.5 * seconds)
     per_ray = t_bake / nr
 
     t_step = per_point * sc.n + per_ray * P * R * R

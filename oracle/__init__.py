@@ -80,7 +80,7 @@ def _sig(lib):
                                        dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr]
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
-                                  C.c_double, dptr, iptr]
+                                  C.c_double, dptr, iptr, iptr]
 
 
 def lib():
@@ -343,9 +343,10 @@ def shade_backward(sc, idx, w, grad, albedo=None, rough=None, metal=None, texels
 
 
 def bake_rays(gs, probe_pos, res, ray_probe, ray_texel, t_min=0.0, alpha_min=1.0 / 255.0,
-              alpha_max=0.99, T_min=1e-4):
+              alpha_max=0.99, T_min=1e-4, used=False):
     """Brute-force trace of the given (probe, texel) rays through every Gaussian.
-    Returns (out [n,5] = R,G,B,O,depth ; ambiguous [n] bool)."""
+    Returns (out [n,5] = R,G,B,O,depth ; ambiguous [n] bool), and with used=True also the
+    number of accepted Gaussians each ray resolves (up to and including the one ending it)."""
     keep = []
 
     def d(a):
@@ -358,8 +359,11 @@ def bake_rays(gs, probe_pos, res, ray_probe, ray_texel, t_min=0.0, alpha_min=1.0
     n = ray_probe.shape[0]
     out = np.zeros((n, 5))
     flags = np.zeros(n, np.int32)
+    n_used = np.zeros(n, np.int32)
     lib().orc_bake_rays(gs.count, d(gs.mean), d(gs.scale), d(gs.rotation), d(gs.opacity),
                         d(gs.color), d(probe_pos), res, n, prp, prt, t_min, alpha_min,
                         alpha_max, T_min, out.ctypes.data_as(dptr),
-                        flags.ctypes.data_as(iptr))
+                        flags.ctypes.data_as(iptr), n_used.ctypes.data_as(iptr))
+    if used:
+        return out, flags.astype(bool), n_used
     return out, flags.astype(bool)

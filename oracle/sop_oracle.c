@@ -619,7 +619,7 @@ static void mat3_vec(const double* M, const double x[3], double y[3]) {
 static int trace_ray(int G, const double* mean, const double* SI, const double* opacity,
                      const double* color, const double o[3], const double d[3], double t_min,
                      double alpha_min, double alpha_max, double T_min, orc_hit* hits,
-                     double out[5]) {
+                     double out[5], int32_t* n_used) {
   int nh = 0;
   double first_near = HUGE_VAL;   /* smallest t* of a Gaussian whose acceptance is near a cut */
   for (int g = 0; g < G; ++g) {
@@ -662,6 +662,13 @@ static int trace_ray(int G, const double* mean, const double* SI, const double* 
     T = Tn;
   }
   if (first_near < t_stop) amb = 1;
+  /* Gaussians the definition must resolve on this ray: every accepted one up to and
+     including the one that ends the ray */
+  if (n_used) {
+    int used = 0;
+    for (int s = 0; s < nh && hits[s].t <= t_stop; ++s) ++used;
+    *n_used = used;
+  }
   out[0] = C[0]; out[1] = C[1]; out[2] = C[2];
   out[3] = Wt;
   out[4] = Wt > 0.0 ? Dp / Wt : 0.0;
@@ -670,12 +677,13 @@ static int trace_ray(int G, const double* mean, const double* SI, const double* 
 
 /* Traces n_rays rays given as (probe index, texel index) pairs; texel t = v*R + u of a
  * resolution-R map, direction = octahedral decode of the texel centre.
- * out [n_rays][5] = (R,G,B,O,depth), flags [n_rays] (1 = ambiguous). */
+ * out [n_rays][5] = (R,G,B,O,depth), flags [n_rays] (1 = ambiguous), n_used [n_rays]
+ * (optional, may be NULL): accepted Gaussians up to and including the one that ends the ray. */
 void orc_bake_rays(int G, const double* mean, const double* scale, const double* rot,
                    const double* opacity, const double* color, const double* probe_pos,
                    int R, long n_rays, const int32_t* ray_probe, const int32_t* ray_texel,
                    double t_min, double alpha_min, double alpha_max, double T_min,
-                   double* out, int32_t* flags) {
+                   double* out, int32_t* flags, int32_t* n_used) {
   double* SI = gaussian_inverse_cov(G, scale, rot);
 #pragma omp parallel
   {
@@ -687,7 +695,7 @@ void orc_bake_rays(int G, const double* mean, const double* scale, const double*
       double d[3];
       orc_oct_decode((t % R) + 0.5, (t / R) + 0.5, R, d);
       flags[r] = trace_ray(G, mean, SI, opacity, color, o, d, t_min, alpha_min, alpha_max,
-                           T_min, hits, out + 5 * r);
+                           T_min, hits, out + 5 * r, n_used ? n_used + r : NULL);
     }
     free(hits);
   }
