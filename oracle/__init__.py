@@ -15,6 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sop_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -26,9 +27,9 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-s
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (always when force, else only if missing or stale)."""
     if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -78,6 +79,35 @@ def _sig(lib):
                                        dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, iptr,
                                        dptr, C.c_int, C.c_int, u32, C.c_int, dptr, dptr, dptr,
                                        dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr]
+    u64 = C.c_uint64
+    u32p = C.POINTER(u32)
+    fl = C.c_float
+    lib.orc_mlp_param_count.restype = C.c_int
+    lib.orc_bf16.restype = C.c_double
+    lib.orc_bf16.argtypes = [C.c_double]
+    lib.orc_pe_features.argtypes = [dptr, dptr, dptr, C.c_double, dptr, dptr, dptr]
+    lib.orc_mlp_forward.argtypes = [dptr, dptr, C.c_int] + [dptr] * 7
+    lib.orc_mlp_infer.argtypes = [dptr, C.c_long, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
+                                  dptr, dptr]
+    lib.orc_mlp_loss_grad.argtypes = [dptr, C.c_long, dptr, dptr, dptr, dptr, dptr, dptr, dptr,
+                                      C.c_int, dptr, dptr]
+    lib.orc_adam.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_double, C.c_double,
+                             C.c_double, C.c_double, C.c_int]
+    lib.orc_hash24.restype = u32
+    lib.orc_hash24.argtypes = [u32, u32, u32, u32]
+    lib.orc_prop_masses.restype = u64
+    lib.orc_prop_masses.argtypes = [fptr, fl, u32p]
+    lib.orc_prop_bin.restype = C.c_int
+    lib.orc_prop_bin.argtypes = [dptr, dptr]
+    lib.orc_prop_pdf.restype = C.c_double
+    lib.orc_prop_pdf.argtypes = [fptr, fl, dptr]
+    lib.orc_prop_samples.argtypes = [fptr, fl, C.c_int, u32, u32, iptr, dptr, dptr]
+    lib.orc_prop_shade.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr, dptr,
+                                   dptr, C.c_int, dptr, C.c_int, C.c_int, iptr, dptr, C.c_int,
+                                   fptr, fl, C.c_int, u32, dptr, dptr]
+    lib.orc_dump_integrand.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
+                                       dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, iptr, dptr,
+                                       C.c_int, C.c_int, u32, dptr]
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dptr, iptr, iptr]
@@ -367,3 +397,159 @@ def bake_rays(gs, probe_pos, res, ray_probe, ray_texel, t_min=0.0, alpha_min=1.0
     if used:
         return out, flags.astype(bool), n_used
     return out, flags.astype(bool)
+
+
+# ------------------------------------------------------------------------------------------
+# learned direction proposal (features, network, training, bin sampler, shading, targets)
+# ------------------------------------------------------------------------------------------
+MLP_IN, MLP_HIDDEN, MLP_BINS = 320, 64, 256
+
+
+def mlp_param_count() -> int:
+    return int(lib().orc_mlp_param_count())
+
+
+def mlp_offsets() -> dict:
+    """Slices of the parameter blob: W1 [320,64], b1, W2 [64,64], b2, W3 [64,256], b3."""
+    sizes = [("W1", MLP_IN * MLP_HIDDEN), ("b1", MLP_HIDDEN), ("W2", MLP_HIDDEN * MLP_HIDDEN),
+             ("b2", MLP_HIDDEN), ("W3", MLP_HIDDEN * MLP_BINS), ("b3", MLP_BINS)]
+    out, o = {}, 0
+    for name, n in sizes:
+        out[name] = slice(o, o + n)
+        o += n
+    return out
+
+
+def bf16(x: float) -> float:
+    return float(lib().orc_bf16(float(x)))
+
+
+def pe_features(pos, n, v, r, lo, hi):
+    """320 sinusoidal features of one point."""
+    out = np.zeros(MLP_IN)
+    a = [_d(x) for x in (pos, n, v)]
+    lo_, plo = _d(lo)
+    hi_, phi = _d(hi)
+    lib().orc_pe_features(a[0][1], a[1][1], a[2][1], float(r), plo, phi,
+                          out.ctypes.data_as(dptr))
+    return out
+
+
+def mlp_forward(params, feat, emulate_bf16=True):
+    """dict of a0, z1, h1, z2, h2, z3 (logits), q (softmax) for one feature vector."""
+    P, pp = _d(params)
+    f, pf = _d(feat)
+    out = {k: np.zeros(n) for k, n in (("a0", MLP_IN), ("z1", 64), ("h1", 64), ("z2", 64),
+                                       ("h2", 64), ("z3", MLP_BINS), ("q", MLP_BINS))}
+    lib().orc_mlp_forward(pp, pf, int(emulate_bf16),
+                          *(out[k].ctypes.data_as(dptr) for k in ("a0", "z1", "h1", "z2", "h2",
+                                                                  "z3", "q")))
+    return out
+
+
+def _pts(pos, normal, view, rough):
+    arrs = [_d(pos), _d(normal), _d(view), _d(rough)]
+    return [a for a, _ in arrs], [p for _, p in arrs]
+
+
+def mlp_infer(params, pos, normal, view, rough, lo, hi, emulate_bf16=True):
+    """(logits [N,256], probs [N,256]) of the proposal network."""
+    P, pp = _d(params)
+    keep, ptrs = _pts(pos, normal, view, rough)
+    lo_, plo = _d(lo)
+    hi_, phi = _d(hi)
+    N = keep[0].shape[0]
+    logits = np.zeros((N, MLP_BINS))
+    probs = np.zeros((N, MLP_BINS))
+    lib().orc_mlp_infer(pp, N, *ptrs, plo, phi, int(emulate_bf16),
+                        logits.ctypes.data_as(dptr), probs.ctypes.data_as(dptr))
+    return logits, probs
+
+
+def mlp_loss_grad(params, pos, normal, view, rough, lo, hi, targets, emulate_bf16=True):
+    """(loss, grad [P]) of the mean cross entropy against row-normalised targets [B,256]."""
+    P, pp = _d(params)
+    keep, ptrs = _pts(pos, normal, view, rough)
+    lo_, plo = _d(lo)
+    hi_, phi = _d(hi)
+    T, pt = _d(targets)
+    grad = np.zeros(P.shape[0])
+    loss = np.zeros(1)
+    lib().orc_mlp_loss_grad(pp, keep[0].shape[0], *ptrs, plo, phi, pt, int(emulate_bf16),
+                            grad.ctypes.data_as(dptr), loss.ctypes.data_as(dptr))
+    return float(loss[0]), grad
+
+
+def adam(params, m, v, grad, lr, beta1, beta2, eps, step):
+    """One Adam update in place on float64 arrays."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g, pg = _d(grad)
+    lib().orc_adam(params.shape[0], params.ctypes.data_as(dptr), m.ctypes.data_as(dptr),
+                   v.ctypes.data_as(dptr), pg, lr, beta1, beta2, eps, int(step))
+
+
+def hash24(seed, i, j, k) -> int:
+    return int(lib().orc_hash24(seed, i, j, k))
+
+
+def prop_masses(probs, eps):
+    """(integer bin masses [256] uint32, total)"""
+    p, pp = _f(probs)
+    c = np.zeros(MLP_BINS, np.uint32)
+    total = lib().orc_prop_masses(pp, eps, c.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return c, int(total)
+
+
+def prop_bin(wl):
+    a, p = _d(wl)
+    uv = np.zeros(2)
+    b = lib().orc_prop_bin(p, uv.ctypes.data_as(dptr))
+    return int(b), uv
+
+
+def prop_pdf(probs, eps, wl) -> float:
+    p, pp = _f(probs)
+    a, pw = _d(wl)
+    return float(lib().orc_prop_pdf(pp, eps, pw))
+
+
+def prop_samples(probs, eps, S, seed, i):
+    """(bins [S], local directions [S,3], densities [S]) of point i's draws."""
+    p, pp = _f(probs)
+    bins = np.zeros(S, np.int32)
+    wl = np.zeros((S, 3))
+    pdf = np.zeros(S)
+    lib().orc_prop_samples(pp, eps, S, seed, i, bins.ctypes.data_as(iptr),
+                           wl.ctypes.data_as(dptr), pdf.ctypes.data_as(dptr))
+    return bins, wl, pdf
+
+
+def prop_shade(sc, idx, w, probs, eps, n_dirs, seed, albedo=None, rough=None, metal=None,
+               texels=None, env=None, irradiance=False):
+    """Proposal-sampled shading of a ShadeScene with probs [N,256] (float32 decisions)."""
+    keep, a = _scene_args(sc, albedo, rough, metal, texels, env)
+    idx, pi = _i(idx)
+    w, pw = _d(w)
+    pr, ppr = _f(probs)
+    N = a[0]
+    rgb = np.zeros((N, 3))
+    irr = np.zeros((N, 3)) if irradiance else None
+    lib().orc_prop_shade(*a, pi, pw, idx.shape[1], ppr, eps, n_dirs, seed,
+                         rgb.ctypes.data_as(dptr), irr.ctypes.data_as(dptr) if irradiance else None)
+    del keep
+    return (rgb, irr) if irradiance else rgb
+
+
+def dump_integrand(sc, idx, w, samples_per_bin, seed, albedo=None, rough=None, metal=None,
+                   texels=None, env=None):
+    """Per-point bin integrals [N,256] of lum(f L_i cos) (training targets)."""
+    keep, a = _scene_args(sc, albedo, rough, metal, texels, env)
+    idx, pi = _i(idx)
+    w, pw = _d(w)
+    N = a[0]
+    T = np.zeros((N, MLP_BINS))
+    lib().orc_dump_integrand(*a, pi, pw, idx.shape[1], samples_per_bin, seed,
+                             T.ctypes.data_as(dptr))
+    del keep
+    return T

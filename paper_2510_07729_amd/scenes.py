@@ -18,6 +18,8 @@ surface, object views of 800x800 and scene views up to 1920x1080):
                       normal by 1% of the object's diagonal, 200k points, S=128, K=8,
                       256x512 environment.
 * ``diff_step``       the tiny scene plus hidden materials for a reconstruction target.
+* ``proposal_eval``   the tiny scene with 200k held-out points (learned proposal).
+* ``mlp_init`` / ``bin_probs``  proposal network weights and bin distributions.
 * ``gbuffer_frames``  8 pinhole cameras (1920x1080, f=3200 px) on a sphere of radius 3
                       looking at the unit sphere; 16,384 probes with 32x32 f16 maps.
 """
@@ -148,6 +150,42 @@ def tiny_shade(n_points: int = 4096, n_probes: int = 64, res: int = 16, H: int =
     return ShadeScene("tiny_shade", ppos, np.full(3, -1.05, F32), np.full(3, 1.05, F32), tex,
                       env, pts.astype(F32), normal, view, None, 0, albedo, rough, metal,
                       n_dirs, k, seed=seed)
+
+
+def proposal_eval(n_points: int = 200_000, seed: int = 0) -> ShadeScene:
+    """The tiny scene (same probes, textures and environment) with new shading points from
+    the proposal workload's own streams: the held-out set of the learned proposal."""
+    sc = tiny_shade(n_points=1, seed=seed)
+    cfg = CFG_PROPOSAL
+    pts = unit_vectors(rng(cfg, 2, seed), n_points)
+    view = hemisphere_vectors(rng(cfg, 3, seed), pts).astype(F32)
+    albedo, rough, metal = materials(rng(cfg, 4, seed), n_points)
+    return dataclasses.replace(sc, name="proposal_eval", pos=pts.astype(F32),
+                               normal=pts.astype(F32), view=view, albedo=albedo, rough=rough,
+                               metal=metal)
+
+
+# learned direction proposal: parameter blob W1 [320,64], b1, W2 [64,64], b2, W3 [64,256], b3
+MLP_SHAPES = ((320, 64), (64,), (64, 64), (64,), (64, 256), (256,))
+MLP_PARAMS = sum(int(np.prod(s)) for s in MLP_SHAPES)
+
+
+def mlp_init(seed: int = 0, gain: float = 1.0) -> np.ndarray:
+    """He-normal weights (std = gain * sqrt(2 / fan_in)), zero biases, as one f32 blob."""
+    g = rng(CFG_PROPOSAL, 10, seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            parts.append(g.standard_normal(shape).ravel() * gain * np.sqrt(2.0 / shape[0]))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(F32)
+
+
+def bin_probs(n: int, concentration: float = 0.3, seed: int = 0) -> np.ndarray:
+    """Random distributions over the 256 proposal bins, Dirichlet(concentration), f32."""
+    g = rng(CFG_PROPOSAL, 11, seed)
+    return g.dirichlet(np.full(256, concentration), size=n).astype(F32)
 
 
 def diff_step(seed: int = 0):
