@@ -187,7 +187,8 @@ sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps, const sop
  * --------------------------------------------------------------------------------------*/
 
 typedef enum sop_sampler {
-  SOP_SAMPLER_HAMMERSLEY = 0      /* uniform hemisphere Hammersley set (Eq. 7)              */
+  SOP_SAMPLER_HAMMERSLEY = 0,     /* uniform hemisphere Hammersley set (Eq. 7)              */
+  SOP_SAMPLER_PROPOSAL = 1        /* per-point bin distributions (learned proposal below)  */
 } sop_sampler;
 
 typedef struct sop_shade_opts {
@@ -198,9 +199,18 @@ typedef struct sop_shade_opts {
   int32_t  rotate_per_point;     /* 0: one rotation per call, 1: one per point            */
   int32_t  sampler;              /* sop_sampler                                           */
   float*   out_irradiance;       /* optional device [N,3]: (2pi/S) sum_j L_i cos(theta)   */
+  const float* probs;            /* SOP_SAMPLER_PROPOSAL: device [N,256] bin distributions
+                                    (one row per point, any non-negative weights; values
+                                    are clamped to [0,1], NaN counts as 0)                */
+  float    mix_eps;              /* SOP_SAMPLER_PROPOSAL: weight of the uniform-bin part of
+                                    the mixture, 0 <= mix_eps <= 1                         */
 } sop_shade_opts;
 
-/* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL. */
+/* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL.
+ * With SOP_SAMPLER_PROPOSAL the S directions of point i are drawn from its bin distribution
+ * (see "Learned direction proposal" below) and rgb_i = (1/S) sum_j f L_i cos / pdf(w_j);
+ * out_irradiance is then (1/S) sum_j L_i cos / pdf(w_j). The proposal sampler has no
+ * adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
                      const sop_points* pts, const sop_neighbors* nb,
                      const sop_shade_opts* opts, float* rgb,
@@ -224,7 +234,10 @@ typedef enum sop_op {
   SOP_OP_KNN = 0,
   SOP_OP_QUERY = 1,
   SOP_OP_SHADE = 2,
-  SOP_OP_SHADE_BACKWARD = 3
+  SOP_OP_SHADE_BACKWARD = 3,
+  SOP_OP_DUMP_INTEGRAND = 4,     /* sop_dump_integrand (sized by sop_workspace_size)        */
+  SOP_OP_PROPOSAL_INFER = 5,     /* sop_proposal_infer (sized by sop_proposal_workspace_size) */
+  SOP_OP_PROPOSAL_TRAIN = 6      /* sop_proposal_train_step (sop_proposal_workspace_size)   */
 } sop_op;
 
 /* Workspace bytes that `op` needs for n_points points with k neighbours, n_dirs directions
@@ -290,6 +303,88 @@ sop_status sop_bake_plan_destroy(sop_bake_plan* plan);
  * (R,G,B,O); depth: device [P,res,res] f32 or NULL. No workspace. */
 sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n_probes,
                     int32_t res, float* texels, float* depth, sop_stream stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Learned direction proposal: an extension of the Monte Carlo estimate of Eq. 7 (the paper
+ * uses a fixed Hammersley set; here the directions can instead be importance sampled from a
+ * per-point distribution that a small network predicts, trained on integrand samples that
+ * the shading step itself produces).
+ *
+ * Bins: the local hemisphere of the shading frame (the frame of the direction set above)
+ * is mapped to the square (u,v) = ((x+y), (x-y)) / (|x|+|y|+z) in [-1,1]^2, cut into 16x16
+ * cells; bin b = 16*row + col with col = floor((u+1)*8), row = floor((v+1)*8). Inside a
+ * cell the density is uniform in (u,v); in solid angle it is
+ *   pdf(w) = (c_b / C) * 128 / s^3,   s = |x| + |y| + z of the unit local direction.
+ * Masses: q_b = fmaf(1 - eps, clamp(p_b, 0, 1), eps/256) in IEEE single precision,
+ * c_b = floor(q_b * 2^24), C = sum_b c_b (all-zero masses fall back to c_b = 1).
+ * Draw j of S at point i: x_j = (j*C + ((r*C) >> 24)) / S in integer arithmetic with
+ * r = h(i,j,0); the bin is the smallest b with c_0 + ... + c_b > x_j; the position in the
+ * cell is ((h(i,j,1) + 0.5), (h(i,j,2) + 0.5)) / 2^24, where
+ * h(i,j,k) = pcg(pcg(pcg(seed) ^ i) ^ (4j + k)) >> 8 and pcg is the hash of the direction
+ * set above.
+ *
+ * Network: features are sin(pi f_l x) and cos(pi f_l x) (feature 32c + 2l and 32c + 2l + 1),
+ * f_l = 2^(l/2), l = 0..15, of the 10 scalars x = (2 (pos - lo)/(hi - lo) - 1, n, v, r);
+ * z1 = x W1 + b1, h1 = relu(z1), z2 = h1 W2 + b2, h2 = relu(z2), z3 = h2 W3 + b3,
+ * p = softmax(z3). Features, weights and hidden activations are rounded to bfloat16
+ * (round to nearest even) and multiplied on the matrix cores with FP32 accumulation;
+ * biases, logits and the softmax stay FP32.
+ * --------------------------------------------------------------------------------------*/
+#define SOP_MLP_FREQS 16
+#define SOP_MLP_IN 320
+#define SOP_MLP_HIDDEN 64
+#define SOP_MLP_BINS 256
+#define SOP_MLP_PARAMS 41344          /* W1[320][64] b1[64] W2[64][64] b2[64] W3[64][256] b3[256] */
+
+typedef struct sop_mlp {
+  float* params;                 /* device [SOP_MLP_PARAMS] f32, row-major W[in][out]; read by
+                                    inference, updated in place by a training step        */
+  float  bounds_lo[3];           /* host: scene box mapped to [-1,1]^3 for the features   */
+  float  bounds_hi[3];
+} sop_mlp;
+
+typedef struct sop_adam {
+  float   lr, beta1, beta2, eps;
+  int32_t step;                  /* 1-based index of this update (bias correction)        */
+} sop_adam;
+
+/* Workspace bytes of SOP_OP_PROPOSAL_INFER / SOP_OP_PROPOSAL_TRAIN for n_points points
+ * (0 on an invalid argument). */
+size_t sop_proposal_workspace_size(sop_op op, int64_t n_points);
+
+/* probs [N,256] (device f32, rows sum to 1) and optionally logits [N,256] (NULL to skip)
+ * of the proposal network for the points' position, normal, view and roughness. */
+sop_status sop_proposal_infer(const sop_mlp* mlp, const sop_points* pts, float* probs,
+                              float* logits, void* ws, size_t ws_bytes, sop_stream stream);
+
+/* One training step on a batch of B points with raw bin targets T [B,256] (device f32,
+ * non-negative; each row is normalised, a row summing to <= 0 counts as uniform):
+ * loss = mean_i sum_b -t_ib log p_ib, written to *loss (device f32). The gradient of the
+ * loss (in the parameter layout) is written to grad (device [SOP_MLP_PARAMS], may be NULL).
+ * When opt is not NULL the parameters are then updated in place by Adam with the state
+ * adam_m / adam_v (device [SOP_MLP_PARAMS] each). In the backward pass the output-side
+ * gradients are rounded to bfloat16 before they meet a weight or an activation. */
+sop_status sop_proposal_train_step(const sop_mlp* mlp, const sop_points* pts,
+                                   const float* targets, const sop_adam* opt, float* adam_m,
+                                   float* adam_v, float* loss, float* grad, void* ws,
+                                   size_t ws_bytes, sop_stream stream);
+
+/* Adam (Kingma & Ba 2015) on n parameters: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). All device f32. */
+sop_status sop_adam_update(float* params, float* adam_m, float* adam_v, const float* grad,
+                           int64_t n, const sop_adam* opt, sop_stream stream);
+
+/* Training targets of the proposal: T[i,b] = (1/(128 n)) sum_k lum(f L_i cos)(w_bk) / l_bk^3
+ * estimates the integral over bin b of the luminance (Rec. 709 weights) of the integrand of
+ * Eq. 6 at point i, with n = samples_per_bin directions placed in bin b's cell at
+ * ((h(i,j,1) + 0.5), (h(i,j,2) + 0.5)) / 2^24, j = b n + k, and l_bk the L2 norm of the
+ * (px,py,z) point of the direction. Uses opts->seed (and k/radius when nb is NULL);
+ * targets: device [N,256] f32. */
+sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_maps* maps,
+                              const sop_envmap* env, const sop_points* pts,
+                              const sop_neighbors* nb, const sop_shade_opts* opts,
+                              int32_t samples_per_bin, float* targets,
+                              void* ws, size_t ws_bytes, sop_stream stream);
 
 /* ----------------------------------------------------------------------------------------
  * Misc

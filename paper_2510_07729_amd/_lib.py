@@ -24,7 +24,9 @@ SOP_TEXEL_F32 = 0
 SOP_TEXEL_F16 = 1
 
 SOP_OP_KNN, SOP_OP_QUERY, SOP_OP_SHADE, SOP_OP_SHADE_BACKWARD = 0, 1, 2, 3
-SOP_SAMPLER_HAMMERSLEY = 0
+SOP_OP_DUMP_INTEGRAND, SOP_OP_PROPOSAL_INFER, SOP_OP_PROPOSAL_TRAIN = 4, 5, 6
+SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL = 0, 1
+SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
 
 
 class sop_probe_set(C.Structure):
@@ -52,7 +54,8 @@ class sop_neighbors(C.Structure):
 
 class sop_shade_opts(C.Structure):
     _fields_ = [("n_dirs", c_i32), ("k", c_i32), ("radius", c_f32), ("seed", c_u32),
-                ("rotate_per_point", c_i32), ("sampler", c_i32), ("out_irradiance", c_vp)]
+                ("rotate_per_point", c_i32), ("sampler", c_i32), ("out_irradiance", c_vp),
+                ("probs", c_vp), ("mix_eps", c_f32)]
 
 
 class sop_gaussians(C.Structure):
@@ -63,6 +66,15 @@ class sop_gaussians(C.Structure):
 class sop_bake_opts(C.Structure):
     _fields_ = [("t_min", c_f32), ("alpha_min", c_f32), ("alpha_max", c_f32), ("T_min", c_f32),
                 ("cell_scale", c_f32)]
+
+
+class sop_mlp(C.Structure):
+    _fields_ = [("params", c_vp), ("bounds_lo", c_f32 * 3), ("bounds_hi", c_f32 * 3)]
+
+
+class sop_adam(C.Structure):
+    _fields_ = [("lr", c_f32), ("beta1", c_f32), ("beta2", c_f32), ("eps", c_f32),
+                ("step", c_i32)]
 
 
 P = C.POINTER
@@ -88,6 +100,15 @@ SIGNATURES = {
     "sop_bake_plan_check": (c_i32, [c_vp, c_vp]),
     "sop_bake_plan_destroy": (c_i32, [c_vp]),
     "sop_bake": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "sop_proposal_workspace_size": (C.c_size_t, [c_i32, c_i64]),
+    "sop_proposal_infer": (c_i32, [P(sop_mlp), P(sop_points), c_vp, c_vp, c_vp, C.c_size_t,
+                                   c_vp]),
+    "sop_proposal_train_step": (c_i32, [P(sop_mlp), P(sop_points), c_vp, P(sop_adam), c_vp,
+                                        c_vp, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_adam_update": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, P(sop_adam), c_vp]),
+    "sop_dump_integrand": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
+                                   P(sop_neighbors), P(sop_shade_opts), c_i32, c_vp, c_vp,
+                                   C.c_size_t, c_vp]),
     "sop_status_string": (C.c_char_p, [c_i32]),
     "sop_last_error": (C.c_char_p, []),
     "sop_version": (c_i32, []),

@@ -232,7 +232,7 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     carve_knn(b, plan, N);
     return b.used;
   }
-  if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD) {
+  if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD || op == SOP_OP_DUMP_INTEGRAND) {
     (void)b.take<double4>((size_t)n_dirs);
     (void)b.take<double2>((size_t)env_w + 2);
     (void)b.take<double2>((size_t)env_h + 2);
@@ -328,7 +328,7 @@ extern "C" size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_
                                      int32_t k, int32_t n_dirs, int32_t env_height,
                                      int32_t env_width, int32_t with_neighbors) {
   if (!plan || n_points < 0 || k < 1 || k > SOP_MAX_K) return 0;
-  if (op < SOP_OP_KNN || op > SOP_OP_SHADE_BACKWARD) return 0;
+  if (op < SOP_OP_KNN || op > SOP_OP_DUMP_INTEGRAND) return 0;
   if (env_height < 0 || env_width < 0) return 0;
   size_t need = ws_needed(plan, op, n_points, k, with_neighbors != 0, n_dirs > 0 ? n_dirs : 1,
                           env_height, env_width);
@@ -446,7 +446,8 @@ namespace {
 
 sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
                           const sop_envmap* env, const sop_points* pts,
-                          const sop_neighbors* nb, const sop_shade_opts* o) {
+                          const sop_neighbors* nb, const sop_shade_opts* o,
+                          bool allow_proposal) {
   if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (!o) return fail(SOP_ERR_INVALID_ARGUMENT, "opts is NULL");
   sop_status st = validate_points(pts);
@@ -460,8 +461,16 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
   }
   if (o->n_dirs < 1 || o->n_dirs > SOP_MAX_DIRS)
     return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
-  if (o->sampler != SOP_SAMPLER_HAMMERSLEY)
+  if (o->sampler == SOP_SAMPLER_PROPOSAL) {
+    if (!allow_proposal)
+      return fail(SOP_ERR_UNSUPPORTED, "the proposal sampler has no adjoint");
+    if (pts->count > 0 && (!o->probs || !aligned(o->probs, 16)))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "probs is NULL or not 16-byte aligned");
+    if (!(o->mix_eps >= 0.0f && o->mix_eps <= 1.0f))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "mix_eps out of [0, 1]");
+  } else if (o->sampler != SOP_SAMPLER_HAMMERSLEY) {
     return fail(SOP_ERR_UNSUPPORTED, "unknown sampler");
+  }
   if (o->out_irradiance && !aligned(o->out_irradiance, 4))
     return fail(SOP_ERR_INVALID_ARGUMENT, "out_irradiance misaligned");
   return SOP_OK;
@@ -500,7 +509,7 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
                                 const sop_envmap* env, const sop_points* pts,
                                 const sop_neighbors* nb, const sop_shade_opts* opts,
                                 float* rgb, void* ws, size_t ws_bytes, sop_stream stream) {
-  sop_status st = validate_shade(plan, maps, env, pts, nb, opts);
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts, true);
   if (st != SOP_OK) return st;
   if (pts->count > 0 && (!rgb || !aligned(rgb, 4)))
     return fail(SOP_ERR_INVALID_ARGUMENT, "rgb is NULL or misaligned");
@@ -520,7 +529,44 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
-  SOP_HIP(sopk::launch_shade_fwd(a, kk, maps->format, s), "sop_shade");
+  if (opts->sampler == SOP_SAMPLER_PROPOSAL) {
+    a.probs = opts->probs;
+    a.mix_eps = opts->mix_eps;
+    SOP_HIP(sopk::launch_shade_prop(a, kk, maps->format, s), "sop_shade");
+  } else {
+    SOP_HIP(sopk::launch_shade_fwd(a, kk, maps->format, s), "sop_shade");
+  }
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_maps* maps,
+                                         const sop_envmap* env, const sop_points* pts,
+                                         const sop_neighbors* nb, const sop_shade_opts* opts,
+                                         int32_t samples_per_bin, float* targets, void* ws,
+                                         size_t ws_bytes, sop_stream stream) {
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts, true);
+  if (st != SOP_OK) return st;
+  if (samples_per_bin < 1 || samples_per_bin > 64)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "samples_per_bin out of [1, 64]");
+  if (pts->count > 0 && (!targets || !aligned(targets, 16)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "targets is NULL or not 16-byte aligned");
+  const int32_t k = nb ? nb->k : opts->k;
+  const size_t need = ws_needed(plan, SOP_OP_DUMP_INTEGRAND, pts->count, k, nb != nullptr,
+                                opts->n_dirs, env->height, env->width);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a = base_args(plan, maps, pts);
+  set_dirs(a, env, opts);
+  a.npb = samples_per_bin;
+  a.targets = targets;
+  int32_t kk;
+  Bump b{(char*)ws, 0, ws_bytes};
+  if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
+  if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
+                       &a.nb_w, &kk)) != SOP_OK)
+    return st;
+  SOP_HIP(sopk::launch_dump_integrand(a, kk, maps->format, s), "sop_dump_integrand");
   return SOP_OK;
 }
 
@@ -531,7 +577,7 @@ extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_m
                                          float* g_rough, float* g_metal, float* g_env,
                                          float* g_tex, void* ws, size_t ws_bytes,
                                          sop_stream stream) {
-  sop_status st = validate_shade(plan, maps, env, pts, nb, opts);
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts, false);
   if (st != SOP_OK) return st;
   if (pts->count > 0 && (!grad_rgb || !aligned(grad_rgb, 4)))
     return fail(SOP_ERR_INVALID_ARGUMENT, "grad_rgb is NULL or misaligned");
@@ -559,6 +605,182 @@ extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_m
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
   SOP_HIP(sopk::launch_shade_bwd(a, kk, maps->format, s), "sop_shade_backward");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// learned direction proposal: network inference, training step, Adam
+// ------------------------------------------------------------------------------------------
+namespace {
+
+sop_status validate_mlp(const sop_mlp* m) {
+  if (!m) return fail(SOP_ERR_INVALID_ARGUMENT, "mlp is NULL");
+  if (!m->params || !aligned(m->params, 16))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "mlp->params is NULL or not 16-byte aligned");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(m->bounds_lo[a]) || !std::isfinite(m->bounds_hi[a]) ||
+        !(m->bounds_hi[a] > m->bounds_lo[a]))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "mlp bounds must be finite with hi > lo");
+  return SOP_OK;
+}
+
+// the network reads position, normal, view (or camera) and roughness
+sop_status validate_mlp_points(const sop_points* pts) {
+  if (!pts) return fail(SOP_ERR_INVALID_ARGUMENT, "pts is NULL");
+  if (pts->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "pts->count < 0");
+  if (pts->count > INT32_MAX) return fail(SOP_ERR_UNSUPPORTED, "more than 2^31-1 points");
+  if (pts->count == 0) return SOP_OK;
+  const void* req[] = {pts->pos, pts->normal, pts->roughness};
+  for (const void* p : req)
+    if (!p || !aligned(p, 4))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "a point array is NULL or misaligned");
+  if (pts->view) {
+    if (!aligned(pts->view, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "view misaligned");
+  } else if (!pts->cam_pos || !aligned(pts->cam_pos, 4) || pts->points_per_frame < 1 ||
+             pts->n_frames < 1 ||
+             (int64_t)pts->n_frames * pts->points_per_frame != pts->count) {
+    return fail(SOP_ERR_INVALID_ARGUMENT,
+                "view is NULL: need cam_pos and n_frames * points_per_frame == count");
+  }
+  return SOP_OK;
+}
+
+sop_status validate_adam(const sop_adam* o) {
+  if (!(o->lr >= 0.0f) || !std::isfinite(o->lr) || !(o->beta1 >= 0.0f && o->beta1 < 1.0f) ||
+      !(o->beta2 >= 0.0f && o->beta2 < 1.0f) || !(o->eps > 0.0f) || !std::isfinite(o->eps) ||
+      o->step < 1)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "Adam options out of range");
+  return SOP_OK;
+}
+
+sopk::MlpArgs mlp_args(const sop_mlp* m, const sop_points* pts) {
+  sopk::MlpArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = pts->count;
+  a.pos = pts->pos;
+  a.nrm = pts->normal;
+  a.view = pts->view;
+  a.cam = pts->cam_pos;
+  a.ppf = pts->points_per_frame > 0 ? pts->points_per_frame : 1;
+  a.rough = pts->roughness;
+  for (int c = 0; c < 3; ++c) {
+    a.lo[c] = m->bounds_lo[c];
+    a.inv2[c] = 2.0f / (m->bounds_hi[c] - m->bounds_lo[c]);
+  }
+  a.params = m->params;
+  return a;
+}
+
+// Workspace: [weight fragments] then, for training, the transposed bf16 operands
+// x^T [320][B16], h1^T, h2^T, dz1^T, dz2^T [64][B16], dz3^T [256][B16] and a gradient buffer
+size_t proposal_ws(sop_op op, int64_t n) {
+  Bump b{nullptr, 0, 0};
+  (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+  if (op == SOP_OP_PROPOSAL_TRAIN) {
+    const size_t ld = (size_t)((n + 15) / 16) * 16;
+    (void)b.take<uint16_t>((size_t)SOP_MLP_IN * ld);
+    for (int i = 0; i < 4; ++i) (void)b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
+    (void)b.take<uint16_t>((size_t)SOP_MLP_BINS * ld);
+    (void)b.take<float>(SOP_MLP_PARAMS);
+  }
+  return b.used;
+}
+
+}  // namespace
+
+extern "C" size_t sop_proposal_workspace_size(sop_op op, int64_t n_points) {
+  if (n_points < 0 || n_points > INT32_MAX) return 0;
+  if (op != SOP_OP_PROPOSAL_INFER && op != SOP_OP_PROPOSAL_TRAIN) return 0;
+  return proposal_ws(op, n_points);
+}
+
+extern "C" sop_status sop_proposal_infer(const sop_mlp* mlp, const sop_points* pts,
+                                         float* probs, float* logits, void* ws,
+                                         size_t ws_bytes, sop_stream stream) {
+  sop_status st = validate_mlp(mlp);
+  if (st != SOP_OK) return st;
+  if ((st = validate_mlp_points(pts)) != SOP_OK) return st;
+  if (pts->count > 0 && (!probs || !aligned(probs, 16) || (logits && !aligned(logits, 16))))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "probs is NULL or probs/logits not 16-byte aligned");
+  if ((st = validate_ws(ws, ws_bytes, proposal_ws(SOP_OP_PROPOSAL_INFER, pts->count))) != SOP_OK)
+    return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  Bump b{(char*)ws, 0, ws_bytes};
+  uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+  sopk::MlpArgs a = mlp_args(mlp, pts);
+  a.frags = frags;
+  a.probs = probs;
+  a.logits = logits;
+  SOP_HIP(sopk::launch_mlp_frags(mlp->params, frags, s), "sop_proposal_infer");
+  SOP_HIP(sopk::launch_mlp_infer(a, s), "sop_proposal_infer");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_adam_update(float* params, float* adam_m, float* adam_v,
+                                      const float* grad, int64_t n, const sop_adam* opt,
+                                      sop_stream stream) {
+  if (!opt) return fail(SOP_ERR_INVALID_ARGUMENT, "opt is NULL");
+  if (n < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "n < 0");
+  sop_status st = validate_adam(opt);
+  if (st != SOP_OK) return st;
+  if (n == 0) return SOP_OK;
+  const void* req[] = {params, adam_m, adam_v, grad};
+  for (const void* p : req)
+    if (!p || !aligned(p, 4))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "an Adam array is NULL or misaligned");
+  const double ic1 = 1.0 / (1.0 - std::pow((double)opt->beta1, opt->step));
+  const double ic2 = 1.0 / (1.0 - std::pow((double)opt->beta2, opt->step));
+  SOP_HIP(sopk::launch_adam(params, adam_m, adam_v, grad, n, opt->lr, opt->beta1, opt->beta2,
+                            opt->eps, (float)ic1, (float)ic2, (hipStream_t)stream),
+          "sop_adam_update");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_proposal_train_step(const sop_mlp* mlp, const sop_points* pts,
+                                              const float* targets, const sop_adam* opt,
+                                              float* adam_m, float* adam_v, float* loss,
+                                              float* grad, void* ws, size_t ws_bytes,
+                                              sop_stream stream) {
+  sop_status st = validate_mlp(mlp);
+  if (st != SOP_OK) return st;
+  if ((st = validate_mlp_points(pts)) != SOP_OK) return st;
+  if (pts->count > 0 && (!targets || !aligned(targets, 16)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "targets is NULL or not 16-byte aligned");
+  if (!loss || !aligned(loss, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "loss is NULL or misaligned");
+  if (grad && !aligned(grad, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "grad misaligned");
+  if (opt) {
+    if ((st = validate_adam(opt)) != SOP_OK) return st;
+    if (!adam_m || !adam_v || !aligned(adam_m, 4) || !aligned(adam_v, 4))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "adam_m/adam_v NULL or misaligned");
+  }
+  if ((st = validate_ws(ws, ws_bytes, proposal_ws(SOP_OP_PROPOSAL_TRAIN, pts->count))) != SOP_OK)
+    return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  Bump b{(char*)ws, 0, ws_bytes};
+  sopk::MlpArgs a = mlp_args(mlp, pts);
+  const size_t ld = (size_t)((pts->count + 15) / 16) * 16;
+  uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+  a.frags = frags;
+  a.xT = b.take<uint16_t>((size_t)SOP_MLP_IN * ld);
+  a.h1T = b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
+  a.h2T = b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
+  a.dz1T = b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
+  a.dz2T = b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
+  a.dz3T = b.take<uint16_t>((size_t)SOP_MLP_BINS * ld);
+  float* ws_grad = b.take<float>(SOP_MLP_PARAMS);
+  a.ldT = (int64_t)ld;
+  a.targets = targets;
+  a.loss = loss;
+  a.grad = grad ? grad : ws_grad;
+  SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(a.grad), 0, SOP_MLP_PARAMS, s),
+          "sop_proposal_train_step");
+  SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(loss), 0, 1, s),
+          "sop_proposal_train_step");
+  SOP_HIP(sopk::launch_mlp_frags(mlp->params, frags, s), "sop_proposal_train_step");
+  SOP_HIP(sopk::launch_mlp_train(a, s), "sop_proposal_train_step");
+  if (opt) return sop_adam_update(mlp->params, adam_m, adam_v, a.grad, SOP_MLP_PARAMS, opt, stream);
   return SOP_OK;
 }
 

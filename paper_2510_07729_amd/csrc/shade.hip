@@ -114,16 +114,10 @@ struct Sample {
   float O;
 };
 
+// environment and probe fetches of a sample whose direction (w64, w, ct) is set
 template <int KT, typename TexT>
-__device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState& ps,
-                                            const Neighbors<KT>& nb, int32_t k, int j,
-                                            Sample& s) {
-  const double4 e = a.dir_tab[j];
-  const double da = e.x * ps.cr - e.y * ps.sr;
-  const double db = e.x * ps.sr + e.y * ps.cr;
-  world_dir64(ps.F, da, db, e.z, s.w64);
-  s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
-  s.ct = (float)e.z;
+__device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps,
+                                        const Neighbors<KT>& nb, int32_t k, Sample& s) {
   s.et = env_taps64(s.w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
   s.Le[0] = s.Le[1] = s.Le[2] = 0.0f;
 #pragma unroll
@@ -155,6 +149,19 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
       s.O += c * x.w;
     }
   }
+}
+
+template <int KT, typename TexT>
+__device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState& ps,
+                                            const Neighbors<KT>& nb, int32_t k, int j,
+                                            Sample& s) {
+  const double4 e = a.dir_tab[j];
+  const double da = e.x * ps.cr - e.y * ps.sr;
+  const double db = e.x * ps.sr + e.y * ps.cr;
+  world_dir64(ps.F, da, db, e.z, s.w64);
+  s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+  s.ct = (float)e.z;
+  eval_at<KT, TexT>(a, ps, nb, k, s);
 }
 
 template <int KT, typename TexT>
@@ -200,6 +207,208 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
       a.irr[3 * ps.p + 2] = r[2];
     }
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Learned direction proposal: importance-sampled estimate of Eq. 7. Directions are drawn
+// from 16x16 bins over the hemispherical octahedral square of the local frame,
+// (u,v) = (x+y, x-y)/(|x|+|y|+z), with integer bin masses (decided in IEEE single
+// precision, so every bin choice is exact), and each sample is weighted by 1/pdf,
+// pdf = (c_b / C) * 128 * l^3 with l = |(px,py,z)|.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hash24(uint32_t seed_h, uint32_t i, uint32_t j, uint32_t k) {
+  return pcg_hash(pcg_hash(seed_h ^ i) ^ (4u * j + k)) >> 8;
+}
+
+// unit local direction of square point (u,v); returns l = |(px, py, z)|
+__device__ __forceinline__ double bin_dir(double u, double v, double wl[3]) {
+  const double px = 0.5 * (u + v), py = 0.5 * (u - v);
+  const double z = 1.0 - fabs(px) - fabs(py);
+  const double l = sqrt(fma(px, px, fma(py, py, z * z)));
+  const double il = 1.0 / l;
+  wl[0] = px * il;
+  wl[1] = py * il;
+  wl[2] = z * il;
+  return l;
+}
+
+// position of draw j inside bin b (streams 1 and 2 of the point's generator)
+__device__ __forceinline__ double cell_point(uint32_t seed_h, uint32_t i, uint32_t j, int b,
+                                             double wl[3]) {
+  const double xu = ((double)hash24(seed_h, i, j, 1) + 0.5) * 0x1p-24;
+  const double xv = ((double)hash24(seed_h, i, j, 2) + 0.5) * 0x1p-24;
+  const double u = -1.0 + ((double)(b & 15) + xu) * 0.125;
+  const double v = -1.0 + ((double)(b >> 4) + xv) * 0.125;
+  return bin_dir(u, v, wl);
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+  const uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// cumulative integer masses cum[0..256] of the point's bins into the wave's LDS row
+__device__ __forceinline__ uint64_t bin_masses(const ShadeArgs& a, int64_t p, int lane,
+                                               uint64_t* cum) {
+  const float4 pr = *reinterpret_cast<const float4*>(a.probs + (size_t)p * SOP_MLP_BINS + 4 * lane);
+  const float om = 1.0f - a.mix_eps, add = a.mix_eps * (1.0f / 256.0f);
+  const float pv[4] = {pr.x, pr.y, pr.z, pr.w};
+  uint32_t c[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float q = pv[t];
+    q = q > 0.0f ? fminf(q, 1.0f) : 0.0f;                  // NaN and negatives count as 0
+    c[t] = (uint32_t)floorf(__builtin_fmaf(om, q, add) * 16777216.0f);
+  }
+  uint64_t own = (uint64_t)c[0] + c[1] + c[2] + c[3];
+  uint64_t incl = own;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t o = shfl_up_u64(incl, d);
+    if (lane >= d) incl += o;
+  }
+  uint64_t total = shfl_u64(incl, 63);
+  if (total == 0) {                                         // nothing to sample: one unit per bin
+    c[0] = c[1] = c[2] = c[3] = 1;
+    incl = 4 * (uint64_t)(lane + 1);
+    own = 4;
+    total = 256;
+  }
+  uint64_t run = incl - own;
+  if (lane == 0) cum[0] = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    run += c[t];
+    cum[4 * lane + t + 1] = run;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return total;
+}
+
+// bin of mass coordinate x < total: the largest b with cum[b] <= x
+__device__ __forceinline__ int find_bin(const uint64_t* cum, uint64_t x) {
+  int b = 0;
+#pragma unroll
+  for (int step = 128; step >= 1; step >>= 1)
+    if (cum[b + step] <= x) b += step;
+  return b;
+}
+
+template <int KT, typename TexT>
+__global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
+  __shared__ uint64_t s_cum[kWavesPerBlock][SOP_MLP_BINS + 1];
+  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  if (wv >= a.n) return;
+  const int lane = threadIdx.x & 63;
+  uint64_t* cum = s_cum[threadIdx.x >> 6];
+  PointState ps;
+  if (!load_point(a, wv, ps)) return;
+  Neighbors<KT> nb;
+  nb.load(a, ps.p, k);
+  const uint64_t total = bin_masses(a, ps.p, lane, cum);
+  const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+  const double inv_total = 1.0 / (double)total;
+
+  float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
+  for (int j0 = 0; j0 < a.S; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < a.S) {
+      const uint64_t r = hash24(sh, pi, (uint32_t)j, 0);
+      const uint64_t x = ((uint64_t)j * total + ((r * total) >> 24)) / (uint64_t)a.S;
+      const int b = find_bin(cum, x);
+      const uint64_t cb = cum[b + 1] - cum[b];
+      double wl[3];
+      const double l = cell_point(sh, pi, (uint32_t)j, b, wl);
+      const float inv_pdf = (float)(1.0 / ((double)cb * inv_total * 128.0 * l * l * l));
+      Sample s;
+      world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
+      s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+      s.ct = (float)wl[2];
+      eval_at<KT, TexT>(a, ps, nb, k, s);
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+      const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+        acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li * inv_pdf;
+        acc_e[c] += Li * s.ct * inv_pdf;
+      }
+    }
+  }
+  const float scale = 1.0f / (float)a.S;
+  float r3[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r3[c] = wave_sum(acc[c]) * scale;
+  if (lane == 0) {
+    a.rgb[3 * ps.p] = r3[0];
+    a.rgb[3 * ps.p + 1] = r3[1];
+    a.rgb[3 * ps.p + 2] = r3[2];
+  }
+  if (a.irr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r3[c] = wave_sum(acc_e[c]) * scale;
+    if (lane == 0) {
+      a.irr[3 * ps.p] = r3[0];
+      a.irr[3 * ps.p + 1] = r3[1];
+      a.irr[3 * ps.p + 2] = r3[2];
+    }
+  }
+}
+
+// Training targets of the proposal: T[i][b] = (1/(128 n)) sum_k lum(f L_i cos) / l^3 over n
+// draws placed in bin b's cell (draw j = b n + k), summed per bin in the wave's LDS row.
+template <int KT, typename TexT>
+__global__ __launch_bounds__(256) void k_dump_integrand(ShadeArgs a, int32_t k) {
+  __shared__ float s_acc[kWavesPerBlock][SOP_MLP_BINS];
+  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  if (wv >= a.n) return;
+  const int lane = threadIdx.x & 63;
+  float* accb = s_acc[threadIdx.x >> 6];
+  PointState ps;
+  if (!load_point(a, wv, ps)) return;
+  Neighbors<KT> nb;
+  nb.load(a, ps.p, k);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) accb[4 * lane + t] = 0.0f;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+  const int npb = a.npb, total = SOP_MLP_BINS * npb;
+  const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+  for (int j0 = 0; j0 < total; j0 += 64) {
+    const int j = j0 + lane;
+    if (j < total) {
+      const int b = j / npb;
+      double wl[3];
+      const double l = cell_point(sh, pi, (uint32_t)j, b, wl);
+      Sample s;
+      world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
+      s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+      s.ct = (float)wl[2];
+      eval_at<KT, TexT>(a, ps, nb, k, s);
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+      float y[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        y[c] = fcos(ps.M, bt, al[c], s.ct) * ((1.0f - s.O) * s.Le[c] + s.Lin[c]);
+      const float lum = 0.2126f * y[0] + 0.7152f * y[1] + 0.0722f * y[2];
+      atomicAdd(accb + b, lum * (float)(1.0 / (l * l * l)));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const float sc = 1.0f / (128.0f * (float)npb);
+  const float4 v = make_float4(accb[4 * lane] * sc, accb[4 * lane + 1] * sc,
+                               accb[4 * lane + 2] * sc, accb[4 * lane + 3] * sc);
+  *reinterpret_cast<float4*>(a.targets + (size_t)ps.p * SOP_MLP_BINS + 4 * lane) = v;
 }
 
 // Adjoint of one sample. With g the upstream gradient of the point and s = 2 pi / S:
@@ -506,6 +715,41 @@ __global__ __launch_bounds__(256) void k_query(ShadeArgs a, int32_t k, const flo
   Lin[3 * t + 1] = L1;
   Lin[3 * t + 2] = L2;
   O[t] = oc;
+}
+
+template <int KT>
+static void launch_prop_kt(int mode, const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
+                           hipStream_t s) {
+  if (mode == 0) {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_prop<KT, uint2>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_prop<KT, float4>), grid, dim3(256), 0, s, a, k);
+  } else {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_dump_integrand<KT, uint2>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_dump_integrand<KT, float4>), grid, dim3(256), 0, s, a, k);
+  }
+}
+
+static hipError_t dispatch_prop(int mode, const ShadeArgs& a, int32_t k, int32_t format,
+                                hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((a.n + kWavesPerBlock - 1) / kWavesPerBlock));
+  switch (k) {
+    case 4: launch_prop_kt<4>(mode, a, k, format, grid, s); break;
+    case 8: launch_prop_kt<8>(mode, a, k, format, grid, s); break;
+    default: launch_prop_kt<0>(mode, a, k, format, grid, s); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  return dispatch_prop(0, a, k, format, s);
+}
+hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  return dispatch_prop(1, a, k, format, s);
 }
 
 template <int KT>

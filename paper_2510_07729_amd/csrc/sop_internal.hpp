@@ -84,6 +84,11 @@ struct ShadeArgs {
   int32_t per_point;
   float* rgb;
   float* irr;
+  // learned proposal sampler / training targets
+  const float* probs;       // [n,256] bin distributions
+  float mix_eps;
+  float* targets;           // [n,256] bin integrals (integrand dump)
+  int32_t npb;              // draws per bin (integrand dump)
   // adjoint
   const float* grad;
   float* g_albedo;
@@ -93,11 +98,41 @@ struct ShadeArgs {
   float* g_tex;
 };
 
+// learned proposal network (proposal.hip)
+struct MlpArgs {
+  int64_t n;                 // points (inference) or batch size (training)
+  const float* pos;
+  const float* nrm;
+  const float* view;         // or NULL: camera mode
+  const float* cam;
+  int64_t ppf;
+  const float* rough;
+  float lo[3], inv2[3];      // features: (pos - lo) * inv2 - 1, inv2 = 2 / (hi - lo)
+  const float* params;       // [SOP_MLP_PARAMS] f32
+  const uint16_t* frags;     // bf16 operand fragments of the weights
+  float* probs;              // inference outputs [n,256]
+  float* logits;
+  // training
+  const float* targets;      // [n,256]
+  float* loss;               // [1] (accumulated; zeroed by the caller)
+  float* grad;               // [SOP_MLP_PARAMS] (bias part accumulated; zeroed by the caller)
+  uint16_t *xT, *h1T, *h2T, *dz1T, *dz2T, *dz3T;   // [rows][ldT] bf16, transposed operands
+  int64_t ldT;               // batch rounded up to 16
+};
+size_t mlp_frag_bytes();
+hipError_t launch_mlp_frags(const float* params, uint16_t* frags, hipStream_t s);
+hipError_t launch_mlp_infer(const MlpArgs& a, hipStream_t s);
+hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s);
+hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, float lr,
+                       float b1, float b2, float eps, float ic1, float ic2, hipStream_t s);
+
 // per-call direction table: dir_entry(j, S, rho) with rho of the call (0 when per point)
 hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,
                             double4* tab, double2* col_ref, double2* row_ref, hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
                         int32_t D, float* Lin, float* O, hipStream_t s);
 

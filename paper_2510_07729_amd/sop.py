@@ -196,12 +196,15 @@ def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
 
 
 def shade_opts(n_dirs: int, k: int, seed: int = 0, radius: float = math.inf,
-               rotate_per_point: bool = False, irradiance: Optional[torch.Tensor] = None):
+               rotate_per_point: bool = False, irradiance: Optional[torch.Tensor] = None,
+               probs: Optional[torch.Tensor] = None, mix_eps: float = 0.1):
     o = L.sop_shade_opts()
     o.n_dirs, o.k, o.radius, o.seed = int(n_dirs), int(k), float(radius), int(seed) & 0xFFFFFFFF
     o.rotate_per_point = int(rotate_per_point)
-    o.sampler = L.SOP_SAMPLER_HAMMERSLEY
+    o.sampler = L.SOP_SAMPLER_HAMMERSLEY if probs is None else L.SOP_SAMPLER_PROPOSAL
     o.out_irradiance = _ptr(irradiance, torch.float32, "irradiance")
+    o.probs = _ptr(probs, torch.float32, "probs")
+    o.mix_eps = float(mix_eps)
     return o
 
 
@@ -209,8 +212,10 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
               k: int = 4, nb: Optional[Neighbors] = None, seed: int = 0,
               radius: float = math.inf, rotate_per_point: bool = False,
               irradiance: bool = False, ws: Optional[torch.Tensor] = None,
-              out: Optional[torch.Tensor] = None):
-    """Forward shading: rgb [N,3] (and irradiance [N,3] when asked)."""
+              out: Optional[torch.Tensor] = None, probs: Optional[torch.Tensor] = None,
+              mix_eps: float = 0.1):
+    """Forward shading: rgb [N,3] (and irradiance [N,3] when asked). With probs [N,256] the
+    directions are drawn from those bin distributions (mixed with mix_eps of uniform bins)."""
     dev = pts.pos.device
     n = pts.n
     rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -219,7 +224,7 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
     if ws is None:
         ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, env.shape[:2],
                                            nb is not None), dev)
-    o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr)
+    o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr, probs, mix_eps)
     m, e, cp = _maps(texels), _env(env), pts.c()
     nbc = nb.c() if nb is not None else None
     L.check(plan._lib.sop_shade(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
@@ -269,6 +274,114 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
         _ptr(out.get("env")), _ptr(out.get("tex")), ws.data_ptr(), ws.numel(), _stream()),
         "sop_shade_backward")
     return out
+
+
+# ------------------------------------------------------------------------------------------
+# learned direction proposal
+# ------------------------------------------------------------------------------------------
+def sop_dump_integrand(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points,
+                       samples_per_bin: int, k: int = 4, nb: Optional[Neighbors] = None,
+                       seed: int = 0, radius: float = math.inf,
+                       out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Training targets [N,256]: per-bin integrals of the luminance of f L_i cos."""
+    dev = pts.pos.device
+    n = pts.n
+    T = out if out is not None else torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32,
+                                                device=dev)
+    kk = nb.k if nb is not None else k
+    if ws is None:
+        ws = workspace(plan.workspace_size(L.SOP_OP_DUMP_INTEGRAND, n, kk, 1, env.shape[:2],
+                                           nb is not None), dev)
+    o = shade_opts(1, kk, seed, radius)
+    m, e, cp = _maps(texels), _env(env), pts.c()
+    nbc = nb.c() if nb is not None else None
+    L.check(plan._lib.sop_dump_integrand(
+        plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+        C.byref(nbc) if nbc is not None else None, C.byref(o), int(samples_per_bin),
+        _ptr(T, torch.float32, "targets"), ws.data_ptr(), ws.numel(), _stream()),
+        "sop_dump_integrand")
+    return T
+
+
+class Mlp:
+    """Proposal network parameters (f32 [41344] on the GPU) with the scene box of its
+    position features, and optional Adam state."""
+
+    def __init__(self, params: torch.Tensor, bounds_lo, bounds_hi):
+        if params.numel() != L.SOP_MLP_PARAMS:
+            raise ValueError(f"params must have {L.SOP_MLP_PARAMS} entries")
+        self.params = params
+        self.lo = [float(x) for x in bounds_lo]
+        self.hi = [float(x) for x in bounds_hi]
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        self._lib = L.load()
+
+    def c(self) -> L.sop_mlp:
+        m = L.sop_mlp()
+        m.params = _ptr(self.params, torch.float32, "params")
+        m.bounds_lo = (C.c_float * 3)(*self.lo)
+        m.bounds_hi = (C.c_float * 3)(*self.hi)
+        return m
+
+
+def proposal_workspace(op: int, n: int, device) -> torch.Tensor:
+    return workspace(L.load().sop_proposal_workspace_size(op, int(n)), device)
+
+
+def sop_proposal_infer(mlp: Mlp, pts: Points, logits: bool = False,
+                       ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+    """probs [N,256] (and logits [N,256] when asked)."""
+    dev = pts.pos.device
+    n = pts.n
+    probs = out if out is not None else torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32,
+                                                    device=dev)
+    lg = torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32, device=dev) if logits else None
+    if ws is None:
+        ws = proposal_workspace(L.SOP_OP_PROPOSAL_INFER, n, dev)
+    mc, cp = mlp.c(), pts.c()
+    L.check(mlp._lib.sop_proposal_infer(C.byref(mc), C.byref(cp), _ptr(probs, torch.float32),
+                                        _ptr(lg, torch.float32), ws.data_ptr(), ws.numel(),
+                                        _stream()), "sop_proposal_infer")
+    return (probs, lg) if logits else probs
+
+
+def adam_opts(lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8) -> L.sop_adam:
+    return L.sop_adam(float(lr), float(beta1), float(beta2), float(eps), int(step))
+
+
+def sop_proposal_train_step(mlp: Mlp, pts: Points, targets: torch.Tensor,
+                            lr: Optional[float] = None, grad: Optional[torch.Tensor] = None,
+                            loss: Optional[torch.Tensor] = None,
+                            ws: Optional[torch.Tensor] = None, **adam_kw):
+    """One step: returns the batch loss (device scalar tensor). With lr the parameters are
+    updated by Adam (mlp.step advances); with grad the batch gradient is written there."""
+    dev = pts.pos.device
+    lo = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = proposal_workspace(L.SOP_OP_PROPOSAL_TRAIN, pts.n, dev)
+    opt = None
+    if lr is not None:
+        mlp.step += 1
+        opt = adam_opts(lr, mlp.step, **adam_kw)
+    mc, cp = mlp.c(), pts.c()
+    L.check(mlp._lib.sop_proposal_train_step(
+        C.byref(mc), C.byref(cp), _ptr(targets.contiguous(), torch.float32, "targets"),
+        C.byref(opt) if opt is not None else None, _ptr(mlp.m), _ptr(mlp.v),
+        _ptr(lo, torch.float32), _ptr(grad, torch.float32, "grad"), ws.data_ptr(), ws.numel(),
+        _stream()), "sop_proposal_train_step")
+    return lo
+
+
+def sop_adam_update(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                    grad: torch.Tensor, lr: float, step: int, **adam_kw) -> None:
+    opt = adam_opts(lr, step, **adam_kw)
+    L.check(L.load().sop_adam_update(_ptr(params, torch.float32), _ptr(m, torch.float32),
+                                     _ptr(v, torch.float32), _ptr(grad, torch.float32),
+                                     params.numel(), C.byref(opt), _stream()),
+            "sop_adam_update")
 
 
 # ------------------------------------------------------------------------------------------

@@ -1,0 +1,224 @@
+"""GPU parity of the learned direction proposal against the oracle, through the C ABI:
+network inference (BF16 matrix cores, FP32 accumulation) against the oracle's network that
+rounds the same operands to bfloat16, the training step's loss and gradient, Adam, the
+proposal-sampled shading (bin choices are exact integer decisions on both sides) and the
+training-target dump."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_07729_amd import scenes
+from tests.gpu_util import (TOL, dev, gpu_plan, gpu_points, log, oracle_knn, parity_err,
+                            report, sum_err)
+
+pytestmark = pytest.mark.gpu
+
+OFF = oracle.mlp_offsets()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def sop():
+    from paper_2510_07729_amd import sop as s
+    return s
+
+
+def eval_scene(n, seed=0):
+    return scenes.proposal_eval(n_points=n, seed=seed)
+
+
+def gpu_mlp(params, sc):
+    return sop().Mlp(dev(params), sc.bounds_lo, sc.bounds_hi)
+
+
+def logit_mass(params, sc, rows):
+    """sum_k |h2_k W3_kb| + |b3_b| per logit (oracle activations): the scale of a logit's
+    rounding error."""
+    W3 = params[OFF["W3"]].astype(np.float64).reshape(64, 256)
+    b3 = params[OFF["b3"]].astype(np.float64)
+    out = []
+    for i in rows:
+        f = oracle.pe_features(sc.pos[i], sc.normal[i], sc.view[i], sc.rough[i], sc.bounds_lo,
+                               sc.bounds_hi)
+        h2 = oracle.mlp_forward(params.astype(np.float64), f)["h2"]
+        out.append(np.abs(h2) @ np.abs(np.array([[oracle.bf16(x) for x in row] for row in W3]))
+                   + np.abs(b3))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n", [1000, 1, 17])
+def test_infer_matches_bf16_oracle(torch_gpu, n):
+    log(f"proposal inference: {n} points")
+    sc = eval_scene(max(n, 1))
+    params = scenes.mlp_init(seed=3)
+    params[OFF["b1"]] = 0.1
+    params[OFF["b3"]] = np.linspace(-1, 1, 256)
+    mlp = gpu_mlp(params, sc)
+    probs, logits = sop().sop_proposal_infer(mlp, gpu_points(sc), logits=True)
+    torch_gpu.cuda.synchronize()
+    lg, pg = logits.cpu().numpy(), probs.cpu().numpy()
+    lo, po = oracle.mlp_infer(params.astype(np.float64), sc.pos, sc.normal, sc.view, sc.rough,
+                              sc.bounds_lo, sc.bounds_hi, emulate_bf16=True)
+    rows = np.arange(min(n, 64))
+    mass = logit_mass(params, sc, rows)
+    rel = np.abs(lg[rows] - lo[rows]) / mass
+    log(f"logits: max |d|/mass {rel.max():.3e}  p99.9 {np.percentile(rel, 99.9):.3e}; "
+        f"max |d| all rows {np.abs(lg - lo).max():.3e}")
+    # one bfloat16 step (2^-8 relative) of an operand moves a logit by far less than its
+    # mass; FP32 vs FP64 accumulation adds ~1e-7 of it
+    assert np.percentile(rel, 99.9) <= 2.0 ** -8 and rel.max() <= 2.0 ** -6
+    dq = np.abs(pg - po)
+    bound = 2.0 * po * np.abs(lg - lo).max(axis=1, keepdims=True) + 1e-7
+    assert np.all(dq <= bound)
+    assert np.allclose(pg.sum(1), 1.0, atol=1e-5)
+
+
+def test_infer_empty(torch_gpu):
+    sc = eval_scene(4)
+    mlp = gpu_mlp(scenes.mlp_init(), sc)
+    pts = gpu_points(sc)
+    import dataclasses
+    pts0 = dataclasses.replace(pts, pos=pts.pos[:0], normal=pts.normal[:0],
+                               albedo=pts.albedo[:0], rough=pts.rough[:0], metal=pts.metal[:0],
+                               view=pts.view[:0])
+    out = sop().sop_proposal_infer(mlp, pts0)
+    assert out.shape == (0, 256)
+
+
+def batch(B, seed=2):
+    sc = eval_scene(B, seed=seed)
+    rng = np.random.default_rng(seed)
+    T = (rng.uniform(0, 1, (B, 256)) ** 3).astype(np.float32)
+    T[::7] = 0.0                                  # rows without signal count as uniform
+    return sc, T
+
+
+@pytest.mark.parametrize("B", [300, 4096])
+def test_train_gradient_matches_oracle(torch_gpu, B):
+    log(f"proposal training gradient: batch {B}")
+    import torch
+    sc, T = batch(B)
+    params = scenes.mlp_init(seed=4)
+    params[OFF["b1"]] = 0.05
+    params[OFF["b2"]] = 0.05
+    mlp = gpu_mlp(params, sc)
+    grad = torch.empty(params.size, dtype=torch.float32, device="cuda")
+    loss = sop().sop_proposal_train_step(mlp, gpu_points(sc), dev(T), grad=grad)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    lo, go = oracle.mlp_loss_grad(params.astype(np.float64), sc.pos, sc.normal, sc.view,
+                                  sc.rough, sc.bounds_lo, sc.bounds_hi, T, emulate_bf16=True)
+    lg = float(loss.item())
+    log(f"loss gpu {lg:.7f} oracle {lo:.7f}")
+    assert abs(lg - lo) <= 1e-4 * abs(lo)
+    for name, sl in OFF.items():
+        e = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        log(f"grad {name}: relative L2 error {e:.3e}")
+        assert e <= 1e-2, name
+    # parameters untouched without an optimiser
+    assert np.array_equal(mlp.params.cpu().numpy(), params)
+
+
+def test_adam_matches_oracle(torch_gpu):
+    log("Adam update")
+    import torch
+    rng = np.random.default_rng(9)
+    n = 41344
+    p = rng.standard_normal(n).astype(np.float32)
+    m = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    v = (rng.uniform(0, 1e-6, n)).astype(np.float32)
+    g = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    tp, tm, tv = dev(p), dev(m), dev(v)
+    sop().sop_adam_update(tp, tm, tv, dev(g), 3e-3, 5)
+    torch.cuda.synchronize()
+    po, mo, vo = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    oracle.adam(po, mo, vo, g.astype(np.float64), 3e-3, 0.9, 0.999, 1e-8, 5)
+    # m and v are two-term sums that can cancel: measure against the sum of |terms|
+    m_mass = 0.9 * np.abs(m.astype(np.float64)) + 0.1 * np.abs(g.astype(np.float64))
+    v_mass = 0.999 * v.astype(np.float64) + 0.001 * g.astype(np.float64) ** 2
+    assert report("adam m", sum_err(tm.cpu().numpy(), mo, m_mass)) <= 1e-6
+    assert report("adam v", sum_err(tv.cpu().numpy(), vo, v_mass)) <= 1e-6
+    step_gpu = tp.cpu().numpy() - p
+    step_orc = po - p
+    assert np.max(np.abs(step_gpu - step_orc)) <= 1e-4 * 3e-3 + 1e-6
+
+
+def test_train_step_moves_like_oracle(torch_gpu):
+    log("one training step with Adam")
+    import torch
+    sc, T = batch(512, seed=5)
+    params = scenes.mlp_init(seed=6)
+    mlp = gpu_mlp(params, sc)
+    sop().sop_proposal_train_step(mlp, gpu_points(sc), dev(T), lr=1e-3)
+    torch.cuda.synchronize()
+    _, go = oracle.mlp_loss_grad(params.astype(np.float64), sc.pos, sc.normal, sc.view,
+                                 sc.rough, sc.bounds_lo, sc.bounds_hi, T, emulate_bf16=True)
+    po = params.astype(np.float64)
+    oracle.adam(po, np.zeros_like(po), np.zeros_like(po), go, 1e-3, 0.9, 0.999, 1e-8, 1)
+    d_gpu = mlp.params.cpu().numpy() - params
+    d_orc = po - params
+    close = np.abs(d_gpu - d_orc) <= 0.05 * 1e-3
+    log(f"first Adam step: {close.mean() * 100:.3f}% of parameters agree to 5% of lr")
+    # step 1 of Adam is lr * g / (|g| + eps): only gradients within rounding of zero may
+    # land on the other side
+    assert close.mean() >= 0.995
+
+
+# ------------------------------------------------------------------------------------------
+# proposal-sampled shading and the training targets
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("S,eps,kind", [(32, 0.1, "dirichlet"), (100, 0.1, "dirichlet"),
+                                        (64, 1.0, "dirichlet"), (16, 0.0, "onehot"),
+                                        (8, 0.0, "nan")])
+def test_proposal_shade_matches_oracle(torch_gpu, S, eps, kind):
+    log(f"proposal shading S={S} eps={eps} probs={kind}")
+    import torch
+    sc = scenes.tiny_shade(n_points=512)
+    idx, w = oracle_knn(sc)
+    if kind == "dirichlet":
+        probs = scenes.bin_probs(sc.n, concentration=0.3, seed=S)
+    elif kind == "onehot":
+        probs = np.zeros((sc.n, 256), np.float32)
+        probs[np.arange(sc.n), np.arange(sc.n) % 256] = 1.0
+    else:
+        probs = np.full((sc.n, 256), np.nan, np.float32)
+    ref, ref_e = oracle.prop_shade(sc, idx, w, probs, eps, S, 77, irradiance=True)
+    plan = gpu_plan(sc)
+    rgb, irr = sop().sop_shade(plan, dev(sc.texels), dev(sc.env), gpu_points(sc), S, k=sc.k,
+                               seed=77, irradiance=True, probs=dev(probs), mix_eps=eps)
+    torch.cuda.synchronize()
+    assert report("proposal rgb", parity_err(rgb.cpu().numpy(), ref)) <= TOL
+    assert report("proposal irradiance", parity_err(irr.cpu().numpy(), ref_e)) <= TOL
+
+
+def test_proposal_sampler_rejected_by_backward(torch_gpu):
+    sc = scenes.tiny_shade(n_points=16)
+    plan = gpu_plan(sc)
+    probs = dev(scenes.bin_probs(sc.n))
+    o = sop().shade_opts(16, 4, probs=probs)
+    import ctypes as C
+    from paper_2510_07729_amd import _lib as L
+    m, e, cp = sop()._maps(dev(sc.texels)), sop()._env(dev(sc.env)), gpu_points(sc).c()
+    st = plan._lib.sop_shade_backward(plan.handle, C.byref(m), C.byref(e), C.byref(cp), None,
+                                      C.byref(o), 16, None, None, None, None, None, None, 0,
+                                      None)
+    assert st == L.SOP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("npb", [2, 3])
+def test_dump_integrand_matches_oracle(torch_gpu, npb):
+    log(f"integrand dump, {npb} draws per bin")
+    import torch
+    sc = scenes.tiny_shade(n_points=256)
+    idx, w = oracle_knn(sc)
+    ref = oracle.dump_integrand(sc, idx, w, npb, 13)
+    plan = gpu_plan(sc)
+    T = sop().sop_dump_integrand(plan, dev(sc.texels), dev(sc.env), gpu_points(sc), npb,
+                                 k=sc.k, seed=13)
+    torch.cuda.synchronize()
+    assert report("bin targets", parity_err(T.cpu().numpy(), ref)) <= TOL
