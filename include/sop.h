@@ -318,8 +318,10 @@ sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n
  * Masses: q_b = fmaf(1 - eps, clamp(p_b, 0, 1), eps/256) in IEEE single precision,
  * c_b = floor(q_b * 2^24), C = sum_b c_b (all-zero masses fall back to c_b = 1).
  * Draw j of S at point i: x_j = (j*C + ((r*C) >> 24)) / S in integer arithmetic with
- * r = h(i,j,0); the bin is the smallest b with c_0 + ... + c_b > x_j; the position in the
- * cell is ((h(i,j,1) + 0.5), (h(i,j,2) + 0.5)) / 2^24, where
+ * r = h(i,j,0); the bin is the smallest b with C_b + c_b > x_j (C_b = c_0 + ... + c_{b-1});
+ * the position in the cell is u = (x_j - C_b + 0.5) / c_b (the draw's place on the bin's
+ * stretch of the mass line) and v = ((((bitreverse32(j) >> 8) + h(i,0,2)) mod 2^24) + 0.5)
+ * / 2^24 (a radical inverse of j rotated per point), where
  * h(i,j,k) = pcg(pcg(pcg(seed) ^ i) ^ (4j + k)) >> 8 and pcg is the hash of the direction
  * set above.
  *
@@ -377,7 +379,8 @@ sop_status sop_adam_update(float* params, float* adam_m, float* adam_v, const fl
 /* Training targets of the proposal: T[i,b] = (1/(128 n)) sum_k lum(f L_i cos)(w_bk) / l_bk^3
  * estimates the integral over bin b of the luminance (Rec. 709 weights) of the integrand of
  * Eq. 6 at point i, with n = samples_per_bin directions placed in bin b's cell at
- * ((h(i,j,1) + 0.5), (h(i,j,2) + 0.5)) / 2^24, j = b n + k, and l_bk the L2 norm of the
+ * u = (k + (h(i,j,1) + 0.5) / 2^24) / n, v = (h(i,j,2) + 0.5) / 2^24, j = b n + k, and
+ * l_bk the L2 norm of the
  * (px,py,z) point of the direction. Uses opts->seed (and k/radius when nb is NULL);
  * targets: device [N,256] f32. */
 sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_maps* maps,

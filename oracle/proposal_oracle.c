@@ -19,7 +19,9 @@
  *    16x16 cells over [-1,1]^2, density constant in (u,v) inside a cell;
  *  - defensive mixture with the uniform-bin distribution: q_b = (1-eps) p_b + eps/256,
  *    quantised to 24-bit integer masses so that the bin draws are exact integer decisions;
- *  - stratified draws: sample j takes the j-th of S equal slices of the integer mass line;
+ *  - stratified draws: sample j takes the j-th of S equal slices of the integer mass line,
+ *    its position inside the bin's cell follows its place on the bin's stretch of that line
+ *    (u) and a per-point rotated radical inverse of j (v);
  *  - training target of a point: the luminance of f L_i cos integrated over each bin,
  *    estimated with samples placed uniformly in every bin; loss = cross entropy.
  * Build: compiled with sop_oracle.c (gcc -O2 -ffp-contract=off -fopenmp -shared).
@@ -47,6 +49,7 @@
 
 /* from sop_oracle.c */
 uint32_t orc_pcg_hash(uint32_t v);
+uint32_t orc_bitreverse32(uint32_t x);
 void orc_frame(const double n[3], double t[3], double b[3]);
 void orc_env_fetch(const double* env, int H, int W, const double w[3], double out[3]);
 void orc_interp(const double* tex, int R, const int32_t* nb_idx, const double* nb_w, int K,
@@ -311,8 +314,12 @@ static int prop_draw(const uint32_t c[PR_BINS], uint64_t total, int S, uint32_t 
     cum += c[b];
   }
   if (b == PR_BINS) b = PR_BINS - 1;   /* unreachable: x < total */
-  double xu = ((double)orc_hash24(seed, i, (uint32_t)j, 1) + 0.5) / 16777216.0;
-  double xv = ((double)orc_hash24(seed, i, (uint32_t)j, 2) + 0.5) / 16777216.0;
+  /* position in the cell: u from the draw's place on the bin's stretch of the mass line,
+     v from the radical inverse of j rotated per point (a Hammersley set warped through the
+     bin distribution) */
+  double xu = ((double)(x - cum) + 0.5) / (double)c[b];
+  uint32_t v24 = ((orc_bitreverse32((uint32_t)j) >> 8) + orc_hash24(seed, i, 0, 2)) & 0xFFFFFFu;
+  double xv = ((double)v24 + 0.5) / 16777216.0;
   double u = -1.0 + ((b % PR_SIDE) + xu) / 8.0, v = -1.0 + ((b / PR_SIDE) + xv) / 8.0;
   double l = bin_direction(u, v, wl);
   *pdf = (double)c[b] / (double)total * 128.0 * l * l * l;
@@ -394,9 +401,10 @@ void orc_prop_shade(long N, const double* pos, const double* normal, const doubl
 
 /* ------------------------------------------------------------------------------------
  * Training data: T[i][b] estimates the integral over bin b of lum(f L_i cos), with n_pb
- * samples placed uniformly in each bin's (u,v) cell: the (u,v) cell has area 1/64 and
+ * samples placed in each bin's (u,v) cell: the (u,v) cell has area 1/64 and
  * d omega = s^3 / 2 dA_uv, so T_b = (1/(128 n_pb)) sum_k lum(y_k) s_k^3. Sample k of bin b
- * is sample j = b n_pb + k of the counter-based generator (streams 1 and 2 as above).
+ * is sample j = b n_pb + k of the counter-based generator: u = (k + h(i,j,1))/n_pb inside
+ * the cell, v = h(i,j,2) (with the half-unit offset of the 24-bit values).
  * lum = Rec. 709 weights.
  * ----------------------------------------------------------------------------------*/
 void orc_dump_integrand(long N, const double* pos, const double* normal, const double* view,
@@ -414,7 +422,8 @@ void orc_dump_integrand(long N, const double* pos, const double* normal, const d
       double acc = 0.0;
       for (int k = 0; k < n_pb; ++k) {
         uint32_t j = (uint32_t)(b * n_pb + k);
-        double xu = ((double)orc_hash24(seed, (uint32_t)i, j, 1) + 0.5) / 16777216.0;
+        /* u stratified over the n_pb draws of the bin, v random */
+        double xu = (k + ((double)orc_hash24(seed, (uint32_t)i, j, 1) + 0.5) / 16777216.0) / n_pb;
         double xv = ((double)orc_hash24(seed, (uint32_t)i, j, 2) + 0.5) / 16777216.0;
         double u = -1.0 + ((b % PR_SIDE) + xu) / 8.0, vv = -1.0 + ((b / PR_SIDE) + xv) / 8.0;
         double wl[3], w[3], y[3];

@@ -232,11 +232,8 @@ __device__ __forceinline__ double bin_dir(double u, double v, double wl[3]) {
   return l;
 }
 
-// position of draw j inside bin b (streams 1 and 2 of the point's generator)
-__device__ __forceinline__ double cell_point(uint32_t seed_h, uint32_t i, uint32_t j, int b,
-                                             double wl[3]) {
-  const double xu = ((double)hash24(seed_h, i, j, 1) + 0.5) * 0x1p-24;
-  const double xv = ((double)hash24(seed_h, i, j, 2) + 0.5) * 0x1p-24;
+// local direction of the point (xu, xv) in [0,1)^2 of bin b's cell
+__device__ __forceinline__ double cell_point(double xu, double xv, int b, double wl[3]) {
   const double u = -1.0 + ((double)(b & 15) + xu) * 0.125;
   const double v = -1.0 + ((double)(b >> 4) + xv) * 0.125;
   return bin_dir(u, v, wl);
@@ -313,6 +310,7 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
   nb.load(a, ps.p, k);
   const uint64_t total = bin_masses(a, ps.p, lane, cum);
   const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+  const uint32_t rot_v = hash24(sh, pi, 0, 2);
   const double inv_total = 1.0 / (double)total;
 
   float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
@@ -323,8 +321,13 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
       const uint64_t x = ((uint64_t)j * total + ((r * total) >> 24)) / (uint64_t)a.S;
       const int b = find_bin(cum, x);
       const uint64_t cb = cum[b + 1] - cum[b];
+      // u: place of the draw on the bin's stretch of the mass line; v: radical inverse of j
+      // rotated per point
+      const double xu = ((double)(x - cum[b]) + 0.5) / (double)cb;
+      const uint32_t v24 = ((__builtin_bitreverse32((uint32_t)j) >> 8) + rot_v) & 0xFFFFFFu;
+      const double xv = ((double)v24 + 0.5) * 0x1p-24;
       double wl[3];
-      const double l = cell_point(sh, pi, (uint32_t)j, b, wl);
+      const double l = cell_point(xu, xv, b, wl);
       const float inv_pdf = (float)(1.0 / ((double)cb * inv_total * 128.0 * l * l * l));
       Sample s;
       world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
@@ -362,7 +365,8 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
 }
 
 // Training targets of the proposal: T[i][b] = (1/(128 n)) sum_k lum(f L_i cos) / l^3 over n
-// draws placed in bin b's cell (draw j = b n + k), summed per bin in the wave's LDS row.
+// draws placed in bin b's cell (draw j = b n + k, u stratified over the n draws, v random),
+// summed per bin in the wave's LDS row.
 template <int KT, typename TexT>
 __global__ __launch_bounds__(256) void k_dump_integrand(ShadeArgs a, int32_t k) {
   __shared__ float s_acc[kWavesPerBlock][SOP_MLP_BINS];
@@ -385,9 +389,13 @@ __global__ __launch_bounds__(256) void k_dump_integrand(ShadeArgs a, int32_t k) 
   for (int j0 = 0; j0 < total; j0 += 64) {
     const int j = j0 + lane;
     if (j < total) {
-      const int b = j / npb;
+      const int b = j / npb, kk = j - b * npb;
+      // u stratified over the bin's draws, v random
+      const double xu =
+          ((double)kk + ((double)hash24(sh, pi, (uint32_t)j, 1) + 0.5) * 0x1p-24) / (double)npb;
+      const double xv = ((double)hash24(sh, pi, (uint32_t)j, 2) + 0.5) * 0x1p-24;
       double wl[3];
-      const double l = cell_point(sh, pi, (uint32_t)j, b, wl);
+      const double l = cell_point(xu, xv, b, wl);
       Sample s;
       world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
       s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
