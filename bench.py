@@ -4,7 +4,11 @@ One step = one pass of the whole path over the object workload: re-register the 
 Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays), rebuild the probe
 grid, order the 200k shading points and find their 8 nearest probes, shade them with 128
 directions (forward) and run the adjoint (backward) into the probe and environment
-gradients. value = shaded point-direction samples (N*S) per second of the whole step.
+gradients; then run the proposal network on the 200k points, shade them again with 32
+proposal-sampled directions, and take one proposal training step (fresh bin targets for
+4096 points + Adam). value = shaded point-direction samples (N*S, S = 128) per second of the
+whole step. After the timed region, the learned proposal's speedup at matched error is
+measured on the tiny scene's geometry (see proposal_study).
 
 Prints ONE JSON line. Per-kernel durations are measured with HIP events on the stream the
 kernels run on; algorithmic flop counts per sample are documented below.
@@ -26,6 +30,9 @@ if ROOT not in sys.path:
 METRIC = "shaded point·direction samples/s fwd+bwd; % HBM roofline; speedup at matched error"
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector, published (packed FMA)
 PEAK_HBM_GBS = 8000.0
+S_PROP = 32            # proposal-sampled directions per point in the step
+MIX_EPS = 0.1          # uniform-bin share of the proposal mixture
+TRAIN_BATCH = 4096     # points per proposal training step
 
 
 # Algorithmic FP32 operations per sample (+, -, *, / and each transcendental, sqrt, floor
@@ -60,6 +67,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-proposal-study", action="store_true")
+    ap.add_argument("--proposal-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -71,7 +80,8 @@ def main() -> int:
     import numpy as np
     import torch
 
-    from paper_2510_07729_amd import scenes, sop
+    from paper_2510_07729_amd import _lib as L
+    from paper_2510_07729_amd import proposal, scenes, sop
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -110,12 +120,34 @@ def main() -> int:
     ws_b = sop.workspace(plan.workspace_size(sop.L.SOP_OP_SHADE_BACKWARD, N, K, S, env.shape[:2],
                                              True), dev)
 
-    names = ["bake_grid", "bake", "probe_grid", "knn", "shade_fwd", "shade_bwd"]
+    # learned proposal on the same points: network inference, proposal-sampled shading at
+    # S_PROP directions, and one training step (fresh bin targets for a batch + Adam)
+    mlp_obj = proposal.default_mlp(dev, sc.bounds_lo, sc.bounds_hi, seed=0)
+    probs = torch.empty((N, L.SOP_MLP_BINS), dtype=torch.float32, device=dev)
+    rgb_p = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    ws_inf = sop.proposal_workspace(L.SOP_OP_PROPOSAL_INFER, N, dev)
+    ws_pf = sop.workspace(plan.workspace_size(L.SOP_OP_SHADE, N, K, S_PROP, env.shape[:2], True),
+                          dev)
+    pts_tb = sop.Points(pts.pos[:TRAIN_BATCH], pts.normal[:TRAIN_BATCH], pts.albedo[:TRAIN_BATCH],
+                        pts.rough[:TRAIN_BATCH], pts.metal[:TRAIN_BATCH],
+                        view=pts.view[:TRAIN_BATCH])
+    T_tb = torch.empty((TRAIN_BATCH, L.SOP_MLP_BINS), dtype=torch.float32, device=dev)
+    loss_tb = torch.empty(1, dtype=torch.float32, device=dev)
+    ws_dump = sop.workspace(plan.workspace_size(L.SOP_OP_DUMP_INTEGRAND, TRAIN_BATCH, K, 1,
+                                                env.shape[:2]), dev)
+    ws_tr = sop.proposal_workspace(L.SOP_OP_PROPOSAL_TRAIN, TRAIN_BATCH, dev)
+
+    names = ["bake_grid", "bake", "probe_grid", "knn", "shade_fwd", "shade_bwd",
+             "proposal_infer", "proposal_shade", "proposal_train"]
     ev = {n: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for n in names}
     acc = {n: 0.0 for n in names}
 
+    it_count = [0]
+
     def step(timed: bool):
+        it_count[0] += 1
+
         def mark(n, i):
             if timed:
                 ev[n][i].record()
@@ -140,6 +172,18 @@ def main() -> int:
         sop.sop_shade_backward(plan, tex, env, pts, grad, S, nb=nb, g_env=g_env, g_tex=g_tex,
                                ws=ws_b)
         mark("shade_bwd", 1)
+        mark("proposal_infer", 0)
+        sop.sop_proposal_infer(mlp_obj, pts, ws=ws_inf, out=probs)
+        mark("proposal_infer", 1)
+        mark("proposal_shade", 0)
+        sop.sop_shade(plan, tex, env, pts, S_PROP, nb=nb, ws=ws_pf, out=rgb_p, probs=probs,
+                      mix_eps=MIX_EPS)
+        mark("proposal_shade", 1)
+        mark("proposal_train", 0)
+        sop.sop_dump_integrand(plan, tex, env, pts_tb, 1, k=K, seed=it_count[0], out=T_tb,
+                               ws=ws_dump)
+        sop.sop_proposal_train_step(mlp_obj, pts_tb, T_tb, lr=1e-4, loss=loss_tb, ws=ws_tr)
+        mark("proposal_train", 1)
         if timed:
             torch.cuda.synchronize()
             for n in names:
@@ -203,6 +247,11 @@ def main() -> int:
         shade_roof[n] = {"achieved_tflops": round(a, 3), "frac": round(a / PEAK_FP32_TFLOPS, 4),
                          "flops_per_sample": f, "launch_ms": round(phase[n], 4)}
 
+    study = None
+    if not args.no_proposal_study:
+        study = proposal_study(torch, dev, args.proposal_steps)
+        print(f"# proposal study: {json.dumps(study)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, gs, probes_np, R, args.cpu_seconds, samples)
@@ -214,16 +263,94 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "object_scene: bake 100k Gaussians into 4096 probes x 32x32 "
                                "texels, probe grid, kNN (K=8), shade fwd+bwd of 200k points "
-                               "x 128 directions, env 256x512",
+                               "x 128 directions, env 256x512; proposal network on 200k "
+                               "points, proposal shade x 32 directions, one training step "
+                               "(4096 points)",
                    "points": N, "dirs": S, "k": K, "probes": P, "res": R, "gaussians": G},
         "fwd_bwd_samples_per_s": round(fb_rate, 1),
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "roofline": roof,
         "shade_roofline": shade_roof,
+        "proposal_study": study,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def proposal_study(torch, dev, steps: int) -> dict:
+    """Speedup at matched error of the learned proposal on the tiny scene's geometry (64
+    probes with 16x16 maps, 32x64 environment, K=4): online training on a pool of 262,144
+    points, then 200k held-out points shaded with the fixed Hammersley set (the paper's
+    estimator) and with proposal samples, each against a 4096-direction Hammersley reference.
+    RMSE is taken over the points with roughness >= 0.25, whose lobes the reference itself
+    resolves (narrower lobes are not converged by 4096 uniform directions either). S* is the
+    smallest proposal count whose RMSE reaches the Hammersley RMSE at 128 directions;
+    speedup = t(Hammersley 128) / (t(network) + t(proposal S*))."""
+    import numpy as np
+
+    from paper_2510_07729_amd import _lib as L
+    from paper_2510_07729_amd import proposal, scenes, sop
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+
+    def pts_of(sc):
+        return sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                          view=d(sc.view))
+
+    pool_sc = scenes.proposal_eval(262_144, seed=5)
+    ev_sc = scenes.proposal_eval(200_000, seed=0)
+    plan = sop.Plan(d(pool_sc.probe_pos), pool_sc.bounds_lo, pool_sc.bounds_hi)
+    tex, env = d(pool_sc.texels), d(pool_sc.env)
+    pool, ev = pts_of(pool_sc), pts_of(ev_sc)
+    mlp = proposal.default_mlp(dev, pool_sc.bounds_lo, pool_sc.bounds_hi, seed=0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    losses = proposal.train(mlp, plan, tex, env, pool, steps, batch=TRAIN_BATCH, lr=2e-3,
+                            log_every=max(1, steps // 4))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+
+    nb = sop.sop_knn(plan, ev, 4)
+    ref = sop.sop_shade(plan, tex, env, ev, 4096, nb=nb, seed=123)
+    mask = ev.rough >= 0.25
+
+    def rmse(x):
+        return float(torch.sqrt(torch.mean(((x - ref)[mask]) ** 2)))
+
+    def timed(fn, reps=10):
+        out = fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b) / reps
+
+    ham = {}
+    for S in (32, 64, 128):
+        out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7))
+        ham[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
+    probs, t_mlp = timed(lambda: sop.sop_proposal_infer(mlp, ev))
+    prop = {}
+    for S in (8, 16, 32, 64):
+        out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7, probs=probs,
+                                              mix_eps=MIX_EPS))
+        prop[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
+    target = ham[128]["rmse"]
+    s_star = next((S for S in sorted(prop) if prop[S]["rmse"] <= target), None)
+    speedup = (ham[128]["ms"] / (t_mlp + prop[s_star]["ms"])) if s_star else None
+    return {"workload": "tiny scene geometry, 200k held-out points, K=4, RMSE over "
+                        "roughness >= 0.25 against 4096 Hammersley directions",
+            "train_steps": steps, "train_batch": TRAIN_BATCH,
+            "train_integrand_samples": proposal.integrand_samples(steps, TRAIN_BATCH),
+            "train_ms": round(train_ms, 1), "loss_trace": [round(x, 4) for x in losses],
+            "mix_eps": MIX_EPS, "hammersley": ham, "proposal": prop,
+            "network_ms": round(t_mlp, 4), "S_star": s_star,
+            "speedup_vs_hammersley_128": round(speedup, 3) if speedup else None}
 
 
 def copy_calibration(torch, dev) -> int:

@@ -24,10 +24,15 @@ struct PointState {
   double cr, sr;   // per-point rotation of the direction table (1, 0 when per call)
 };
 
+// Point of processing slot wv. Uniform: one point per wavefront (the index is made
+// wave-uniform so that the point's data comes through scalar loads); otherwise each lane
+// group loads its own point.
+template <bool Uniform = true>
 __device__ __forceinline__ bool load_point(const ShadeArgs& a, int64_t wv, PointState& ps) {
   int64_t p = wv;
   if (a.order) {
-    const int32_t o = __builtin_amdgcn_readfirstlane(a.order[wv]);
+    int32_t o = a.order[wv];
+    if (Uniform) o = __builtin_amdgcn_readfirstlane(o);
     if ((uint64_t)o >= (uint64_t)a.n) return false;
     p = o;
   }
@@ -164,20 +169,41 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
   eval_at<KT, TexT>(a, ps, nb, k, s);
 }
 
-template <int KT, typename TexT>
-__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
-  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
-  if (wv >= a.n) return;
-  const int lane = threadIdx.x & 63;
-  PointState ps;
-  if (!load_point(a, wv, ps)) return;
-  Neighbors<KT> nb;
-  nb.load(a, ps.p, k);
+// Sum over the L lanes of a lane group (L = 64: the whole wavefront, with DPP).
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (L == 64) {
+    return wave_sum(v);
+  } else {
+#pragma unroll
+    for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+  }
+}
 
+// Processing slot of the lane's group: L lanes per point, 64/L points per wavefront (small
+// direction counts would otherwise leave lanes idle and pay a wavefront's fixed per-point
+// cost for one point).
+template <int L>
+__device__ __forceinline__ int64_t group_slot(int lane) {
+  return ((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * (64 / L) + lane / L;
+}
+
+template <int KT, typename TexT, int L>
+__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
+  const int lane = threadIdx.x & 63, li = lane % L;
+  const int64_t slot = group_slot<L>(lane);
+  if (((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+  PointState ps;
+  // lanes of a group past the end (or with an invalid order entry) skip the work but take
+  // part in the group sums
+  const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
+  if (L == 64 && !valid) return;
+  Neighbors<KT> nb;
   float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
-  for (int j0 = 0; j0 < a.S; j0 += 64) {
-    const int j = j0 + lane;
-    if (j < a.S) {
+  if (valid) {
+    nb.load(a, ps.p, k);
+    for (int j = li; j < a.S; j += L) {
       Sample s;
       eval_sample<KT, TexT>(a, ps, nb, k, j, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
@@ -192,16 +218,16 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
   }
   float r[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) r[c] = wave_sum(acc[c]) * a.scale;
-  if (lane == 0) {
+  for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc[c]) * a.scale;
+  if (valid && li == 0) {
     a.rgb[3 * ps.p] = r[0];
     a.rgb[3 * ps.p + 1] = r[1];
     a.rgb[3 * ps.p + 2] = r[2];
   }
   if (a.irr) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = wave_sum(acc_e[c]) * a.scale;
-    if (lane == 0) {
+    for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc_e[c]) * a.scale;
+    if (valid && li == 0) {
       a.irr[3 * ps.p] = r[0];
       a.irr[3 * ps.p + 1] = r[1];
       a.irr[3 * ps.p + 2] = r[2];
@@ -239,48 +265,61 @@ __device__ __forceinline__ double cell_point(double xu, double xv, int b, double
   return bin_dir(u, v, wl);
 }
 
-__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
-  const uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d, int width) {
+  const uint32_t lo = __shfl_up((uint32_t)v, d, width);
+  const uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, width);
   return ((uint64_t)hi << 32) | lo;
 }
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
-  const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src, int width) {
+  const uint32_t lo = __shfl((uint32_t)v, src, width), hi = __shfl((uint32_t)(v >> 32), src, width);
   return ((uint64_t)hi << 32) | lo;
 }
 
-// cumulative integer masses cum[0..256] of the point's bins into the wave's LDS row
-__device__ __forceinline__ uint64_t bin_masses(const ShadeArgs& a, int64_t p, int lane,
-                                               uint64_t* cum) {
-  const float4 pr = *reinterpret_cast<const float4*>(a.probs + (size_t)p * SOP_MLP_BINS + 4 * lane);
+// Cumulative integer masses cum[0..256] of the point's bins into the group's LDS row; the L
+// lanes of the group take 256/L consecutive bins each. Lanes with load = false (a group past
+// the end) contribute nothing and take the uniform fallback.
+template <int L>
+__device__ __forceinline__ uint64_t bin_masses(const ShadeArgs& a, int64_t p, bool load,
+                                               int li, uint64_t* cum) {
+  constexpr int BPL = SOP_MLP_BINS / L;
   const float om = 1.0f - a.mix_eps, add = a.mix_eps * (1.0f / 256.0f);
-  const float pv[4] = {pr.x, pr.y, pr.z, pr.w};
-  uint32_t c[4];
+  uint32_t c[BPL];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    float q = pv[t];
-    q = q > 0.0f ? fminf(q, 1.0f) : 0.0f;                  // NaN and negatives count as 0
-    c[t] = (uint32_t)floorf(__builtin_fmaf(om, q, add) * 16777216.0f);
+  for (int q4 = 0; q4 < BPL / 4; ++q4) {
+    float4 pr = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (load)
+      pr = *reinterpret_cast<const float4*>(a.probs + (size_t)p * SOP_MLP_BINS + BPL * li + 4 * q4);
+    const float pv[4] = {pr.x, pr.y, pr.z, pr.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float q = pv[t];
+      q = q > 0.0f ? fminf(q, 1.0f) : 0.0f;                // NaN and negatives count as 0
+      c[4 * q4 + t] = (uint32_t)floorf(__builtin_fmaf(om, q, add) * 16777216.0f);
+    }
   }
-  uint64_t own = (uint64_t)c[0] + c[1] + c[2] + c[3];
+  uint64_t own = 0;
+#pragma unroll
+  for (int t = 0; t < BPL; ++t) own += c[t];
   uint64_t incl = own;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t o = shfl_up_u64(incl, d);
-    if (lane >= d) incl += o;
+  for (int d = 1; d < L; d <<= 1) {
+    const uint64_t o = shfl_up_u64(incl, d, L);
+    if (li >= d) incl += o;
   }
-  uint64_t total = shfl_u64(incl, 63);
+  uint64_t total = shfl_u64(incl, L - 1, L);
   if (total == 0) {                                         // nothing to sample: one unit per bin
-    c[0] = c[1] = c[2] = c[3] = 1;
-    incl = 4 * (uint64_t)(lane + 1);
-    own = 4;
-    total = 256;
+#pragma unroll
+    for (int t = 0; t < BPL; ++t) c[t] = 1;
+    incl = (uint64_t)BPL * (li + 1);
+    own = BPL;
+    total = SOP_MLP_BINS;
   }
   uint64_t run = incl - own;
-  if (lane == 0) cum[0] = 0;
+  if (li == 0) cum[0] = 0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < BPL; ++t) {
     run += c[t];
-    cum[4 * lane + t + 1] = run;
+    cum[BPL * li + t + 1] = run;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -297,26 +336,27 @@ __device__ __forceinline__ int find_bin(const uint64_t* cum, uint64_t x) {
   return b;
 }
 
-template <int KT, typename TexT>
+template <int KT, typename TexT, int L>
 __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
-  __shared__ uint64_t s_cum[kWavesPerBlock][SOP_MLP_BINS + 1];
-  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
-  if (wv >= a.n) return;
-  const int lane = threadIdx.x & 63;
-  uint64_t* cum = s_cum[threadIdx.x >> 6];
+  constexpr int PPW = 64 / L;
+  __shared__ uint64_t s_cum[kWavesPerBlock][PPW][SOP_MLP_BINS + 1];
+  const int lane = threadIdx.x & 63, li = lane % L;
+  const int64_t slot = group_slot<L>(lane);
+  if (((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * PPW >= a.n) return;
+  uint64_t* cum = s_cum[threadIdx.x >> 6][lane / L];
   PointState ps;
-  if (!load_point(a, wv, ps)) return;
+  const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
+  if (L == 64 && !valid) return;
+  const uint64_t total = bin_masses<L>(a, valid ? ps.p : 0, valid, li, cum);
   Neighbors<KT> nb;
-  nb.load(a, ps.p, k);
-  const uint64_t total = bin_masses(a, ps.p, lane, cum);
-  const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
-  const uint32_t rot_v = hash24(sh, pi, 0, 2);
-  const double inv_total = 1.0 / (double)total;
-
   float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
-  for (int j0 = 0; j0 < a.S; j0 += 64) {
-    const int j = j0 + lane;
-    if (j < a.S) {
+  if (valid) {
+    nb.load(a, ps.p, k);
+    const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+    const uint32_t rot_v = hash24(sh, pi, 0, 2);
+    const double inv_total = 1.0 / (double)total;
+    const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+    for (int j = li; j < a.S; j += L) {
       const uint64_t r = hash24(sh, pi, (uint32_t)j, 0);
       const uint64_t x = ((uint64_t)j * total + ((r * total) >> 24)) / (uint64_t)a.S;
       const int b = find_bin(cum, x);
@@ -335,7 +375,6 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
       s.ct = (float)wl[2];
       eval_at<KT, TexT>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
-      const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
@@ -347,16 +386,16 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
   const float scale = 1.0f / (float)a.S;
   float r3[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) r3[c] = wave_sum(acc[c]) * scale;
-  if (lane == 0) {
+  for (int c = 0; c < 3; ++c) r3[c] = group_sum<L>(acc[c]) * scale;
+  if (valid && li == 0) {
     a.rgb[3 * ps.p] = r3[0];
     a.rgb[3 * ps.p + 1] = r3[1];
     a.rgb[3 * ps.p + 2] = r3[2];
   }
   if (a.irr) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r3[c] = wave_sum(acc_e[c]) * scale;
-    if (lane == 0) {
+    for (int c = 0; c < 3; ++c) r3[c] = group_sum<L>(acc_e[c]) * scale;
+    if (valid && li == 0) {
       a.irr[3 * ps.p] = r3[0];
       a.irr[3 * ps.p + 1] = r3[1];
       a.irr[3 * ps.p + 2] = r3[2];
@@ -725,14 +764,32 @@ __global__ __launch_bounds__(256) void k_query(ShadeArgs a, int32_t k, const flo
   O[t] = oc;
 }
 
+// lanes per point for S directions: 16, 32 or 64
+static int lanes_for(int32_t S) { return S <= 16 ? 16 : (S <= 32 ? 32 : 64); }
+
+static dim3 grid_for(int64_t n, int L) {
+  const int64_t per_block = (int64_t)kWavesPerBlock * (64 / L);
+  return dim3((unsigned)((n + per_block - 1) / per_block));
+}
+
+template <int KT, int L>
+static void launch_prop_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const dim3 grid = grid_for(a.n, L);
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shade_prop<KT, uint2, L>), grid, dim3(256), 0, s, a, k);
+  else
+    hipLaunchKernelGGL((k_shade_prop<KT, float4, L>), grid, dim3(256), 0, s, a, k);
+}
+
 template <int KT>
 static void launch_prop_kt(int mode, const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
                            hipStream_t s) {
   if (mode == 0) {
-    if (format == SOP_TEXEL_F16)
-      hipLaunchKernelGGL((k_shade_prop<KT, uint2>), grid, dim3(256), 0, s, a, k);
-    else
-      hipLaunchKernelGGL((k_shade_prop<KT, float4>), grid, dim3(256), 0, s, a, k);
+    switch (lanes_for(a.S)) {
+      case 16: launch_prop_l<KT, 16>(a, k, format, s); break;
+      case 32: launch_prop_l<KT, 32>(a, k, format, s); break;
+      default: launch_prop_l<KT, 64>(a, k, format, s); break;
+    }
   } else {
     if (format == SOP_TEXEL_F16)
       hipLaunchKernelGGL((k_dump_integrand<KT, uint2>), grid, dim3(256), 0, s, a, k);
@@ -760,14 +817,24 @@ hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, 
   return dispatch_prop(1, a, k, format, s);
 }
 
+template <int KT, int L>
+static void launch_fwd_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const dim3 grid = grid_for(a.n, L);
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shade_fwd<KT, uint2, L>), grid, dim3(256), 0, s, a, k);
+  else
+    hipLaunchKernelGGL((k_shade_fwd<KT, float4, L>), grid, dim3(256), 0, s, a, k);
+}
+
 template <int KT>
 static void launch_kt(bool fwd, const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
                       hipStream_t s) {
   if (fwd) {
-    if (format == SOP_TEXEL_F16)
-      hipLaunchKernelGGL((k_shade_fwd<KT, uint2>), grid, dim3(256), 0, s, a, k);
-    else
-      hipLaunchKernelGGL((k_shade_fwd<KT, float4>), grid, dim3(256), 0, s, a, k);
+    switch (lanes_for(a.S)) {
+      case 16: launch_fwd_l<KT, 16>(a, k, format, s); break;
+      case 32: launch_fwd_l<KT, 32>(a, k, format, s); break;
+      default: launch_fwd_l<KT, 64>(a, k, format, s); break;
+    }
   } else {
     if (format == SOP_TEXEL_F16)
       hipLaunchKernelGGL((k_shade_bwd<KT, uint2>), grid, dim3(256), 0, s, a, k);

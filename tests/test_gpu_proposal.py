@@ -179,7 +179,7 @@ def test_train_step_moves_like_oracle(torch_gpu):
 def test_proposal_shade_matches_oracle(torch_gpu, S, eps, kind):
     log(f"proposal shading S={S} eps={eps} probs={kind}")
     import torch
-    sc = scenes.tiny_shade(n_points=512)
+    sc = scenes.tiny_shade(n_points=509)          # not a multiple of the points per wavefront
     idx, w = oracle_knn(sc)
     if kind == "dirichlet":
         probs = scenes.bin_probs(sc.n, concentration=0.3, seed=S)

@@ -131,7 +131,9 @@ def test_shade_tiny_full_parity(torch_gpu):
 
 @pytest.mark.parametrize("n_dirs,k,per_point,n", [(1, 4, False, 257), (5, 3, False, 1001),
                                                    (100, 8, True, 999), (128, 16, False, 512),
-                                                   (64, 1, True, 64), (200, 2, False, 130)])
+                                                   (64, 1, True, 64), (200, 2, False, 130),
+                                                   (32, 4, True, 1003), (16, 8, False, 77),
+                                                   (17, 5, False, 3)])
 def test_shade_variants(torch_gpu, n_dirs, k, per_point, n):
     log(f"shade variant S={n_dirs} K={k} per_point={per_point} N={n}")
     sc = scenes.tiny_shade(n_points=n, seed=5)
