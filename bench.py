@@ -1,8 +1,8 @@
 """Benchmark of the SOP hot path on one MI355X.
 
-One step = one pass of the whole path over the object workload: re-register the 100k
-Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays), rebuild the probe
-grid, order the 200k shading points and find their 8 nearest probes, shade them with 128
+One step = one pass of the whole path over the object workload: rebuild the probe grid,
+re-register the 100k Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays,
+probes traced in the probe grid's Morton order), order the 200k shading points and find their 8 nearest probes, shade them with 128
 directions (forward) and run the adjoint (backward) into the probe and environment
 gradients; then run the proposal network on the 200k points, shade them again with 32
 proposal-sampled directions, and take one proposal training step (fresh bin targets for
@@ -151,15 +151,15 @@ def main() -> int:
         def mark(n, i):
             if timed:
                 ev[n][i].record()
+        mark("probe_grid", 0)
+        plan.rebuild(probes)
+        mark("probe_grid", 1)
         mark("bake_grid", 0)
         bake_plan.update(g_mean, g_scale, g_rot, g_op, g_col)
         mark("bake_grid", 1)
         mark("bake", 0)
-        sop.sop_bake(bake_plan, probes, R, texels=tex, depth_out=dep)
+        sop.sop_bake(bake_plan, probes, R, texels=tex, depth_out=dep, order_by=plan)
         mark("bake", 1)
-        mark("probe_grid", 0)
-        plan.rebuild(probes)
-        mark("probe_grid", 1)
         mark("knn", 0)
         nb = sop.sop_knn(plan, pts, K)
         mark("knn", 1)

@@ -300,9 +300,13 @@ sop_status sop_bake_plan_check(const sop_bake_plan* plan, sop_stream stream);
 sop_status sop_bake_plan_destroy(sop_bake_plan* plan);
 
 /* Traces every texel of P probes at resolution res. texels: device [P,res,res,4] f32
- * (R,G,B,O); depth: device [P,res,res] f32 or NULL. No workspace. */
+ * (R,G,B,O); depth: device [P,res,res] f32 or NULL. No workspace. order_by (may be NULL) is
+ * a probe plan over the same P probes: the probes are then traced in its cell-major Morton
+ * order, which keeps the Gaussians that concurrently traced rays meet in one die's cache;
+ * outputs stay in the caller's probe order and do not depend on it. */
 sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n_probes,
-                    int32_t res, float* texels, float* depth, sop_stream stream);
+                    int32_t res, float* texels, float* depth, const sop_plan* order_by,
+                    sop_stream stream);
 
 /* ----------------------------------------------------------------------------------------
  * Learned direction proposal: an extension of the Monte Carlo estimate of Eq. 7 (the paper

@@ -99,7 +99,7 @@ SIGNATURES = {
     "sop_bake_plan_update": (c_i32, [c_vp, P(sop_gaussians), c_vp]),
     "sop_bake_plan_check": (c_i32, [c_vp, c_vp]),
     "sop_bake_plan_destroy": (c_i32, [c_vp]),
-    "sop_bake": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "sop_bake": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "sop_proposal_workspace_size": (C.c_size_t, [c_i32, c_i64]),
     "sop_proposal_infer": (c_i32, [P(sop_mlp), P(sop_points), c_vp, c_vp, c_vp, C.c_size_t,
                                    c_vp]),

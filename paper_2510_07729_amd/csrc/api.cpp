@@ -1015,16 +1015,18 @@ extern "C" sop_status sop_bake_plan_destroy(sop_bake_plan* plan) {
 
 extern "C" sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos,
                                int32_t n_probes, int32_t res, float* texels, float* depth,
-                               sop_stream stream) {
+                               const sop_plan* order_by, sop_stream stream) {
   if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
   if (n_probes < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "n_probes < 0");
+  if (order_by && order_by->P != n_probes)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "order_by holds a different number of probes");
   if (res < 2 || res > SOP_MAX_RES) return fail(SOP_ERR_INVALID_ARGUMENT, "res out of [2, 256]");
   if (n_probes > 0 && (!probe_pos || !texels || !aligned(probe_pos, 4) || !aligned(texels, 16) ||
                        (depth && !aligned(depth, 4))))
     return fail(SOP_ERR_INVALID_ARGUMENT, "probe_pos/texels NULL or misaligned");
   if (n_probes == 0) return SOP_OK;
   SOP_HIP(sopk::launch_bake(plan->grid, probe_pos, n_probes, res, texels, depth,
-                            (hipStream_t)stream),
+                            order_by ? order_by->qsorted : nullptr, (hipStream_t)stream),
           "sop_bake");
   return SOP_OK;
 }

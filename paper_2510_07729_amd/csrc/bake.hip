@@ -167,13 +167,19 @@ __device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
 }
 
 __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
-                                              int32_t R, float* texels, float* depth) {
-  // a wavefront covers an 8x8 tile of one probe's texels
+                                              int32_t R, float* texels, float* depth,
+                                              const int4* order) {
+  // a wavefront covers an 8x8 tile of one probe's texels; consecutive workgroups take
+  // consecutive probes of the order, so the workgroups in flight on all dies trace rays from
+  // one neighbourhood of probes and share the Gaussians those rays meet in cache
   const int32_t tiles_x = (R + 7) >> 3;
   const int32_t tiles = tiles_x * tiles_x;
   const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wave >= (int64_t)P * tiles) return;
-  const int32_t p = (int32_t)(wave / tiles);
+  const int32_t slot = (int32_t)(wave / tiles);
+  // probes in the given order (the cell-major Morton order of a probe plan), else as stored
+  const int32_t p = order ? order[slot].w : slot;
+  if ((uint32_t)p >= (uint32_t)P) return;
   const int32_t tile = (int32_t)(wave % tiles);
   const int lane = threadIdx.x & 63;
   const int32_t ti = (tile % tiles_x) * 8 + (lane & 7);
@@ -377,12 +383,13 @@ hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_
 }
 
 hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
-                       float* texels, float* depth, hipStream_t s) {
+                       float* texels, float* depth, const int4* order, hipStream_t s) {
   const int64_t tiles = (int64_t)((R + 7) / 8) * ((R + 7) / 8);
   const int64_t waves = (int64_t)P * tiles;
   if (waves == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bake, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, G, probe_pos,
-                     P, R, texels, depth);
+  const int64_t blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL(k_bake, dim3((unsigned)blocks), dim3(256), 0, s, G, probe_pos, P, R,
+                     texels, depth, order);
   return hipGetLastError();
 }
 

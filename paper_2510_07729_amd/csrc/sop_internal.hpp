@@ -161,6 +161,6 @@ hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_
                              int32_t* cursor, int32_t* entries, int32_t capacity,
                              int32_t* overflow, hipStream_t s);
 hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
-                       float* texels, float* depth, hipStream_t s);
+                       float* texels, float* depth, const int4* order, hipStream_t s);
 
 }  // namespace sopk

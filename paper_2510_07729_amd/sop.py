@@ -433,8 +433,10 @@ class BakePlan:
 
 
 def sop_bake(plan: BakePlan, probe_pos: torch.Tensor, res: int, depth: bool = True,
-             texels: Optional[torch.Tensor] = None, depth_out: Optional[torch.Tensor] = None):
-    """Probe textures [P,res,res,4] (R,G,B,O) and depth [P,res,res] by ray tracing."""
+             texels: Optional[torch.Tensor] = None, depth_out: Optional[torch.Tensor] = None,
+             order_by: Optional[Plan] = None):
+    """Probe textures [P,res,res,4] (R,G,B,O) and depth [P,res,res] by ray tracing; with
+    order_by (a probe Plan over the same probes) the probes are traced in its Morton order."""
     P = int(probe_pos.shape[0])
     dev = probe_pos.device
     tex = texels if texels is not None else torch.empty((P, res, res, 4), dtype=torch.float32,
@@ -446,5 +448,6 @@ def sop_bake(plan: BakePlan, probe_pos: torch.Tensor, res: int, depth: bool = Tr
                                                                   device=dev)
     L.check(plan._lib.sop_bake(plan.handle, _ptr(probe_pos, torch.float32, "probe_pos"), P,
                                int(res), _ptr(tex, torch.float32, "texels"), _ptr(dep),
+                               order_by.handle if order_by is not None else None,
                                _stream()), "sop_bake")
     return tex, dep

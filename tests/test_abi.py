@@ -86,7 +86,7 @@ def test_null_plan_and_null_out_are_rejected():
                          None) == L.SOP_ERR_INVALID_ARGUMENT
     assert lib.sop_shade_backward(None, None, None, None, None, C.byref(o), None, None, None,
                                   None, None, None, None, 0, None) == L.SOP_ERR_INVALID_ARGUMENT
-    assert lib.sop_bake(None, None, 0, 16, None, None, None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_bake(None, None, 0, 16, None, None, None, None) == L.SOP_ERR_INVALID_ARGUMENT
     assert lib.sop_bake_plan_check(None, None) == L.SOP_ERR_INVALID_ARGUMENT
 
 

@@ -114,3 +114,18 @@ def test_bake_plan_update_and_overflow(torch_gpu):
         plan.check()
     t3, _ = sop.sop_bake(plan, dev(probes), 8)
     assert torch.isnan(t3).all()
+
+
+def test_bake_morton_order_is_output_invariant(torch_gpu):
+    log("bake: probes traced in a probe plan's Morton order give the same bytes")
+    import torch
+    from paper_2510_07729_amd import sop
+    gs = scenes.object_gaussians()
+    probes_np = scenes.object_probes()[:1024]
+    probes = dev(probes_np)
+    lo, hi = probes_np.min(0) - 0.1, probes_np.max(0) + 0.1
+    pplan = sop.Plan(probes, lo, hi)
+    plan, t1, d1 = gpu_bake(gs, probes_np, 16)
+    t2, d2 = sop.sop_bake(plan, probes, 16, order_by=pplan)
+    torch.cuda.synchronize()
+    assert np.array_equal(t1, t2.cpu().numpy()) and np.array_equal(d1, d2.cpu().numpy())
