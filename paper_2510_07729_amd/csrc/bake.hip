@@ -2,8 +2,10 @@
 // initialised by ray tracing; the compositing of Eq. 1).
 //
 // Every Gaussian is turned into its whitening map M = S^-1 R^T (ray in Gaussian units) and
-// registered in the cells of a uniform grid overlapped by the box around its cut-off
-// ellipsoid (where opacity * exp(-m^2/2) can reach alpha_min), padded for FP32 rounding.
+// registered in the cells of a uniform grid that its cut-off ellipsoid (where
+// opacity * exp(-m^2/2) can reach alpha_min) may overlap: the cells of its axis-aligned box
+// that also pass a separating-axis test along the ellipsoid's own axes, padded for FP32
+// rounding.
 // One thread traces one texel's ray; a wavefront covers an 8x8 texel tile of one probe so
 // that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
 // composited in the cell whose t-window [t_enter, t_exit) holds its t*, and within a cell
@@ -64,7 +66,7 @@ __global__ __launch_bounds__(256) void k_gauss_prep(sop_gaussians g, float alpha
   const float mm = sqrtf(m2max);
   // bounding sphere of the cut-off ellipsoid, padded like the box below
   const float rb = (mm * fmaxf(s0, fmaxf(s1, s2))) * 1.002f + 1e-5f;
-  gd[4] = make_float4(rb * rb, rb, 0.0f, 0.0f);
+  gd[4] = make_float4(rb * rb, rb, mm, 0.0f);
   float hx = mm * sqrtf(R00 * R00 * s0 * s0 + R01 * R01 * s1 * s1 + R02 * R02 * s2 * s2);
   float hy = mm * sqrtf(R10 * R10 * s0 * s0 + R11 * R11 * s1 * s1 + R12 * R12 * s2 * s2);
   float hz = mm * sqrtf(R20 * R20 * s0 * s0 + R21 * R21 * s1 * s1 + R22 * R22 * s2 * s2);
@@ -111,6 +113,30 @@ __device__ __forceinline__ bool inside_grid(const BakeGrid& G, float4 lo, float4
          hi.z <= G.origin[2] + G.dims[2] * G.cell[2];
 }
 
+// Whether the cut-off ellipsoid of record gd (rows M_k = u_k / s_k, cut-off Mahalanobis
+// radius in gd[4].z) can reach cell (cx, cy, cz): separating-axis test along the ellipsoid's
+// three axes (its box already bounds the cell range along the grid axes). In the scaled
+// frame the ellipsoid spans |M_k (x - mean)| <= m; the cell projects to an interval of
+// half-width sum_a |M_k,a| h_a around M_k (centre - mean). Padded like the box, so the test
+// is conservative; count and fill take the same decisions.
+__device__ __forceinline__ bool cell_overlaps(const BakeGrid& G, const float4* gd, int cx,
+                                              int cy, int cz) {
+  const float mm = gd[4].z;
+  const float h0 = 0.5f * G.cell[0], h1 = 0.5f * G.cell[1], h2 = 0.5f * G.cell[2];
+  const float c0 = G.origin[0] + ((float)cx + 0.5f) * G.cell[0] - gd[0].w;
+  const float c1 = G.origin[1] + ((float)cy + 0.5f) * G.cell[1] - gd[1].w;
+  const float c2 = G.origin[2] + ((float)cz + 0.5f) * G.cell[2] - gd[2].w;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float4 r = gd[k];
+    const float proj = r.x * c0 + r.y * c1 + r.z * c2;
+    const float ext = fabsf(r.x) * h0 + fabsf(r.y) * h1 + fabsf(r.z) * h2;
+    const float len = sqrtf(r.x * r.x + r.y * r.y + r.z * r.z);   // 1 / s_k
+    if (fabsf(proj) > mm * 1.002f + 1e-5f * len + ext) return false;
+  }
+  return true;
+}
+
 __global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* aabb,
                                                      int32_t* counts, int32_t* overflow) {
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
@@ -119,10 +145,12 @@ __global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* a
   int c0[3], c1[3];
   if (!cell_range(G, lo, hi, c0, c1)) return;
   if (!inside_grid(G, lo, hi)) atomicOr(overflow, 1);
+  const float4* gd = G.gdata + (size_t)kGRows * i;
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x)
-        atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
+        if (cell_overlaps(G, gd, x, y, z))
+          atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
 }
 
 __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aabb,
@@ -139,9 +167,11 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
   const float4 lo = aabb[2 * i], hi = aabb[2 * i + 1];
   int c0[3], c1[3];
   if (!cell_range(G, lo, hi, c0, c1)) return;
+  const float4* gd = G.gdata + (size_t)kGRows * i;
   for (int z = c0[2]; z <= c1[2]; ++z)
     for (int y = c0[1]; y <= c1[1]; ++y)
       for (int x = c0[0]; x <= c1[0]; ++x) {
+        if (!cell_overlaps(G, gd, x, y, z)) continue;
         const int32_t c = (z * G.dims[1] + y) * G.dims[0] + x;
         const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
         entries[slot] = i;
@@ -368,6 +398,7 @@ hipError_t launch_gauss_prep(const sop_gaussians& g, float alpha_min, float4* gd
 hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* counts,
                               int32_t* overflow, hipStream_t s) {
   if (G.G == 0) return hipSuccess;
+  if (!G.gdata || !aabb || !counts || !overflow) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gauss_count, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb, counts,
                      overflow);
   return hipGetLastError();
@@ -377,6 +408,8 @@ hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_
                              int32_t* cursor, int32_t* entries, int32_t capacity,
                              int32_t* overflow, hipStream_t s) {
   if (G.G == 0) return hipSuccess;
+  if (!G.gdata || !aabb || !cell_start || !cursor || !entries || !overflow)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb,
                      cell_start, cursor, entries, capacity, overflow);
   return hipGetLastError();
