@@ -308,14 +308,26 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
         float al[kBuf];
 #pragma unroll
         for (int s = 0; s < kBuf; ++s) { key[s] = ~0ull; al[s] = 0.0f; }
+        // software pipeline: the record of entry e+1 and the index of entry e+2 are in
+        // flight while entry e is tested
+        int32_t gi_c = G.entries[e0];
+        float4 p0, p1, p2, p4;
+        {
+          const float4* gq = G.gdata + (size_t)kGRows * gi_c;
+          p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
+        }
+        int32_t gi_n = e0 + 1 < e1 ? G.entries[e0 + 1] : gi_c;
         for (int32_t e = e0; e < e1; ++e) {
-          const int32_t gi = G.entries[e];
+          const int32_t gi = gi_c;
+          const float4 r0 = p0, r1 = p1, r2 = p2, bs = p4;
           const float4* gd = G.gdata + (size_t)kGRows * gi;
-          const float4 r0 = gd[0], r1 = gd[1], r2 = gd[2];
+          if (e + 1 < e1) {
+            gi_c = gi_n;
+            const float4* gq = G.gdata + (size_t)kGRows * gi_c;
+            p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
+            if (e + 2 < e1) gi_n = G.entries[e + 2];
+          }
           const v3 om = mk3(o.x - r0.w, o.y - r1.w, o.z - r2.w);
-          // conservative pre-test: the accepted point o + t* d lies inside the cut-off
-          // ellipsoid, so within rb of the mean, and |t* - tc| <= rb
-          const float4 bs = gd[4];
           const float tc = -dot(om, d);
           if (dot(om, om) - tc * tc > bs.x) continue;
           if (tc + bs.y < t_lo || tc - bs.y >= t_hi) continue;
