@@ -3,14 +3,14 @@
  *         AMD Instinct MI355X (gfx950).
  *
  * The library computes the deferred-shading step of ComGS (arXiv 2510.07729), Sec. 3.1.2
- * ("Material and Lighting Decomposition"):
+ * (material and lighting decomposition):
  *   - every shading point x evaluates the rendering equation (Eq. 6) by the Monte Carlo
  *     estimate of Eq. 7 over S_r Hammersley directions on its hemisphere;
  *   - incident light is the environment map attenuated by occlusion plus indirect light
  *     (Eq. 8);
  *   - occlusion O and indirect radiance L_in come from the octahedral textures of the K
  *     nearest surface octahedral probes, blended with spatial and back-face weights
- *     (Eq. 9-11, "Efficient Querying through SOPs");
+ *     (Eq. 9-11, efficient querying through SOPs);
  *   - probe textures are initialised by tracing rays through the Gaussians (Sec. 3.1.2,
  *     paragraph introducing SOPs; Sec. 4.1 implementation details).
  * Two entry points go beyond the paper: the adjoint of the shading step
@@ -71,7 +71,7 @@ typedef enum sop_texel_format {
  * Inputs
  * --------------------------------------------------------------------------------------*/
 
-/* Probe positions (Sec. 3.1.2, "Automatic Placement of SOPs"). bounds_lo/hi are HOST
+/* Probe positions (Sec. 3.1.2, automatic placement of SOPs). bounds_lo/hi are HOST
  * values: the box in which positions are quantised for the neighbour search. Positions
  * outside the box are clamped onto it by the quantisation; hi > lo on every axis. */
 typedef struct sop_probe_set {
@@ -97,7 +97,7 @@ typedef struct sop_envmap {
   const float* texels;           /* device [H,W,3]                                        */
 } sop_envmap;
 
-/* Shading points (G-buffer texels, Sec. 3.1 "Multi-Target Rendering"). The view direction
+/* Shading points (G-buffer texels, Sec. 3.1, multi-target rendering). The view direction
  * is either given per point (`view`, unit vectors toward the viewer) or derived from one
  * camera position per frame: points [f*points_per_frame, (f+1)*points_per_frame) see
  * cam_pos[f]. Normals must be unit length; the BRDF assumes n . view > 0. */
@@ -129,7 +129,7 @@ typedef struct sop_plan sop_plan;             /* probe grid (opaque)            
 
 /* ----------------------------------------------------------------------------------------
  * Probe plan: quantised lattice + uniform grid over the probes, the acceleration structure
- * of the fixed-radius / k-nearest search of Sec. 3.1.2 ("Efficient Querying").
+ * of the fixed-radius / k-nearest search of Sec. 3.1.2 (efficient querying).
  * --------------------------------------------------------------------------------------*/
 
 /* Creates a plan for `probes` and builds its grid on `stream`. Allocates device memory for
@@ -179,7 +179,7 @@ sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps, const sop
  * phi = 2*pi * (((bitreverse32(j) >> 8) + rho) mod 2^24) / 2^24 in the orthonormal frame of
  * the normal (Duff et al. 2017). rho = pcg_hash(seed) >> 8 (or, per point,
  * pcg_hash(seed ^ pcg_hash(i)) >> 8), pcg_hash as in Jarzynski & Olano 2020.
- * BRDF (a reading of the "simplified Disney BRDF"): Lambert (1-m)*a/pi plus GGX
+ * BRDF (a reading of the simplified Disney BRDF the paper names): Lambert (1-m)*a/pi plus GGX
  * D*F*G/(4 NoL NoV), alpha = r^2, Smith-Schlick G with k = alpha/2, Schlick F with
  * F0 = 0.04(1-m) + a*m, NoV = max(n.v, 1e-4).
  * rgb_i = (2*pi/S) * sum_j f(w_j) * L_i(w_j) * cos(theta_j),
@@ -208,7 +208,7 @@ typedef struct sop_shade_opts {
 
 /* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL.
  * With SOP_SAMPLER_PROPOSAL the S directions of point i are drawn from its bin distribution
- * (see "Learned direction proposal" below) and rgb_i = (1/S) sum_j f L_i cos / pdf(w_j);
+ * (see the learned direction proposal below) and rgb_i = (1/S) sum_j f L_i cos / pdf(w_j);
  * out_irradiance is then (1/S) sum_j L_i cos / pdf(w_j). The proposal sampler has no
  * adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
@@ -251,7 +251,7 @@ size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points, int
 
 /* ----------------------------------------------------------------------------------------
  * Bake: probe textures by ray tracing through 3D Gaussians (Sec. 3.1.2, the SOP texture
- * initialisation "via ray tracing"; Sec. 4.1). For texel (u,v) of probe p the ray starts at
+ * initialisation by ray tracing; Sec. 4.1). For texel (u,v) of probe p the ray starts at
  * p along the octahedral decode of the texel centre. Each Gaussian responds at the ray
  * parameter t* of maximum density; alpha = min(alpha_max, opacity * exp(-m^2/2)) with m the
  * Mahalanobis distance at t*; Gaussians with t* <= t_min or alpha < alpha_min are skipped.

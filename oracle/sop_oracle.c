@@ -16,7 +16,7 @@
  *   xi1 = (j+0.5)/S and an integer rotation of xi2; UE4-style GGX/Lambert BRDF;
  *   shading-point normal in the back-face weight; 3D-Gaussian response at the ray's
  *   point of maximum density for the bake.
- * The BRDF's exact match to the authors' "simplified Disney" model and the pcg hash's
+ * The BRDF's exact match to the authors' simplified Disney model and the pcg hash's
  * match to its publication are parity unpinned (no values to compare against).
  */
 #include <math.h>
@@ -196,7 +196,7 @@ double orc_direction(int j, int S, uint32_t rho24, const double n[3], double w[3
 }
 
 /* ------------------------------------------------------------------------------------
- * BRDF (Eq. 6: "simplified Disney BRDF" of Burley 2012; the form is not given, reading:
+ * BRDF (Eq. 6: the simplified Disney BRDF of Burley 2012; the form is not given, reading:
  * Lambert diffuse weighted by (1-m) plus the GGX microfacet lobe of Walter et al. 2007 with
  * Smith-Schlick geometry k = alpha/2 and Schlick Fresnel, alpha = r^2, as in Karis 2013).
  * ----------------------------------------------------------------------------------*/
@@ -231,7 +231,7 @@ void orc_brdf(const double n[3], const double v[3], const double l[3], const dou
 }
 
 /* ------------------------------------------------------------------------------------
- * Neighbour search (Sec. 3.1.2 "Efficient Querying": FRNN then KNN; Eq. 10-11 weights).
+ * Neighbour search (Sec. 3.1.2, efficient querying: FRNN then KNN; Eq. 10-11 weights).
  * Reading: positions are quantised to a 2^15 lattice in IEEE single precision,
  *   sc = 32768 / max_a (hi_a - lo_a),  q_a = clamp(floor((x_a - lo_a) * sc), 0, 32767),
  * the squared lattice distance is an exact integer, neighbours are the K smallest by

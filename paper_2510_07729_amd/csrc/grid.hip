@@ -1,5 +1,5 @@
 // grid.hip - probe grid, point ordering and k-nearest-probe search (ComGS Sec. 3.1.2,
-// "Efficient Querying through SOPs": FRNN search then KNN weights of Eq. 10-11).
+// efficient querying through SOPs: FRNN search then KNN weights of Eq. 10-11).
 //
 // Positions are quantised to a 2^15 lattice in FP32; distances are exact integers. Probes
 // are counting-sorted into a cube of 2^bits cells per axis addressed by the Morton index of

@@ -333,7 +333,7 @@ def test_query_with_identical_probes_equals_one_probe():
 
 
 # ------------------------------------------------------------------------------------------
-# BRDF (Eq. 6, "simplified Disney" read as Lambert + GGX)
+# BRDF (Eq. 6, the simplified Disney model read as Lambert + GGX)
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("alpha", [0.0025, 0.04, 0.3, 1.0])
 def test_ggx_ndf_is_normalised(alpha):
