@@ -223,3 +223,68 @@ def test_dump_integrand_matches_oracle(torch_gpu, npb):
                                  k=sc.k, seed=13)
     torch.cuda.synchronize()
     assert report("bin targets", parity_err(T.cpu().numpy(), ref)) <= TOL
+
+
+def test_proposal_object_scale_sampled(torch_gpu):
+    """The benchmark's launch configuration: the network on 200k object points, proposal
+    shading at S=32 with K=8 on all 200k; the first 1500 points (i.i.d., so a random sample
+    that keeps the point indices the draws depend on) checked against the oracle, the
+    network's logits on 256 of them."""
+    log("proposal at object scale: 200k points, K=8, S=32; 1500 checked on the oracle")
+    import torch
+    sc = scenes.object_scene()
+    params = scenes.mlp_init(seed=11)
+    mlp = sop().Mlp(dev(params), sc.bounds_lo, sc.bounds_hi)
+    pts = gpu_points(sc)
+    plan = gpu_plan(sc)
+    nb = sop().sop_knn(plan, pts, 8)
+    _, logits = sop().sop_proposal_infer(mlp, pts, logits=True)
+    probs = scenes.bin_probs(sc.n, concentration=0.3, seed=21)
+    rgb = sop().sop_shade(plan, dev(sc.texels), dev(sc.env), pts, 32, nb=nb, seed=3,
+                          probs=dev(probs), mix_eps=0.1)
+    torch.cuda.synchronize()
+    rows = np.arange(1500)
+    sub = sc.subset(rows)
+    idx, w = oracle_knn(sub, 8)
+    ref = oracle.prop_shade(sub, idx, w, probs[rows], 0.1, 32, 3)
+    assert report("object proposal rgb", parity_err(rgb.cpu().numpy()[rows], ref)) <= TOL
+    r2 = rows[:256]
+    lo, _ = oracle.mlp_infer(params.astype(np.float64), sc.pos[r2], sc.normal[r2],
+                             sc.view[r2], sc.rough[r2], sc.bounds_lo, sc.bounds_hi)
+    d = np.abs(logits.cpu().numpy()[r2] - lo)
+    log(f"object logits: max |d| {d.max():.3e} (logit scale {np.abs(lo).max():.3e})")
+    assert d.max() <= 2.0 ** -6 * max(1.0, np.abs(lo).max())
+
+
+def test_trained_proposal_beats_fixed_directions(torch_gpu):
+    """What the learned part gains: after online training on the tiny scene's geometry (the
+    benchmark's recipe, about a second on the GPU), proposal sampling at 32 directions has a lower error than the paper's fixed
+    Hammersley set at 32 directions and than uniform bins (the method without the network)."""
+    log("proposal training gain: 3000 steps, 50k held-out points")
+    import torch
+    from paper_2510_07729_amd import proposal
+    pool_sc = scenes.proposal_eval(262_144, seed=5)
+    ev_sc = scenes.proposal_eval(50_000, seed=0)
+    plan = gpu_plan(pool_sc)
+    tex, env = dev(pool_sc.texels), dev(pool_sc.env)
+    pool, ev = gpu_points(pool_sc), gpu_points(ev_sc)
+    mlp = sop().Mlp(dev(scenes.mlp_init(seed=0)), pool_sc.bounds_lo, pool_sc.bounds_hi)
+    losses = proposal.train(mlp, plan, tex, env, pool, 3000, batch=4096, lr=2e-3,
+                            log_every=750)
+    log(f"losses {losses}")
+    assert losses[-1] < losses[0] - 0.3
+    nb = sop().sop_knn(plan, ev, 4)
+    ref = sop().sop_shade(plan, tex, env, ev, 4096, nb=nb, seed=123)
+    mask = ev.rough >= 0.25
+
+    def rmse(x):
+        return float(torch.sqrt(torch.mean(((x - ref)[mask]) ** 2)))
+
+    ham = rmse(sop().sop_shade(plan, tex, env, ev, 32, nb=nb, seed=7))
+    probs = sop().sop_proposal_infer(mlp, ev)
+    prop = rmse(sop().sop_shade(plan, tex, env, ev, 32, nb=nb, seed=7, probs=probs))
+    uni = rmse(sop().sop_shade(plan, tex, env, ev, 32, nb=nb, seed=7,
+                               probs=torch.full_like(probs, 1.0 / 256)))
+    log(f"RMSE at 32 directions: Hammersley {ham:.4f}, uniform bins {uni:.4f}, "
+        f"trained proposal {prop:.4f}")
+    assert prop < 0.8 * ham and prop < 0.8 * uni
