@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
 // ------------------------------------------------------------------------------------------
 // per-texel ray traversal
 // ------------------------------------------------------------------------------------------
-constexpr int kBuf = 32;   // sorted candidate buffer per cell pass
+constexpr int kBuf = 24;   // sorted candidate buffer per cell pass
 
 __device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
   float px = 2.0f * u / (float)R - 1.0f, py = 2.0f * v / (float)R - 1.0f;
@@ -194,6 +194,34 @@ __device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
   }
   const float il = rsqrtf(px * px + py * py + z * z);
   return mk3(px * il, py * il, z * il);
+}
+
+// Response of a Gaussian (rows r0..r2 of S^-1 R^T with the mean in .w) on the ray o + t d
+// in FP64: t* = -(Mo . Md) / |Md|^2 and m^2 = |Mo + t* Md|^2 (Mo = M (o - mean)). The
+// composite step calls it again for the kept candidates, so alpha is recomputed bit for bit
+// instead of being carried through the candidate buffer.
+__device__ __forceinline__ double exact_tstar(const float4& r0, const float4& r1,
+                                              const float4& r2, const v3& o,
+                                              const double (&d64)[3], double& olx, double& oly,
+                                              double& olz, double& dlx, double& dly,
+                                              double& dlz) {
+  const double ox = (double)o.x - (double)r0.w, oy = (double)o.y - (double)r1.w,
+               oz = (double)o.z - (double)r2.w;
+  olx = fma((double)r0.x, ox, fma((double)r0.y, oy, (double)r0.z * oz));
+  oly = fma((double)r1.x, ox, fma((double)r1.y, oy, (double)r1.z * oz));
+  olz = fma((double)r2.x, ox, fma((double)r2.y, oy, (double)r2.z * oz));
+  dlx = fma((double)r0.x, d64[0], fma((double)r0.y, d64[1], (double)r0.z * d64[2]));
+  dly = fma((double)r1.x, d64[0], fma((double)r1.y, d64[1], (double)r1.z * d64[2]));
+  dlz = fma((double)r2.x, d64[0], fma((double)r2.y, d64[1], (double)r2.z * d64[2]));
+  return -(olx * dlx + oly * dly + olz * dlz) / (dlx * dlx + dly * dly + dlz * dlz);
+}
+
+__device__ __forceinline__ float exact_alpha(const BakeGrid& G, double tsd, double olx,
+                                             double oly, double olz, double dlx, double dly,
+                                             double dlz, float op) {
+  const double xx = fma(dlx, tsd, olx), xy = fma(dly, tsd, oly), xz = fma(dlz, tsd, olz);
+  const float m2 = (float)(xx * xx + xy * xy + xz * xz);
+  return fminf(G.alpha_max, op * expf(-0.5f * m2));
 }
 
 __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
@@ -305,9 +333,8 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
       uint64_t after = 0;      // keys <= after are done
       for (int round = 0; e1 > e0 && !done; ++round) {
         uint64_t key[kBuf];
-        float al[kBuf];
 #pragma unroll
-        for (int s = 0; s < kBuf; ++s) { key[s] = ~0ull; al[s] = 0.0f; }
+        for (int s = 0; s < kBuf; ++s) key[s] = ~0ull;
         // software pipeline: the record of entry e+1 and the index of entry e+2 are in
         // flight while entry e is tested
         int32_t gi_c = G.entries[e0];
@@ -333,47 +360,35 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
           if (tc + bs.y < t_lo || tc - bs.y >= t_hi) continue;
           const float op = gd[3].w;
           // exact test in FP64: t* and the Mahalanobis distance m^2 at t*
-          const double ox = (double)o.x - (double)r0.w, oy = (double)o.y - (double)r1.w,
-                       oz = (double)o.z - (double)r2.w;
-          const double olx = fma((double)r0.x, ox, fma((double)r0.y, oy, (double)r0.z * oz));
-          const double oly = fma((double)r1.x, ox, fma((double)r1.y, oy, (double)r1.z * oz));
-          const double olz = fma((double)r2.x, ox, fma((double)r2.y, oy, (double)r2.z * oz));
-          const double dlx =
-              fma((double)r0.x, d64[0], fma((double)r0.y, d64[1], (double)r0.z * d64[2]));
-          const double dly =
-              fma((double)r1.x, d64[0], fma((double)r1.y, d64[1], (double)r1.z * d64[2]));
-          const double dlz =
-              fma((double)r2.x, d64[0], fma((double)r2.y, d64[1], (double)r2.z * d64[2]));
-          const double tsd = -(olx * dlx + oly * dly + olz * dlz) / (dlx * dlx + dly * dly + dlz * dlz);
+          double olx, oly, olz, dlx, dly, dlz;
+          const double tsd = exact_tstar(r0, r1, r2, o, d64, olx, oly, olz, dlx, dly, dlz);
           if (!(tsd > (double)G.t_min && tsd >= (double)t_lo && tsd < (double)t_hi)) continue;
-          const double xx = fma(dlx, tsd, olx), xy = fma(dly, tsd, oly), xz = fma(dlz, tsd, olz);
-          const float m2 = (float)(xx * xx + xy * xy + xz * xz);
-          const float a = fminf(G.alpha_max, op * expf(-0.5f * m2));
+          const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, op);
           if (!(a >= G.alpha_min)) continue;
           const float ts = (float)tsd;
           uint64_t k = ((uint64_t)(uint32_t)__float_as_int(ts) << 32) | (uint32_t)gi;
           if (k <= after || k >= key[kBuf - 1]) continue;
-          float av = a;
 #pragma unroll
           for (int s = 0; s < kBuf; ++s) {      // sorted insertion, largest falls out
             const bool sw = k < key[s];
             const uint64_t kk = sw ? key[s] : k;
-            const float aa = sw ? al[s] : av;
             key[s] = sw ? k : key[s];
-            al[s] = sw ? av : al[s];
             k = kk;
-            av = aa;
           }
         }
         int used = 0;
 #pragma unroll
         for (int s = 0; s < kBuf; ++s) {
           if (key[s] == ~0ull || done) continue;
-          const float a = al[s];
+          const int32_t gi = (int32_t)(key[s] & 0xFFFFFFFFu);
+          const float4* gk = G.gdata + (size_t)kGRows * gi;
+          const float4 col = gk[3];
+          double olx, oly, olz, dlx, dly, dlz;
+          const double tsd = exact_tstar(gk[0], gk[1], gk[2], o, d64, olx, oly, olz, dlx, dly,
+                                         dlz);
+          const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, col.w);
           const float Tn = T * (1.0f - a);
           if (Tn < G.T_min) { done = true; continue; }
-          const int32_t gi = (int32_t)(key[s] & 0xFFFFFFFFu);
-          const float4 col = G.gdata[(size_t)kGRows * gi + 3];
           const float ts = __int_as_float((int)(key[s] >> 32));
           const float wgt = T * a;
           Cr += wgt * col.x;
