@@ -2,11 +2,11 @@
 
 One step = one pass of the whole path over the object workload: rebuild the probe grid,
 re-register the 100k Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays,
-probes traced in the probe grid's Morton order), order the 200k shading points and find their 8 nearest probes, shade them with 128
-directions (forward) and run the adjoint (backward) into the probe and environment
+probes traced in the probe grid's Morton order), order the 200k shading points and find
+their 8 nearest probes, shade them with 128 directions (forward) and run the adjoint (backward) into the probe and environment
 gradients; then run the proposal network on the 200k points, shade them again with 32
-proposal-sampled directions, and take one proposal training step (fresh bin targets for
-4096 points + Adam). value = shaded point-direction samples (N*S, S = 128) per second of the
+directions drawn from its bin distributions, and take one proposal training step (fresh
+bin targets for 4096 points + Adam). value = shaded point-direction samples (N*S, S = 128) per second of the
 whole step. After the timed region, the learned proposal's speedup at matched error is
 measured on the tiny scene's geometry (see proposal_study).
 
@@ -264,8 +264,8 @@ def main() -> int:
         "config": {"workload": "object_scene: bake 100k Gaussians into 4096 probes x 32x32 "
                                "texels, probe grid, kNN (K=8), shade fwd+bwd of 200k points "
                                "x 128 directions, env 256x512; proposal network on 200k "
-                               "points, proposal shade x 32 directions, one training step "
-                               "(4096 points)",
+                               "points, proposal shade x 32 directions, one proposal "
+                               "training step (4096 points)",
                    "points": N, "dirs": S, "k": K, "probes": P, "res": R, "gaussians": G},
         "fwd_bwd_samples_per_s": round(fb_rate, 1),
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
@@ -286,7 +286,8 @@ def proposal_study(torch, dev, steps: int) -> dict:
     RMSE is taken over the points with roughness >= 0.25, whose lobes the reference itself
     resolves (narrower lobes are not converged by 4096 uniform directions either). S* is the
     smallest proposal count whose RMSE reaches the Hammersley RMSE at 128 directions;
-    speedup = t(Hammersley 128) / (t(network) + t(proposal S*))."""
+    speedup = t(Hammersley 128) / (t(network) + t(proposal S*)); the single call that runs
+    the network inside the shading kernel is timed beside it."""
     import numpy as np
 
     from paper_2510_07729_amd import _lib as L
@@ -336,13 +337,16 @@ def proposal_study(torch, dev, steps: int) -> dict:
         ham[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
     probs, t_mlp = timed(lambda: sop.sop_proposal_infer(mlp, ev))
     prop = {}
-    for S in (8, 16, 32, 64):
+    for S in (8, 16, 24, 32, 64):
         out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7, probs=probs,
                                               mix_eps=MIX_EPS))
         prop[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
     target = ham[128]["rmse"]
     s_star = next((S for S in sorted(prop) if prop[S]["rmse"] <= target), None)
     speedup = (ham[128]["ms"] / (t_mlp + prop[s_star]["ms"])) if s_star else None
+    # the network evaluated inside the shading kernel (no probability array in memory)
+    _, t_fused = timed(lambda: sop.sop_shade(plan, tex, env, ev, s_star or 32, nb=nb, seed=7,
+                                             net=mlp, mix_eps=MIX_EPS))
     return {"workload": "tiny scene geometry, 200k held-out points, K=4, RMSE over "
                         "roughness >= 0.25 against 4096 Hammersley directions",
             "train_steps": steps, "train_batch": TRAIN_BATCH,
@@ -350,7 +354,8 @@ def proposal_study(torch, dev, steps: int) -> dict:
             "train_ms": round(train_ms, 1), "loss_trace": [round(x, 4) for x in losses],
             "mix_eps": MIX_EPS, "hammersley": ham, "proposal": prop,
             "network_ms": round(t_mlp, 4), "S_star": s_star,
-            "speedup_vs_hammersley_128": round(speedup, 3) if speedup else None}
+            "speedup_vs_hammersley_128": round(speedup, 3) if speedup else None,
+            "fused_ms_at_S_star": round(t_fused, 4)}
 
 
 def copy_calibration(torch, dev) -> int:

@@ -188,8 +188,12 @@ sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps, const sop
 
 typedef enum sop_sampler {
   SOP_SAMPLER_HAMMERSLEY = 0,     /* uniform hemisphere Hammersley set (Eq. 7)              */
-  SOP_SAMPLER_PROPOSAL = 1        /* per-point bin distributions (learned proposal below)  */
+  SOP_SAMPLER_PROPOSAL = 1,       /* per-point bin distributions given in opts.probs        */
+  SOP_SAMPLER_PROPOSAL_NET = 2    /* bin distributions of the network opts.net, evaluated
+                                     inside the shading call (they never reach memory)     */
 } sop_sampler;
+
+typedef struct sop_mlp sop_mlp;
 
 typedef struct sop_shade_opts {
   int32_t  n_dirs;               /* S, 1 <= S <= SOP_MAX_DIRS                             */
@@ -202,15 +206,19 @@ typedef struct sop_shade_opts {
   const float* probs;            /* SOP_SAMPLER_PROPOSAL: device [N,256] bin distributions
                                     (one row per point, any non-negative weights; values
                                     are clamped to [0,1], NaN counts as 0)                */
-  float    mix_eps;              /* SOP_SAMPLER_PROPOSAL: weight of the uniform-bin part of
-                                    the mixture, 0 <= mix_eps <= 1                         */
+  float    mix_eps;              /* SOP_SAMPLER_PROPOSAL(_NET): weight of the uniform-bin
+                                    part of the mixture, 0 <= mix_eps <= 1                 */
+  const sop_mlp* net;            /* SOP_SAMPLER_PROPOSAL_NET: the proposal network         */
 } sop_shade_opts;
 
 /* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL.
  * With SOP_SAMPLER_PROPOSAL the S directions of point i are drawn from its bin distribution
  * (see the learned direction proposal below) and rgb_i = (1/S) sum_j f L_i cos / pdf(w_j);
- * out_irradiance is then (1/S) sum_j L_i cos / pdf(w_j). The proposal sampler has no
- * adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. */
+ * out_irradiance is then (1/S) sum_j L_i cos / pdf(w_j). With SOP_SAMPLER_PROPOSAL_NET the
+ * distributions are the network's (opts->net), computed in the same kernel exactly as
+ * sop_proposal_infer computes them; the result equals that of SOP_SAMPLER_PROPOSAL with
+ * sop_proposal_infer's output up to the order of the per-point sums. The proposal samplers
+ * have no adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
                      const sop_points* pts, const sop_neighbors* nb,
                      const sop_shade_opts* opts, float* rgb,
@@ -342,12 +350,12 @@ sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n
 #define SOP_MLP_BINS 256
 #define SOP_MLP_PARAMS 41344          /* W1[320][64] b1[64] W2[64][64] b2[64] W3[64][256] b3[256] */
 
-typedef struct sop_mlp {
+struct sop_mlp {
   float* params;                 /* device [SOP_MLP_PARAMS] f32, row-major W[in][out]; read by
                                     inference, updated in place by a training step        */
   float  bounds_lo[3];           /* host: scene box mapped to [-1,1]^3 for the features   */
   float  bounds_hi[3];
-} sop_mlp;
+};
 
 typedef struct sop_adam {
   float   lr, beta1, beta2, eps;

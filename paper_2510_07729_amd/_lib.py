@@ -25,7 +25,7 @@ SOP_TEXEL_F16 = 1
 
 SOP_OP_KNN, SOP_OP_QUERY, SOP_OP_SHADE, SOP_OP_SHADE_BACKWARD = 0, 1, 2, 3
 SOP_OP_DUMP_INTEGRAND, SOP_OP_PROPOSAL_INFER, SOP_OP_PROPOSAL_TRAIN = 4, 5, 6
-SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL = 0, 1
+SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL, SOP_SAMPLER_PROPOSAL_NET = 0, 1, 2
 SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
 
 
@@ -55,7 +55,7 @@ class sop_neighbors(C.Structure):
 class sop_shade_opts(C.Structure):
     _fields_ = [("n_dirs", c_i32), ("k", c_i32), ("radius", c_f32), ("seed", c_u32),
                 ("rotate_per_point", c_i32), ("sampler", c_i32), ("out_irradiance", c_vp),
-                ("probs", c_vp), ("mix_eps", c_f32)]
+                ("probs", c_vp), ("mix_eps", c_f32), ("net", c_vp)]
 
 
 class sop_gaussians(C.Structure):

@@ -233,6 +233,7 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     return b.used;
   }
   if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD || op == SOP_OP_DUMP_INTEGRAND) {
+    if (op == SOP_OP_SHADE) (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
     (void)b.take<double4>((size_t)n_dirs);
     (void)b.take<double2>((size_t)env_w + 2);
     (void)b.take<double2>((size_t)env_h + 2);
@@ -468,6 +469,18 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
       return fail(SOP_ERR_INVALID_ARGUMENT, "probs is NULL or not 16-byte aligned");
     if (!(o->mix_eps >= 0.0f && o->mix_eps <= 1.0f))
       return fail(SOP_ERR_INVALID_ARGUMENT, "mix_eps out of [0, 1]");
+  } else if (o->sampler == SOP_SAMPLER_PROPOSAL_NET) {
+    if (!allow_proposal)
+      return fail(SOP_ERR_UNSUPPORTED, "the proposal sampler has no adjoint");
+    if (!o->net) return fail(SOP_ERR_INVALID_ARGUMENT, "net is NULL");
+    if (!o->net->params || !aligned(o->net->params, 16))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "net->params is NULL or not 16-byte aligned");
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(o->net->bounds_lo[c]) || !std::isfinite(o->net->bounds_hi[c]) ||
+          !(o->net->bounds_hi[c] > o->net->bounds_lo[c]))
+        return fail(SOP_ERR_INVALID_ARGUMENT, "net bounds must be finite with hi > lo");
+    if (!(o->mix_eps >= 0.0f && o->mix_eps <= 1.0f))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "mix_eps out of [0, 1]");
   } else if (o->sampler != SOP_SAMPLER_HAMMERSLEY) {
     return fail(SOP_ERR_UNSUPPORTED, "unknown sampler");
   }
@@ -525,11 +538,22 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   a.irr = opts->out_irradiance;
   int32_t kk;
   Bump b{(char*)ws, 0, ws_bytes};
+  uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
   if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
-  if (opts->sampler == SOP_SAMPLER_PROPOSAL) {
+  if (opts->sampler == SOP_SAMPLER_PROPOSAL_NET) {
+    a.mix_eps = opts->mix_eps;
+    a.mlp_params = opts->net->params;
+    a.mlp_frags = frags;
+    for (int c = 0; c < 3; ++c) {
+      a.mlp_lo[c] = opts->net->bounds_lo[c];
+      a.mlp_inv2[c] = 2.0f / (opts->net->bounds_hi[c] - opts->net->bounds_lo[c]);
+    }
+    SOP_HIP(sopk::launch_mlp_frags(opts->net->params, frags, s), "sop_shade");
+    SOP_HIP(sopk::launch_shade_prop_net(a, kk, maps->format, s), "sop_shade");
+  } else if (opts->sampler == SOP_SAMPLER_PROPOSAL) {
     a.probs = opts->probs;
     a.mix_eps = opts->mix_eps;
     SOP_HIP(sopk::launch_shade_prop(a, kk, maps->format, s), "sop_shade");

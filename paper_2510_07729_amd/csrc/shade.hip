@@ -8,6 +8,7 @@
 // direction are formed once and reused for all K probes, and the per-point sums are reduced
 // across the wavefront with DPP. The backward pass recomputes every sample instead of
 // storing per-sample fetches.
+#include "mlp_device.hpp"
 #include "sop_device.hpp"
 #include "sop_internal.hpp"
 
@@ -328,7 +329,8 @@ __device__ __forceinline__ uint64_t bin_masses(const ShadeArgs& a, int64_t p, bo
 }
 
 // bin of mass coordinate x < total: the largest b with cum[b] <= x
-__device__ __forceinline__ int find_bin(const uint64_t* cum, uint64_t x) {
+template <typename CumT>
+__device__ __forceinline__ int find_bin(const CumT* cum, uint64_t x) {
   int b = 0;
 #pragma unroll
   for (int step = 128; step >= 1; step >>= 1)
@@ -396,6 +398,126 @@ __global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) r3[c] = group_sum<L>(acc_e[c]) * scale;
     if (valid && li == 0) {
+      a.irr[3 * ps.p] = r3[0];
+      a.irr[3 * ps.p + 1] = r3[1];
+      a.irr[3 * ps.p + 2] = r3[2];
+    }
+  }
+}
+
+// Proposal shading with the network evaluated in the same kernel: a wavefront takes 16
+// points, runs the network on the matrix cores (the logits of point l%16 end in the four
+// lanes l%16 + 16g), turns them into bin masses exactly as the inference kernel and the
+// sampler above do, and then shades the 16 points with lane l%16 + 16g taking draws
+// g, g+4, ... of point l%16. The bin probabilities never leave the chip.
+template <int KT, typename TexT>
+__global__ __launch_bounds__(256) void k_shade_prop_net(ShadeArgs a, int32_t k) {
+  __shared__ uint32_t s_cum[kWavesPerBlock][16][SOP_MLP_BINS + 1];
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  if (tile * 16 >= a.n) return;
+  const int64_t slot = tile * 16 + r;
+  uint32_t* cum = s_cum[threadIdx.x >> 6][r];
+  PointState ps;
+  const bool valid = slot < a.n && load_point<false>(a, slot, ps);
+
+  // network forward of the 16 points and their bin probabilities
+  f32x4 prob[16];
+  {
+    FeatIn fi;
+    if (valid)
+      point_scalars(a.pos, a.nrm, a.view, a.cam, a.ppf, a.rough, a.mlp_lo, a.mlp_inv2, ps.p, fi);
+    else
+#pragma unroll
+      for (int c = 0; c < 10; ++c) fi.x[c] = 0.0f;
+    Fwd F;
+    forward_tile(a.mlp_params, a.mlp_frags, fi, lane, F, nullptr, 0, 0, false);
+    softmax_tile(F.z3);
+#pragma unroll
+    for (int mb = 0; mb < 16; ++mb) prob[mb] = F.z3[mb];
+  }
+  // integer masses into the point's LDS row (bin b = 16 mb + 4 g + t), then the prefix over
+  // bins: lane g of the point takes bins [64 g, 64 g + 64)
+  const float om = 1.0f - a.mix_eps, add = a.mix_eps * (1.0f / 256.0f);
+#pragma unroll
+  for (int mb = 0; mb < 16; ++mb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float q = prob[mb][t];
+      q = q > 0.0f ? fminf(q, 1.0f) : 0.0f;
+      cum[16 * mb + 4 * g + t + 1] = (uint32_t)floorf(__builtin_fmaf(om, q, add) * 16777216.0f);
+    }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t own = 0;
+  for (int b = 64 * g; b < 64 * g + 64; ++b) own += cum[b + 1];
+  uint32_t incl = own;
+  {
+    const uint32_t o1 = __shfl_up(incl, 16);
+    if (g >= 1) incl += o1;
+    const uint32_t o2 = __shfl_up(incl, 32);
+    if (g >= 2) incl += o2;
+  }
+  uint32_t total = __shfl(incl, 48 + r);
+  const bool fallback = total == 0;
+  if (fallback) total = SOP_MLP_BINS;
+  uint32_t run = fallback ? 64u * g : incl - own;
+  if (g == 0) cum[0] = 0;
+  for (int b = 64 * g; b < 64 * g + 64; ++b) {
+    run += fallback ? 1u : cum[b + 1];
+    cum[b + 1] = run;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  Neighbors<KT> nb;
+  float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
+  if (valid) {
+    nb.load(a, ps.p, k);
+    const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+    const uint32_t rot_v = hash24(sh, pi, 0, 2);
+    const double inv_total = 1.0 / (double)total;
+    const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+    for (int j = g; j < a.S; j += 4) {
+      const uint64_t rr = hash24(sh, pi, (uint32_t)j, 0);
+      const uint64_t x = ((uint64_t)j * total + ((rr * total) >> 24)) / (uint64_t)a.S;
+      const int b = find_bin(cum, x);
+      const uint64_t cb = cum[b + 1] - cum[b];
+      const double xu = ((double)(x - cum[b]) + 0.5) / (double)cb;
+      const uint32_t v24 = ((__builtin_bitreverse32((uint32_t)j) >> 8) + rot_v) & 0xFFFFFFu;
+      const double xv = ((double)v24 + 0.5) * 0x1p-24;
+      double wl[3];
+      const double l = cell_point(xu, xv, b, wl);
+      const float inv_pdf = (float)(1.0 / ((double)cb * inv_total * 128.0 * l * l * l));
+      Sample s;
+      world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
+      s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+      s.ct = (float)wl[2];
+      eval_at<KT, TexT>(a, ps, nb, k, s);
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+        acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li * inv_pdf;
+        acc_e[c] += Li * s.ct * inv_pdf;
+      }
+    }
+  }
+  const float scale = 1.0f / (float)a.S;
+  float r3[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r3[c] = point_sum(acc[c]) * scale;
+  if (valid && g == 0) {
+    a.rgb[3 * ps.p] = r3[0];
+    a.rgb[3 * ps.p + 1] = r3[1];
+    a.rgb[3 * ps.p + 2] = r3[2];
+  }
+  if (a.irr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r3[c] = point_sum(acc_e[c]) * scale;
+    if (valid && g == 0) {
       a.irr[3 * ps.p] = r3[0];
       a.irr[3 * ps.p + 1] = r3[1];
       a.irr[3 * ps.p + 2] = r3[2];
@@ -812,6 +934,28 @@ static hipError_t dispatch_prop(int mode, const ShadeArgs& a, int32_t k, int32_t
 
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   return dispatch_prop(0, a, k, format, s);
+}
+
+template <int KT>
+static void launch_prop_net_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const int64_t tiles = (a.n + 15) / 16;
+  const dim3 grid((unsigned)((tiles + kWavesPerBlock - 1) / kWavesPerBlock));
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shade_prop_net<KT, uint2>), grid, dim3(256), 0, s, a, k);
+  else
+    hipLaunchKernelGGL((k_shade_prop_net<KT, float4>), grid, dim3(256), 0, s, a, k);
+}
+
+hipError_t launch_shade_prop_net(const ShadeArgs& a, int32_t k, int32_t format,
+                                 hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (!a.mlp_params || !a.mlp_frags) return hipErrorInvalidValue;
+  switch (k) {
+    case 4: launch_prop_net_kt<4>(a, k, format, s); break;
+    case 8: launch_prop_net_kt<8>(a, k, format, s); break;
+    default: launch_prop_net_kt<0>(a, k, format, s); break;
+  }
+  return hipGetLastError();
 }
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   return dispatch_prop(1, a, k, format, s);

@@ -88,6 +88,9 @@ struct ShadeArgs {
   const float* probs;       // [n,256] bin distributions
   float mix_eps;
   float* targets;           // [n,256] bin integrals (integrand dump)
+  const float* mlp_params;  // fused proposal: network parameters, bf16 fragments, feature box
+  const uint16_t* mlp_frags;
+  float mlp_lo[3], mlp_inv2[3];
   int32_t npb;              // draws per bin (integrand dump)
   // adjoint
   const float* grad;
@@ -133,6 +136,8 @@ hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipSt
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+hipError_t launch_shade_prop_net(const ShadeArgs& a, int32_t k, int32_t format,
+                                 hipStream_t s);
 hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
                         int32_t D, float* Lin, float* O, hipStream_t s);
 

@@ -288,3 +288,26 @@ def test_trained_proposal_beats_fixed_directions(torch_gpu):
     log(f"RMSE at 32 directions: Hammersley {ham:.4f}, uniform bins {uni:.4f}, "
         f"trained proposal {prop:.4f}")
     assert prop < 0.8 * ham and prop < 0.8 * uni
+
+
+@pytest.mark.parametrize("n,k,S", [(509, 4, 32), (1000, 8, 7), (16, 4, 64), (1, 8, 3)])
+def test_fused_network_sampler_matches_two_steps(torch_gpu, n, k, S):
+    """The network evaluated inside the shading kernel gives the two-step result (inference,
+    then shading with its probabilities) up to the order of the per-point sums."""
+    log(f"fused proposal shading: N={n} K={k} S={S}")
+    import torch
+    sc = scenes.tiny_shade(n_points=n, seed=3)
+    mlp = sop().Mlp(dev(scenes.mlp_init(seed=5)), sc.bounds_lo, sc.bounds_hi)
+    pts = gpu_points(sc)
+    plan = gpu_plan(sc)
+    nb = sop().sop_knn(plan, pts, k)
+    probs = sop().sop_proposal_infer(mlp, pts)
+    tex, env = dev(sc.texels), dev(sc.env)
+    two, two_e = sop().sop_shade(plan, tex, env, pts, S, nb=nb, seed=9, irradiance=True,
+                                 probs=probs, mix_eps=0.1)
+    one, one_e = sop().sop_shade(plan, tex, env, pts, S, nb=nb, seed=9, irradiance=True,
+                                 net=mlp, mix_eps=0.1)
+    torch.cuda.synchronize()
+    assert report("fused vs two-step rgb", parity_err(one.cpu().numpy(), two.cpu().numpy())) <= 1e-5
+    assert report("fused vs two-step irradiance",
+                  parity_err(one_e.cpu().numpy(), two_e.cpu().numpy())) <= 1e-5
