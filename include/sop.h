@@ -279,7 +279,7 @@ typedef struct sop_gaussians {
 } sop_gaussians;
 
 typedef struct sop_bake_opts {
-  float t_min;                   /* default 0                                             */
+  float t_min;                   /* default 0; >= 0 (rays start at the probe)             */
   float alpha_min;               /* default 1/255                                         */
   float alpha_max;               /* default 0.99                                          */
   float T_min;                   /* default 1e-4                                          */

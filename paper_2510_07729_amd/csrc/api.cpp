@@ -884,7 +884,8 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   if (st != SOP_OK) return st;
   const sop_bake_opts o = resolve_bake_opts(opts);
   if (!(o.alpha_min > 0.0f) || !(o.alpha_max >= o.alpha_min) || !(o.alpha_max < 1.0f) ||
-      !(o.T_min > 0.0f) || !std::isfinite(o.t_min) || !(o.cell_scale >= 0.0f))
+      !(o.T_min > 0.0f) || !(o.t_min >= 0.0f) || !std::isfinite(o.t_min) ||
+      !(o.cell_scale >= 0.0f))
     return fail(SOP_ERR_INVALID_ARGUMENT, "bake options out of range");
   const hipStream_t s = (hipStream_t)stream;
   sop_bake_plan* pl = new (std::nothrow) sop_bake_plan();

@@ -6,11 +6,13 @@
 // opacity * exp(-m^2/2) can reach alpha_min) may overlap: the cells of its axis-aligned box
 // that also pass a separating-axis test along the ellipsoid's own axes, padded for FP32
 // rounding.
-// One thread traces one texel's ray; a wavefront covers an 8x8 texel tile of one probe so
+// Four lanes trace one texel's ray; a wavefront covers a 4x4 texel block of one probe so
 // that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
-// composited in the cell whose t-window [t_enter, t_exit) holds its t*, and within a cell
-// candidates are taken in ascending (t*, index) through a small sorted register buffer
-// (refilled from the cell when it overflows), so the global order is ascending (t*, index).
+// composited in the cell whose t-window [t_enter, t_exit) holds its t*. Within a cell the
+// four lanes split the candidates, each keeping its smallest (t*, index) keys in a sorted
+// register buffer; the buffers are merged in ascending key order while compositing (and
+// the cell is taken again above the largest key that is known complete when a buffer
+// overflowed), so the global order is ascending (t*, index).
 #include <float.h>
 
 #include "sop_device.hpp"
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_gauss_prep(sop_gaussians g, float alpha
   const float mm = sqrtf(m2max);
   // bounding sphere of the cut-off ellipsoid, padded like the box below
   const float rb = (mm * fmaxf(s0, fmaxf(s1, s2))) * 1.002f + 1e-5f;
-  gd[4] = make_float4(rb * rb, rb, mm, 0.0f);
+  gd[4] = make_float4(rb * rb, rb, mm, op);
   float hx = mm * sqrtf(R00 * R00 * s0 * s0 + R01 * R01 * s1 * s1 + R02 * R02 * s2 * s2);
   float hy = mm * sqrtf(R10 * R10 * s0 * s0 + R11 * R11 * s1 * s1 + R12 * R12 * s2 * s2);
   float hz = mm * sqrtf(R20 * R20 * s0 * s0 + R21 * R21 * s1 * s1 + R22 * R22 * s2 * s2);
@@ -181,7 +183,6 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
 // ------------------------------------------------------------------------------------------
 // per-texel ray traversal
 // ------------------------------------------------------------------------------------------
-constexpr int kBuf = 24;   // sorted candidate buffer per cell pass
 
 __device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
   float px = 2.0f * u / (float)R - 1.0f, py = 2.0f * v / (float)R - 1.0f;
@@ -224,31 +225,65 @@ __device__ __forceinline__ float exact_alpha(const BakeGrid& G, double tsd, doub
   return fminf(G.alpha_max, op * expf(-0.5f * m2));
 }
 
+constexpr int kLpr = 4;    // lanes that trace one ray
+constexpr int kNb = 20;    // sorted candidate keys per lane
+
+// A candidate key (t* bits, Gaussian index) read as the bits of an FP64 number: t* > 0 is a
+// finite float, so the number is finite and non-negative and the order of the numbers is
+// the order of the 64-bit keys; min/max of two keys are single FP64 instructions.
+constexpr double kNone = DBL_MAX;   // above every key
+
+__device__ __forceinline__ double make_key(float ts, int32_t gi) {
+  return __longlong_as_double(
+      (long long)(((uint64_t)(uint32_t)__float_as_int(ts) << 32) | (uint32_t)gi));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// minimum over the kLpr consecutive lanes that trace one ray (DPP quad swaps, then the
+// half-row and row mirrors for groups of 8 and 16)
+__device__ __forceinline__ double ray_min(double x) {
+  if constexpr (kLpr >= 2) x = fmin(x, dpp_f64<0xB1>(x));
+  if constexpr (kLpr >= 4) x = fmin(x, dpp_f64<0x4E>(x));
+  if constexpr (kLpr >= 8) x = fmin(x, dpp_f64<0x141>(x));
+  if constexpr (kLpr >= 16) x = fmin(x, dpp_f64<0x140>(x));
+  return x;
+}
+
 __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
                                               int32_t R, float* texels, float* depth,
                                               const int4* order) {
-  // a wavefront covers an 8x8 tile of one probe's texels; consecutive workgroups take
-  // consecutive probes of the order, so the workgroups in flight on all dies trace rays from
-  // one neighbourhood of probes and share the Gaussians those rays meet in cache
+  // kLpr lanes trace one ray and split each cell's candidates between them; a wavefront
+  // holds 64/kLpr rays of one probe, taken in Z order inside 8x8 texel tiles so that they
+  // stay coherent; consecutive workgroups take consecutive probes of the order
   const int32_t tiles_x = (R + 7) >> 3;
-  const int32_t tiles = tiles_x * tiles_x;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wave >= (int64_t)P * tiles) return;
-  const int32_t slot = (int32_t)(wave / tiles);
-  // probes in the given order (the cell-major Morton order of a probe plan), else as stored
+  const int64_t per_probe = (int64_t)tiles_x * tiles_x * 64;
+  const int lane = threadIdx.x & 63;
+  const int g = lane & (kLpr - 1);
+  const int64_t ray = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / kLpr) + lane / kLpr;
+  if (ray >= (int64_t)P * per_probe) return;      // whole groups leave together
+  const int32_t slot = (int32_t)(ray / per_probe);
   const int32_t p = order ? order[slot].w : slot;
   if ((uint32_t)p >= (uint32_t)P) return;
-  const int32_t tile = (int32_t)(wave % tiles);
-  const int lane = threadIdx.x & 63;
-  const int32_t ti = (tile % tiles_x) * 8 + (lane & 7);
-  const int32_t tj = (tile / tiles_x) * 8 + (lane >> 3);
+  const int32_t within = (int32_t)(ray % per_probe);
+  const int32_t tile = within >> 6, q = within & 63;
+  const int32_t ti = (tile % tiles_x) * 8 + ((q & 1) | ((q >> 1) & 2) | ((q >> 2) & 4));
+  const int32_t tj = (tile / tiles_x) * 8 + (((q >> 1) & 1) | ((q >> 2) & 2) | ((q >> 3) & 4));
   if (ti >= R || tj >= R) return;
   const size_t texel = (size_t)p * R * R + (size_t)tj * R + ti;
 
   if (G.overflow && *G.overflow) {
-    const float nan = __int_as_float(0x7FC00000);
-    reinterpret_cast<float4*>(texels)[texel] = make_float4(nan, nan, nan, nan);
-    if (depth) depth[texel] = nan;
+    if (g == 0) {
+      const float nan = __int_as_float(0x7FC00000);
+      reinterpret_cast<float4*>(texels)[texel] = make_float4(nan, nan, nan, nan);
+      if (depth) depth[texel] = nan;
+    }
     return;
   }
 
@@ -329,58 +364,60 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
       const int32_t e0 = min(G.cell_start[cell], G.capacity);
       const int32_t e1 = min(G.cell_start[cell + 1], G.capacity);
 
-      // candidates of this cell in ascending (t*, index), kBuf at a time
-      uint64_t after = 0;      // keys <= after are done
+      // candidates of this cell in ascending (t*, index): each lane of the ray tests every
+      // kLpr-th entry into its own sorted buffer; the buffers are merged when compositing
+      double after = -1.0;     // keys <= after are done
       for (int round = 0; e1 > e0 && !done; ++round) {
-        uint64_t key[kBuf];
+        double key[kNb];
 #pragma unroll
-        for (int s = 0; s < kBuf; ++s) key[s] = ~0ull;
-        // software pipeline: the record of entry e+1 and the index of entry e+2 are in
-        // flight while entry e is tested
-        int32_t gi_c = G.entries[e0];
+        for (int s = 0; s < kNb; ++s) key[s] = kNone;
+        int32_t e = e0 + g;
+        // software pipeline: the record of entry e+kLpr and the index of entry e+2kLpr are
+        // in flight while entry e is tested
+        int32_t gi_c = e < e1 ? G.entries[e] : 0;
         float4 p0, p1, p2, p4;
-        {
+        if (e < e1) {
           const float4* gq = G.gdata + (size_t)kGRows * gi_c;
           p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
         }
-        int32_t gi_n = e0 + 1 < e1 ? G.entries[e0 + 1] : gi_c;
-        for (int32_t e = e0; e < e1; ++e) {
+        int32_t gi_n = e + kLpr < e1 ? G.entries[e + kLpr] : gi_c;
+        for (; e < e1; e += kLpr) {
           const int32_t gi = gi_c;
           const float4 r0 = p0, r1 = p1, r2 = p2, bs = p4;
-          const float4* gd = G.gdata + (size_t)kGRows * gi;
-          if (e + 1 < e1) {
+          if (e + kLpr < e1) {
             gi_c = gi_n;
             const float4* gq = G.gdata + (size_t)kGRows * gi_c;
             p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
-            if (e + 2 < e1) gi_n = G.entries[e + 2];
+            if (e + 2 * kLpr < e1) gi_n = G.entries[e + 2 * kLpr];
           }
           const v3 om = mk3(o.x - r0.w, o.y - r1.w, o.z - r2.w);
           const float tc = -dot(om, d);
           if (dot(om, om) - tc * tc > bs.x) continue;
           if (tc + bs.y < t_lo || tc - bs.y >= t_hi) continue;
-          const float op = gd[3].w;
           // exact test in FP64: t* and the Mahalanobis distance m^2 at t*
           double olx, oly, olz, dlx, dly, dlz;
           const double tsd = exact_tstar(r0, r1, r2, o, d64, olx, oly, olz, dlx, dly, dlz);
           if (!(tsd > (double)G.t_min && tsd >= (double)t_lo && tsd < (double)t_hi)) continue;
-          const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, op);
+          const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, bs.w);
           if (!(a >= G.alpha_min)) continue;
-          const float ts = (float)tsd;
-          uint64_t k = ((uint64_t)(uint32_t)__float_as_int(ts) << 32) | (uint32_t)gi;
-          if (k <= after || k >= key[kBuf - 1]) continue;
+          double k = make_key((float)tsd, gi);
+          if (k <= after || k >= key[kNb - 1]) continue;
 #pragma unroll
-          for (int s = 0; s < kBuf; ++s) {      // sorted insertion, largest falls out
-            const bool sw = k < key[s];
-            const uint64_t kk = sw ? key[s] : k;
-            key[s] = sw ? k : key[s];
-            k = kk;
+          for (int s = 0; s < kNb; ++s) {      // sorted insertion, largest falls out
+            const double lo = fmin(k, key[s]);
+            k = fmax(k, key[s]);
+            key[s] = lo;
           }
         }
-        int used = 0;
-#pragma unroll
-        for (int s = 0; s < kBuf; ++s) {
-          if (key[s] == ~0ull || done) continue;
-          const int32_t gi = (int32_t)(key[s] & 0xFFFFFFFFu);
+        // every key of the cell up to `bound` is held by some lane: a full lane dropped only
+        // keys above its own largest one
+        const double bound = ray_min(key[kNb - 1]);
+        for (;;) {
+          const double head = key[0];
+          const double m = ray_min(head);
+          if (m == kNone || m > bound) break;
+          const uint64_t mb = (uint64_t)__double_as_longlong(m);
+          const int32_t gi = (int32_t)(mb & 0xFFFFFFFFu);
           const float4* gk = G.gdata + (size_t)kGRows * gi;
           const float4 col = gk[3];
           double olx, oly, olz, dlx, dly, dlz;
@@ -388,8 +425,8 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
                                          dlz);
           const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, col.w);
           const float Tn = T * (1.0f - a);
-          if (Tn < G.T_min) { done = true; continue; }
-          const float ts = __int_as_float((int)(key[s] >> 32));
+          if (Tn < G.T_min) { done = true; break; }
+          const float ts = __int_as_float((int)(mb >> 32));
           const float wgt = T * a;
           Cr += wgt * col.x;
           Cg += wgt * col.y;
@@ -397,19 +434,24 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
           Dp += wgt * ts;
           Wt += wgt;
           T = Tn;
-          ++used;
+          if (head == m) {                     // the lane that held it moves to its next key
+#pragma unroll
+            for (int s = 0; s < kNb - 1; ++s) key[s] = key[s + 1];
+            key[kNb - 1] = kNone;
+          }
         }
-        if (key[kBuf - 1] == ~0ull) break;     // the cell had fewer than kBuf left
-        after = key[kBuf - 1];
-        (void)used;
+        if (bound == kNone) break;             // no lane dropped a key: the cell is finished
+        after = bound;
       }
       if (last) break;
       t_lo = t_exit;
       c[axis] += step[axis];
     }
   }
-  reinterpret_cast<float4*>(texels)[texel] = make_float4(Cr, Cg, Cb, Wt);
-  if (depth) depth[texel] = Wt > 0.0f ? Dp / Wt : 0.0f;
+  if (g == 0) {
+    reinterpret_cast<float4*>(texels)[texel] = make_float4(Cr, Cg, Cb, Wt);
+    if (depth) depth[texel] = Wt > 0.0f ? Dp / Wt : 0.0f;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -445,7 +487,8 @@ hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_
 hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
                        float* texels, float* depth, const int4* order, hipStream_t s) {
   const int64_t tiles = (int64_t)((R + 7) / 8) * ((R + 7) / 8);
-  const int64_t waves = (int64_t)P * tiles;
+  const int64_t rays = (int64_t)P * tiles * 64;
+  const int64_t waves = (rays + (64 / kLpr) - 1) / (64 / kLpr);
   if (waves == 0) return hipSuccess;
   const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_bake, dim3((unsigned)blocks), dim3(256), 0, s, G, probe_pos, P, R,

@@ -108,6 +108,9 @@ def test_bake_plan_validation():
     assert lib.sop_bake_plan_create(C.byref(g), C.byref(o), None, C.byref(h)) == \
         L.SOP_ERR_INVALID_ARGUMENT
     assert "bake options" in lib.sop_last_error().decode()
+    o = L.sop_bake_opts(-1e-3, 1 / 255, 0.99, 1e-4, 0.0)   # rays start at the probe: t_min >= 0
+    assert lib.sop_bake_plan_create(C.byref(g), C.byref(o), None, C.byref(h)) == \
+        L.SOP_ERR_INVALID_ARGUMENT
 
 
 def test_errors_are_thread_local():
