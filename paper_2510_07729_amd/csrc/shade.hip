@@ -706,12 +706,60 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
 // (v = t + kBatchThreads * i) and adds it to g_tex[k] with atomics that are coalesced
 // (consecutive lanes, consecutive words). This replaces K*4*4 scattered atomics per
 // sample by about (distinct probes / kBatch) * res^2 * 4 coalesced atomics per point.
+// The environment adjoint of a sample covers two rows of its bilinear footprint, each two
+// adjacent texels = six consecutive floats (a "run"). Scattered one float per lane, every
+// atomic instruction touches 64 cache lines; instead each wavefront stages the runs of 32
+// samples in LDS and adds them with six consecutive lanes per run, about a tenth of the
+// lines per instruction.
 // ------------------------------------------------------------------------------------------
 constexpr int kBatch = 8;
 constexpr int kBatchThreads = kBatch * 64;
 constexpr int kMaxRes = 32;
 constexpr int kVPT = kMaxRes * kMaxRes * 4 / kBatchThreads;   // values per thread (8)
 constexpr int kMaxEntries = kBatch * 16;                      // (point, neighbour) pairs
+constexpr int kEnvRuns = 64;                                  // staged runs per wavefront
+
+struct EnvRun {
+  int32_t b0, b1;     // float offsets of the run's two texels in g_env (-1: no run)
+  float v[6];         // their three channel values each
+};
+
+// Stages the environment adjoint of the lanes [32h, 32h + 32) of the wavefront and adds it
+// to g_env; every lane of the wavefront calls it (lanes without a sample pass valid=false).
+__device__ __forceinline__ void env_runs_flush(float* g_env, EnvRun* run, int lane, int h,
+                                               bool valid, const Sample& s,
+                                               const SampleAdj& r) {
+  if ((lane >> 5) == h) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      EnvRun& e = run[(lane & 31) * 2 + q];
+      if (valid) {
+        e.b0 = s.et.off[2 * q] * 3;
+        e.b1 = s.et.off[2 * q + 1] * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          e.v[c] = s.et.w[2 * q] * r.ge[c];
+          e.v[3 + c] = s.et.w[2 * q + 1] * r.ge[c];
+        }
+      } else {
+        e.b0 = -1;
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int sub = lane / 6, comp = lane - 6 * sub;        // lanes 60..63 idle
+  for (int q0 = 0; q0 < kEnvRuns; q0 += 10) {
+    const int q = q0 + sub;
+    if (lane < 60 && q < kEnvRuns) {
+      const EnvRun& e = run[q];
+      if (e.b0 >= 0)
+        unsafeAtomicAdd(g_env + (comp < 3 ? e.b0 + comp : e.b1 + comp - 3), e.v[comp]);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 template <int KT, typename TexT>
 __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a, int32_t k) {
@@ -725,6 +773,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
   int32_t* erank = uni + kMaxEntries;                   // [kMaxEntries] slot of a leader
   float* W = reinterpret_cast<float*>(erank + kMaxEntries);     // [kMaxEntries][kBatch]
   int32_t* misc = reinterpret_cast<int32_t*>(W + kMaxEntries * kBatch);  // [1]
+  EnvRun* runs = reinterpret_cast<EnvRun*>(
+      (reinterpret_cast<uintptr_t>(misc + 1) + 15) & ~(uintptr_t)15);   // [kBatch][kEnvRuns]
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -790,11 +840,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
         const float g[3] = {a.grad[3 * ps.p], a.grad[3 * ps.p + 1], a.grad[3 * ps.p + 2]};
         float ga[3] = {0.0f, 0.0f, 0.0f}, gr = 0.0f, gm = 0.0f;
         float* Hb = H + b * MV;
-        for (int j0 = 0; j0 < a.S; j0 += 64) {
+        EnvRun* rb = runs + b * kEnvRuns;
+        for (int j0 = 0; j0 < a.S; j0 += 64) {     // uniform over the wavefront
           const int j = j0 + lane;
+          Sample s;
+          SampleAdj r;
           if (j < a.S) {
-            Sample s;
-            SampleAdj r;
             sample_adjoint<KT, TexT>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
@@ -804,7 +855,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
               atomicAdd(dst + 2, s.tt.w[t] * r.gl[2]);
               atomicAdd(dst + 3, s.tt.w[t] * r.go);
             }
-            if (a.g_env) scatter_env(a, s, r);
+          }
+          if (a.g_env) {
+            env_runs_flush(a.g_env, rb, lane, 0, j < a.S, s, r);
+            env_runs_flush(a.g_env, rb, lane, 1, j < a.S, s, r);
           }
         }
         const float v0 = wave_sum(ga[0]) * a.scale, v1 = wave_sum(ga[1]) * a.scale,
@@ -1004,7 +1058,7 @@ hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipSt
 }
 size_t batched_lds_bytes(int32_t R) {
   return (size_t)kBatch * R * R * 4 * sizeof(float) + 5 * kMaxEntries * 4 +
-         (size_t)kMaxEntries * kBatch * 4 + 4;
+         (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kEnvRuns * sizeof(EnvRun);
 }
 
 template <int KT>
