@@ -9,10 +9,13 @@
 // Four lanes trace one texel's ray; a wavefront covers a 4x4 texel block of one probe so
 // that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
 // composited in the cell whose t-window [t_enter, t_exit) holds its t*. Within a cell the
-// four lanes split the candidates, each keeping its smallest (t*, index) keys in a sorted
-// register buffer; the buffers are merged in ascending key order while compositing (and
-// the cell is taken again above the largest key that is known complete when a buffer
-// overflowed), so the global order is ascending (t*, index).
+// four lanes split the candidates. Each lane first screens its candidates in FP32 (t* in
+// the window and m^2 under the cut-off, both with margins far above the FP32 error) and
+// keeps the survivors in LDS, then runs the exact FP64 test on those only, so the FP64
+// work is done for about one candidate in six and by all lanes together. Accepted keys
+// (t*, index) go to a sorted register buffer per lane; the buffers are merged in ascending
+// key order while compositing (and the cell is taken again above the largest key that is
+// known complete when a buffer overflowed), so the global order is ascending (t*, index).
 #include <float.h>
 
 #include "sop_device.hpp"
@@ -227,6 +230,11 @@ __device__ __forceinline__ float exact_alpha(const BakeGrid& G, double tsd, doub
 
 constexpr int kLpr = 4;    // lanes that trace one ray
 constexpr int kNb = 20;    // sorted candidate keys per lane
+constexpr int kCap = 32;   // candidates a lane keeps per screening pass
+// screening margins: |t*_32 - t*| < kScreenT (1 + |t*|) and |m^2_32 - m^2| < kScreenM (1 + m^2)
+// hold with a wide margin (measured: 4e-7 and 8e-5 on the object workload)
+constexpr float kScreenT = 1e-4f;
+constexpr float kScreenM = 5e-2f;
 
 // A candidate key (t* bits, Gaussian index) read as the bits of an FP64 number: t* > 0 is a
 // finite float, so the number is finite and non-negative and the order of the numbers is
@@ -287,6 +295,8 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
     return;
   }
 
+  __shared__ int32_t screened[4][kCap][64];      // per wavefront: kept candidates per lane
+  int32_t* mylist = &screened[threadIdx.x >> 6][0][lane];
   const v3 o = mk3(probe_pos[3 * p], probe_pos[3 * p + 1], probe_pos[3 * p + 2]);
   // ray direction in FP64 (the candidate test below runs in FP64: a Gaussian of scale 0.01
   // one unit away turns a 1e-7 direction error into 1e-5 in its Mahalanobis distance);
@@ -372,42 +382,69 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
 #pragma unroll
         for (int s = 0; s < kNb; ++s) key[s] = kNone;
         int32_t e = e0 + g;
-        // software pipeline: the record of entry e+kLpr and the index of entry e+2kLpr are
-        // in flight while entry e is tested
-        int32_t gi_c = e < e1 ? G.entries[e] : 0;
-        float4 p0, p1, p2, p4;
-        if (e < e1) {
-          const float4* gq = G.gdata + (size_t)kGRows * gi_c;
-          p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
-        }
-        int32_t gi_n = e + kLpr < e1 ? G.entries[e + kLpr] : gi_c;
-        for (; e < e1; e += kLpr) {
-          const int32_t gi = gi_c;
-          const float4 r0 = p0, r1 = p1, r2 = p2, bs = p4;
-          if (e + kLpr < e1) {
-            gi_c = gi_n;
-            const float4* gq = G.gdata + (size_t)kGRows * gi_c;
-            p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; p4 = gq[4];
-            if (e + 2 * kLpr < e1) gi_n = G.entries[e + 2 * kLpr];
+        for (;;) {
+          // pass 1: an FP32 screen of t* and m^2 with wide margins keeps the candidates the
+          // FP64 test could accept (their indices go to this lane's LDS list)
+          int n = 0;
+          {
+            int32_t gi_c = e < e1 ? G.entries[e] : 0;
+            float4 p0, p1, p2;
+            float pm = 0.0f;
+            if (e < e1) {
+              const float4* gq = G.gdata + (size_t)kGRows * gi_c;
+              p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; pm = gq[4].z;
+            }
+            int32_t gi_n = e + kLpr < e1 ? G.entries[e + kLpr] : gi_c;
+            for (; e < e1 && n < kCap; e += kLpr) {
+              const int32_t gi = gi_c;
+              const float4 r0 = p0, r1 = p1, r2 = p2;
+              const float mmv = pm;
+              if (e + kLpr < e1) {
+                gi_c = gi_n;
+                const float4* gq = G.gdata + (size_t)kGRows * gi_c;
+                p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; pm = gq[4].z;
+                if (e + 2 * kLpr < e1) gi_n = G.entries[e + 2 * kLpr];
+              }
+              const float ox = o.x - r0.w, oy = o.y - r1.w, oz = o.z - r2.w;
+              const float ux = fmaf(r0.x, ox, fmaf(r0.y, oy, r0.z * oz));
+              const float uy = fmaf(r1.x, ox, fmaf(r1.y, oy, r1.z * oz));
+              const float uz = fmaf(r2.x, ox, fmaf(r2.y, oy, r2.z * oz));
+              const float wx = fmaf(r0.x, d.x, fmaf(r0.y, d.y, r0.z * d.z));
+              const float wy = fmaf(r1.x, d.x, fmaf(r1.y, d.y, r1.z * d.z));
+              const float wz = fmaf(r2.x, d.x, fmaf(r2.y, d.y, r2.z * d.z));
+              const float ww = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+              const float uw = fmaf(ux, wx, fmaf(uy, wy, uz * wz));
+              const float t32 = -uw * __builtin_amdgcn_rcpf(ww);
+              const float mt = kScreenT * (1.0f + fabsf(t32));
+              if (!(t32 > G.t_min - mt && t32 >= t_lo - mt && t32 < t_hi + mt)) continue;
+              const float rx = fmaf(wx, t32, ux), ry = fmaf(wy, t32, uy), rz = fmaf(wz, t32, uz);
+              const float m2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+              if (!(m2 <= fmaf(mmv * mmv, 1.0f + kScreenM, kScreenM))) continue;
+              mylist[n * 64] = gi;
+              ++n;
+            }
           }
-          const v3 om = mk3(o.x - r0.w, o.y - r1.w, o.z - r2.w);
-          const float tc = -dot(om, d);
-          if (dot(om, om) - tc * tc > bs.x) continue;
-          if (tc + bs.y < t_lo || tc - bs.y >= t_hi) continue;
-          // exact test in FP64: t* and the Mahalanobis distance m^2 at t*
-          double olx, oly, olz, dlx, dly, dlz;
-          const double tsd = exact_tstar(r0, r1, r2, o, d64, olx, oly, olz, dlx, dly, dlz);
-          if (!(tsd > (double)G.t_min && tsd >= (double)t_lo && tsd < (double)t_hi)) continue;
-          const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, bs.w);
-          if (!(a >= G.alpha_min)) continue;
-          double k = make_key((float)tsd, gi);
-          if (k <= after || k >= key[kNb - 1]) continue;
+          // pass 2: the exact FP64 test of the kept candidates
+          for (int i = 0; i < n; ++i) {
+            const int32_t gi = mylist[i * 64];
+            const float4* gq = G.gdata + (size_t)kGRows * gi;
+            const float4 r0 = gq[0], r1 = gq[1], r2 = gq[2];
+            const float op = gq[4].w;
+            double olx, oly, olz, dlx, dly, dlz;
+            const double tsd = exact_tstar(r0, r1, r2, o, d64, olx, oly, olz, dlx, dly, dlz);
+            if (!(tsd > (double)G.t_min && tsd >= (double)t_lo && tsd < (double)t_hi)) continue;
+            const float a = exact_alpha(G, tsd, olx, oly, olz, dlx, dly, dlz, op);
+            if (!(a >= G.alpha_min)) continue;
+            double k = make_key((float)tsd, gi);
+            if (k <= after || k >= key[kNb - 1]) continue;
 #pragma unroll
-          for (int s = 0; s < kNb; ++s) {      // sorted insertion, largest falls out
-            const double lo = fmin(k, key[s]);
-            k = fmax(k, key[s]);
-            key[s] = lo;
+            for (int s = 0; s < kNb; ++s) {    // sorted insertion, largest falls out
+              const double lo = fmin(k, key[s]);
+              k = fmax(k, key[s]);
+              key[s] = lo;
+            }
           }
+          if (!(e < e1)) break;
         }
         // every key of the cell up to `bound` is held by some lane: a full lane dropped only
         // keys above its own largest one

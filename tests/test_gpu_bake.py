@@ -48,6 +48,37 @@ def test_bake_small_scene_all_rays(torch_gpu):
     assert compare(gs, probes, 8, tex, dep, rp, rt, "small") <= TOL
 
 
+def extremes_scene():
+    # tiny, strongly anisotropic Gaussians 1.5-2.5 away in a cone around +x (large
+    # Mahalanobis offsets, where an FP32 shortcut in the candidate test would lose accuracy)
+    # behind a few large, faint Gaussians around the probes
+    rng = np.random.default_rng(11)
+    n = 3000
+    r = rng.uniform(1.5, 2.5, n)
+    ang = rng.uniform(-0.5, 0.5, (n, 2))
+    mean = np.stack([r * np.cos(ang[:, 0]) * np.cos(ang[:, 1]), r * np.sin(ang[:, 0]),
+                     r * np.cos(ang[:, 0]) * np.sin(ang[:, 1])], 1)
+    far = scenes.random_gaussians(rng, n, log_scale=(-4.5, 0.8))
+    far = scenes.GaussianScene(mean.astype(np.float32), far.scale, far.rotation, far.opacity,
+                               far.color)
+    big = scenes.random_gaussians(rng, 150, spread=0.8, log_scale=(-1.8, 0.5))
+    big = scenes.GaussianScene(big.mean, big.scale, big.rotation,
+                               (big.opacity * 0.3).astype(np.float32), big.color)
+    gs = scenes.GaussianScene(*(np.concatenate([getattr(far, f), getattr(big, f)])
+                                for f in ("mean", "scale", "rotation", "opacity", "color")))
+    probes = rng.uniform(-0.1, 0.1, (2, 3)).astype(np.float32)
+    return gs, probes
+
+
+def test_bake_scale_and_distance_extremes(torch_gpu):
+    log("bake: 3000 tiny far anisotropic + 150 large faint Gaussians, 2 probes, 32x32 all rays")
+    gs, probes = extremes_scene()
+    _, tex, dep = gpu_bake(gs, probes, 32)
+    rp = np.repeat(np.arange(2), 1024).astype(np.int32)
+    rt = np.tile(np.arange(1024), 2).astype(np.int32)
+    assert compare(gs, probes, 32, tex, dep, rp, rt, "extremes") <= TOL
+
+
 def test_bake_object_scene_sampled(torch_gpu):
     log("bake: object scene 100k Gaussians, 4096 probes at 32x32 (4.19M rays); 400 on oracle")
     gs = scenes.object_gaussians()
