@@ -142,45 +142,136 @@ __device__ __forceinline__ bool cell_overlaps(const BakeGrid& G, const float4* g
   return true;
 }
 
+// Whether the cut-off ellipsoid (padded like the box) meets cell (cx, cy, cz), exactly:
+// the minimum of q(x) = (x - mean)^T M^T M (x - mean) over the cell (enlarged by 1e-5) is at
+// most the padded cut-off. The minimiser of this convex quadratic over a box has each
+// coordinate either free (zero gradient) or at a bound, so the minimum is the smallest q
+// over the 26 patterns of fixed coordinates whose free part, solved from the zero-gradient
+// equations, lies inside the box (the 27th, all free, is the mean itself, tested first).
+// Called after cell_overlaps, which it refines; count and fill take the same decisions.
+__device__ __forceinline__ bool cell_meets_ellipsoid(const BakeGrid& G, const float4* gd,
+                                                     int cx, int cy, int cz) {
+  const int ci[3] = {cx, cy, cz};
+  double lo[3], hi[3], mu[3];
+  const double pad = 1e-5;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = (double)G.origin[a] + (double)ci[a] * (double)G.cell[a] - pad;
+    hi[a] = (double)G.origin[a] + (double)(ci[a] + 1) * (double)G.cell[a] + pad;
+    mu[a] = (double)gd[a].w;
+  }
+  if (mu[0] >= lo[0] && mu[0] <= hi[0] && mu[1] >= lo[1] && mu[1] <= hi[1] &&
+      mu[2] >= lo[2] && mu[2] <= hi[2])
+    return true;
+  double A[3][3];
+  {
+    const double m[3][3] = {{gd[0].x, gd[0].y, gd[0].z}, {gd[1].x, gd[1].y, gd[1].z},
+                            {gd[2].x, gd[2].y, gd[2].z}};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        A[a][b] = m[0][a] * m[0][b] + m[1][a] * m[1][b] + m[2][a] * m[2][b];
+  }
+  const double mmp = 1.002 * (double)gd[4].z + 1e-6;
+  const double r2 = mmp * mmp;
+  {                                               // the cell's centre inside: accept
+    double y[3], q = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[a] = 0.5 * (lo[a] + hi[a]) - mu[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) q += y[a] * A[a][b] * y[b];
+    if (q <= r2) return true;
+  }
+  double best = DBL_MAX;
+#pragma unroll
+  for (int code = 0; code < 26; ++code) {        // 26 = all free, covered above
+    const int st[3] = {code % 3, (code / 3) % 3, code / 9};   // 0 free, 1 low, 2 high
+    double y[3];                                  // x - mean
+#pragma unroll
+    for (int a = 0; a < 3; ++a) y[a] = st[a] == 1 ? lo[a] - mu[a] : hi[a] - mu[a];
+    const int nf = (st[0] == 0) + (st[1] == 0) + (st[2] == 0);
+    bool ok = true;
+    if (nf == 1) {
+      const int f = st[0] == 0 ? 0 : (st[1] == 0 ? 1 : 2);
+      const int b0 = (f + 1) % 3, b1 = (f + 2) % 3;
+      y[f] = -(A[f][b0] * y[b0] + A[f][b1] * y[b1]) / A[f][f];
+      ok = y[f] >= lo[f] - mu[f] - 1e-12 && y[f] <= hi[f] - mu[f] + 1e-12;
+    } else if (nf == 2) {
+      const int c = st[0] != 0 ? 0 : (st[1] != 0 ? 1 : 2);
+      const int f = (c + 1) % 3, g = (c + 2) % 3;
+      const double det = A[f][f] * A[g][g] - A[f][g] * A[g][f];
+      const double rf = -A[f][c] * y[c], rg = -A[g][c] * y[c];
+      y[f] = (rf * A[g][g] - A[f][g] * rg) / det;
+      y[g] = (A[f][f] * rg - A[g][f] * rf) / det;
+      ok = y[f] >= lo[f] - mu[f] - 1e-12 && y[f] <= hi[f] - mu[f] + 1e-12 &&
+           y[g] >= lo[g] - mu[g] - 1e-12 && y[g] <= hi[g] - mu[g] + 1e-12;
+    }
+    if (!ok) continue;
+    double q = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) q += y[a] * A[a][b] * y[b];
+    best = fmin(best, q);
+  }
+  return best <= r2;
+}
+
+// One wavefront per Gaussian; its lanes take the cells of the Gaussian's box in turn.
+__device__ __forceinline__ void box_cell(const int c0[3], int nx, int ny, int t, int& x,
+                                         int& y, int& z) {
+  x = c0[0] + t % nx;
+  y = c0[1] + (t / nx) % ny;
+  z = c0[2] + t / (nx * ny);
+}
+
 __global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* aabb,
                                                      int32_t* counts, int32_t* overflow) {
-  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= G.G) return;
   const float4 lo = aabb[2 * i], hi = aabb[2 * i + 1];
   int c0[3], c1[3];
   if (!cell_range(G, lo, hi, c0, c1)) return;
-  if (!inside_grid(G, lo, hi)) atomicOr(overflow, 1);
+  if (lane == 0 && !inside_grid(G, lo, hi)) atomicOr(overflow, 1);
   const float4* gd = G.gdata + (size_t)kGRows * i;
-  for (int z = c0[2]; z <= c1[2]; ++z)
-    for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x)
-        if (cell_overlaps(G, gd, x, y, z))
-          atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
+  const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
+  for (int t = lane; t < nx * ny * nz; t += 64) {
+    int x, y, z;
+    box_cell(c0, nx, ny, t, x, y, z);
+    if (cell_overlaps(G, gd, x, y, z) && cell_meets_ellipsoid(G, gd, x, y, z))
+      atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aabb,
                                                     const int32_t* cell_start, int32_t* cursor,
                                                     int32_t* entries, int32_t capacity,
                                                     int32_t* overflow) {
-  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= G.G) return;
   const int32_t ncell = G.dims[0] * G.dims[1] * G.dims[2];
   if (cell_start[ncell] > capacity) {      // more registrations than the plan holds
-    if (i == 0) atomicOr(overflow, 2);
+    if (i == 0 && lane == 0) atomicOr(overflow, 2);
     return;
   }
   const float4 lo = aabb[2 * i], hi = aabb[2 * i + 1];
   int c0[3], c1[3];
   if (!cell_range(G, lo, hi, c0, c1)) return;
   const float4* gd = G.gdata + (size_t)kGRows * i;
-  for (int z = c0[2]; z <= c1[2]; ++z)
-    for (int y = c0[1]; y <= c1[1]; ++y)
-      for (int x = c0[0]; x <= c1[0]; ++x) {
-        if (!cell_overlaps(G, gd, x, y, z)) continue;
-        const int32_t c = (z * G.dims[1] + y) * G.dims[0] + x;
-        const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
-        entries[slot] = i;
-      }
+  const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
+  for (int t = lane; t < nx * ny * nz; t += 64) {
+    int x, y, z;
+    box_cell(c0, nx, ny, t, x, y, z);
+    if (!cell_overlaps(G, gd, x, y, z) || !cell_meets_ellipsoid(G, gd, x, y, z)) continue;
+    const int32_t c = (z * G.dims[1] + y) * G.dims[0] + x;
+    const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
+    entries[slot] = i;
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -505,7 +596,7 @@ hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* co
                               int32_t* overflow, hipStream_t s) {
   if (G.G == 0) return hipSuccess;
   if (!G.gdata || !aabb || !counts || !overflow) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gauss_count, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb, counts,
+  hipLaunchKernelGGL(k_gauss_count, dim3((G.G + 3) / 4), dim3(256), 0, s, G, aabb, counts,
                      overflow);
   return hipGetLastError();
 }
@@ -516,7 +607,7 @@ hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_
   if (G.G == 0) return hipSuccess;
   if (!G.gdata || !aabb || !cell_start || !cursor || !entries || !overflow)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 255) / 256), dim3(256), 0, s, G, aabb,
+  hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 3) / 4), dim3(256), 0, s, G, aabb,
                      cell_start, cursor, entries, capacity, overflow);
   return hipGetLastError();
 }
