@@ -477,42 +477,58 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
           // pass 1: an FP32 screen of t* and m^2 with wide margins keeps the candidates the
           // FP64 test could accept (their indices go to this lane's LDS list)
           int n = 0;
+          auto screen = [&](const float4& r0, const float4& r1, const float4& r2, float mmv,
+                            int32_t gi) {
+            const float ox = o.x - r0.w, oy = o.y - r1.w, oz = o.z - r2.w;
+            const float ux = fmaf(r0.x, ox, fmaf(r0.y, oy, r0.z * oz));
+            const float uy = fmaf(r1.x, ox, fmaf(r1.y, oy, r1.z * oz));
+            const float uz = fmaf(r2.x, ox, fmaf(r2.y, oy, r2.z * oz));
+            const float wx = fmaf(r0.x, d.x, fmaf(r0.y, d.y, r0.z * d.z));
+            const float wy = fmaf(r1.x, d.x, fmaf(r1.y, d.y, r1.z * d.z));
+            const float wz = fmaf(r2.x, d.x, fmaf(r2.y, d.y, r2.z * d.z));
+            const float ww = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+            const float uw = fmaf(ux, wx, fmaf(uy, wy, uz * wz));
+            const float t32 = -uw * __builtin_amdgcn_rcpf(ww);
+            const float mt = kScreenT * (1.0f + fabsf(t32));
+            if (!(t32 > G.t_min - mt && t32 >= t_lo - mt && t32 < t_hi + mt)) return;
+            const float rx = fmaf(wx, t32, ux), ry = fmaf(wy, t32, uy), rz = fmaf(wz, t32, uz);
+            const float m2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
+            if (!(m2 <= fmaf(mmv * mmv, 1.0f + kScreenM, kScreenM))) return;
+            mylist[n * 64] = gi;
+            ++n;
+          };
           {
-            int32_t gi_c = e < e1 ? G.entries[e] : 0;
-            float4 p0, p1, p2;
-            float pm = 0.0f;
+            // two record sets take turns: one is tested while the other is in flight
+            int32_t giA = 0, giB = 0;
+            float4 a0, a1, a2, b0, b1, b2;
+            float amm = 0.0f, bmm = 0.0f;
             if (e < e1) {
-              const float4* gq = G.gdata + (size_t)kGRows * gi_c;
-              p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; pm = gq[4].z;
+              giA = G.entries[e];
+              const float4* gq = G.gdata + (size_t)kGRows * giA;
+              a0 = gq[0]; a1 = gq[1]; a2 = gq[2]; amm = gq[4].z;
             }
-            int32_t gi_n = e + kLpr < e1 ? G.entries[e + kLpr] : gi_c;
-            for (; e < e1 && n < kCap; e += kLpr) {
-              const int32_t gi = gi_c;
-              const float4 r0 = p0, r1 = p1, r2 = p2;
-              const float mmv = pm;
-              if (e + kLpr < e1) {
-                gi_c = gi_n;
-                const float4* gq = G.gdata + (size_t)kGRows * gi_c;
-                p0 = gq[0]; p1 = gq[1]; p2 = gq[2]; pm = gq[4].z;
-                if (e + 2 * kLpr < e1) gi_n = G.entries[e + 2 * kLpr];
+            int32_t gnext = e + kLpr < e1 ? G.entries[e + kLpr] : 0;
+            while (e < e1 && n < kCap) {
+              const bool hasB = e + kLpr < e1;
+              if (hasB) {
+                giB = gnext;
+                const float4* gq = G.gdata + (size_t)kGRows * giB;
+                b0 = gq[0]; b1 = gq[1]; b2 = gq[2]; bmm = gq[4].z;
+                gnext = e + 2 * kLpr < e1 ? G.entries[e + 2 * kLpr] : 0;
               }
-              const float ox = o.x - r0.w, oy = o.y - r1.w, oz = o.z - r2.w;
-              const float ux = fmaf(r0.x, ox, fmaf(r0.y, oy, r0.z * oz));
-              const float uy = fmaf(r1.x, ox, fmaf(r1.y, oy, r1.z * oz));
-              const float uz = fmaf(r2.x, ox, fmaf(r2.y, oy, r2.z * oz));
-              const float wx = fmaf(r0.x, d.x, fmaf(r0.y, d.y, r0.z * d.z));
-              const float wy = fmaf(r1.x, d.x, fmaf(r1.y, d.y, r1.z * d.z));
-              const float wz = fmaf(r2.x, d.x, fmaf(r2.y, d.y, r2.z * d.z));
-              const float ww = fmaf(wx, wx, fmaf(wy, wy, wz * wz));
-              const float uw = fmaf(ux, wx, fmaf(uy, wy, uz * wz));
-              const float t32 = -uw * __builtin_amdgcn_rcpf(ww);
-              const float mt = kScreenT * (1.0f + fabsf(t32));
-              if (!(t32 > G.t_min - mt && t32 >= t_lo - mt && t32 < t_hi + mt)) continue;
-              const float rx = fmaf(wx, t32, ux), ry = fmaf(wy, t32, uy), rz = fmaf(wz, t32, uz);
-              const float m2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-              if (!(m2 <= fmaf(mmv * mmv, 1.0f + kScreenM, kScreenM))) continue;
-              mylist[n * 64] = gi;
-              ++n;
+              screen(a0, a1, a2, amm, giA);
+              e += kLpr;
+              if (!hasB || n >= kCap) break;
+              const bool hasA = e + kLpr < e1;
+              if (hasA) {
+                giA = gnext;
+                const float4* gq = G.gdata + (size_t)kGRows * giA;
+                a0 = gq[0]; a1 = gq[1]; a2 = gq[2]; amm = gq[4].z;
+                gnext = e + 2 * kLpr < e1 ? G.entries[e + 2 * kLpr] : 0;
+              }
+              screen(b0, b1, b2, bmm, giB);
+              e += kLpr;
+              if (!hasA) break;
             }
           }
           // pass 2: the exact FP64 test of the kept candidates

@@ -91,6 +91,26 @@ def test_bake_object_scene_sampled(torch_gpu):
     assert compare(gs, probes, 32, tex, dep, rp, rt, "object") <= TOL
 
 
+def test_bake_nonzero_t_min_and_cutoffs(torch_gpu):
+    # t_min skips the Gaussians right around the probe; other alpha cut and stop rule
+    log("bake: 300 Gaussians, 6 probes, 8x8, t_min 0.15, alpha_min 0.02, T_min 1e-2")
+    rng = np.random.default_rng(5)
+    gs = scenes.random_gaussians(rng, 300)
+    probes = rng.uniform(-0.3, 0.3, (6, 3)).astype(np.float32)
+    opts = dict(t_min=0.15, alpha_min=0.02, alpha_max=0.95, T_min=1e-2)
+    _, tex, dep = gpu_bake(gs, probes, 8, **opts)
+    rp = np.repeat(np.arange(6), 64).astype(np.int32)
+    rt = np.tile(np.arange(64), 6).astype(np.int32)
+    ref, amb = oracle.bake_rays(gs, probes.astype(np.float64), 8, rp, rt, **opts)
+    keep = ~amb
+    log(f"t_min: {amb.sum()} of {len(amb)} rays ambiguous (excluded)")
+    flat = tex.reshape(-1, 64, 4)[rp, rt]
+    d = dep.reshape(-1, 64)[rp, rt]
+    assert keep.mean() > 0.85
+    assert report("t_min rgbo", parity_err(flat[keep], ref[keep, :4])) <= TOL
+    assert report("t_min depth", parity_err(d[keep], ref[keep, 4])) <= TOL
+
+
 def test_bake_single_gaussian_closed_form(torch_gpu):
     log("bake: one Gaussian on the axis of a texel")
     R = 4
