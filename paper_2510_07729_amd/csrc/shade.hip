@@ -902,7 +902,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
 #pragma unroll
     for (int i = 0; i < kVPT; ++i) {
       const int v = tid + kBatchThreads * i;
-      if (v < MV) unsafeAtomicAdd(dst + v, acc[i]);
+      if (v < MV && acc[i] != 0.0f) unsafeAtomicAdd(dst + v, acc[i]);   // texels no sample reached stay untouched
     }
   }
 }
