@@ -68,7 +68,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-proposal-study", action="store_true")
-    ap.add_argument("--proposal-steps", type=int, default=3000)
+    ap.add_argument("--proposal-steps", type=int, default=6000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -242,10 +242,17 @@ def main() -> int:
                 "unit_def": "shaded point-direction sample", "launch_ms": round(phase[dom], 4)}
     # the shading kernels' own figures (the metric's fwd+bwd rate)
     shade_roof = {}
-    for n, f in (("shade_fwd", flops_fwd(K)), ("shade_bwd", flops_bwd(K))):
+    for n, f, kern in (("shade_fwd", flops_fwd(K), "k_shade_fwd"),
+                       ("shade_bwd", flops_bwd(K), "k_shade_bwd_batched")):
         a = samples * f / (phase[n] * 1e-3) / 1e12
         shade_roof[n] = {"achieved_tflops": round(a, 3), "frac": round(a / PEAK_FP32_TFLOPS, 4),
                          "flops_per_sample": f, "launch_ms": round(phase[n], 4)}
+        # HBM side: counter-measured bytes of the same kernel over its measured time
+        hb = measured_traffic(kern)
+        if hb is not None:
+            bw = hb / (phase[n] * 1e-3) / 1e9
+            shade_roof[n].update({"hbm_bytes": round(hb), "hbm_GBps": round(bw, 1),
+                                  "hbm_frac": round(bw / PEAK_HBM_GBS, 4)})
 
     study = None
     if not args.no_proposal_study:
