@@ -231,6 +231,10 @@ def main() -> int:
                 "units_per_launch": round(rays * work["resolved_per_ray_mean"]),
                 "unit_def": "Gaussian resolved on a ray (accepted, up to the one ending it)",
                 "launch_ms": round(phase["bake"], 4)}
+        # how busy the vector ALUs were while doing the search (counter summary)
+        issue = counter_summary("k_bake_object_valu.txt", "valu_issue_fraction")
+        if issue is not None:
+            roof["valu_issue_frac"] = issue
     else:
         f = flops_fwd(K) if dom == "shade_fwd" else flops_bwd(K)
         achieved = samples * f / (phase[dom] * 1e-3) / 1e12
@@ -383,6 +387,26 @@ def bake_work() -> dict:
     reference trace (tests/golden/make_bake_work.py) and stored as data."""
     with open(os.path.join(ROOT, "tests", "golden", "bake_work_object.json")) as f:
         return json.load(f)
+
+
+def counter_summary(fname: str, key: str):
+    """A figure from a committed rocprofv3 counter summary under profiles/, or None when the
+    summary is missing or was taken on a different source of the kernel."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", fname)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = vals.get("source")
+    if not src or key not in vals:
+        return None
+    fn, digest = src.split("@")
+    h = hashlib.sha256(open(os.path.join(ROOT, fn), "rb").read()).hexdigest()[:16]
+    return float(vals[key]) if h == digest else None
 
 
 def measured_traffic(kernel: str):
