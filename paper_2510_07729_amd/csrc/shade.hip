@@ -773,8 +773,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
   int32_t* erank = uni + kMaxEntries;                   // [kMaxEntries] slot of a leader
   float* W = reinterpret_cast<float*>(erank + kMaxEntries);     // [kMaxEntries][kBatch]
   int32_t* misc = reinterpret_cast<int32_t*>(W + kMaxEntries * kBatch);  // [1]
-  EnvRun* runs = reinterpret_cast<EnvRun*>(
-      (reinterpret_cast<uintptr_t>(misc + 1) + 15) & ~(uintptr_t)15);   // [kBatch][kEnvRuns]
+  // [kBatch][kEnvRuns], 16-byte aligned; indexed off the LDS array itself so that the
+  // accesses stay LDS instructions (not generic ones that also wait on global memory)
+  const int run_off = (kBatch * MV + 5 * kMaxEntries + kMaxEntries * kBatch + 1 + 3) & ~3;
+  EnvRun* runs = reinterpret_cast<EnvRun*>(lds + run_off);
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
