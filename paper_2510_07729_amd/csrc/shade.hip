@@ -145,14 +145,17 @@ __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps
     if (id < 0) continue;
     const float wk = nb.wt(s2, a, ps.p, k);
     const TexT* T = tex + (size_t)id * RR;
+    // the four taps are requested together, then used
+    float4 x[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = load_texel(T, (size_t)s.tt.off[t]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const float4 x = load_texel(T, (size_t)s.tt.off[t]);
       const float c = wk * s.tt.w[t];
-      s.Lin[0] += c * x.x;
-      s.Lin[1] += c * x.y;
-      s.Lin[2] += c * x.z;
-      s.O += c * x.w;
+      s.Lin[0] += c * x[t].x;
+      s.Lin[1] += c * x[t].y;
+      s.Lin[2] += c * x[t].z;
+      s.O += c * x[t].w;
     }
   }
 }
@@ -191,7 +194,9 @@ __device__ __forceinline__ int64_t group_slot(int lane) {
 }
 
 template <int KT, typename TexT, int L>
-__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, int32_t k) {
+// three wavefronts per SIMD (at most 168 registers): the batched tap loads would otherwise
+// take the kernel to two
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd(ShadeArgs a, int32_t k) {
   const int lane = threadIdx.x & 63, li = lane % L;
   const int64_t slot = group_slot<L>(lane);
   if (((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
