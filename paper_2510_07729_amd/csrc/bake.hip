@@ -278,19 +278,6 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
 // per-texel ray traversal
 // ------------------------------------------------------------------------------------------
 
-__device__ __forceinline__ v3 oct_decode_dev(float u, float v, int R) {
-  float px = 2.0f * u / (float)R - 1.0f, py = 2.0f * v / (float)R - 1.0f;
-  const float z = 1.0f - fabsf(px) - fabsf(py);
-  if (z < 0.0f) {
-    const float fx = (1.0f - fabsf(py)) * sgn1(px);
-    const float fy = (1.0f - fabsf(px)) * sgn1(py);
-    px = fx;
-    py = fy;
-  }
-  const float il = rsqrtf(px * px + py * py + z * z);
-  return mk3(px * il, py * il, z * il);
-}
-
 // Response of a Gaussian (rows r0..r2 of S^-1 R^T with the mean in .w) on the ray o + t d
 // in FP64: t* = -(Mo . Md) / |Md|^2 and m^2 = |Mo + t* Md|^2 (Mo = M (o - mean)). The
 // composite step calls it again for the kept candidates, so alpha is recomputed bit for bit
@@ -468,7 +455,7 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
       // candidates of this cell in ascending (t*, index): each lane of the ray tests every
       // kLpr-th entry into its own sorted buffer; the buffers are merged when compositing
       double after = -1.0;     // keys <= after are done
-      for (int round = 0; e1 > e0 && !done; ++round) {
+      while (e1 > e0 && !done) {            // rounds: the cell again above `after`
         double key[kNb];
 #pragma unroll
         for (int s = 0; s < kNb; ++s) key[s] = kNone;
