@@ -182,6 +182,20 @@ def test_shade_frames_half_texels_camera_views(torch_gpu):
     assert report("shade frames sampled", parity_err(rgb[rows], ro)) <= TOL
 
 
+def test_shade_frames_full_size_sampled(torch_gpu):
+    # the G-buffer configuration at its full size (8 frames x 1920 x 1080 = 16.6M points,
+    # 16,384 probes with f16 maps, 64 directions, K = 8) in one call; 40 pixels per frame
+    # checked against the oracle
+    log("shade g-buffer frames at full size: 16.6M points, 16384 f16 probes, S=64, K=8")
+    sc = scenes.gbuffer_frames()
+    rgb = run_shade(sc)
+    assert rgb.shape == (sc.n, 3) and np.all(np.isfinite(rgb))
+    sub, rows = subset_frames(sc, 40, seed=3)
+    idx, w = oracle_knn(sub)
+    ro = oracle.shade(sub, idx, w)
+    assert report("shade frames full size sampled", parity_err(rgb[rows], ro)) <= TOL
+
+
 def test_shade_empty_and_no_probes(torch_gpu):
     log("shade N=0 and P=0")
     s = sop()
