@@ -344,7 +344,8 @@ __device__ __forceinline__ int find_bin(const CumT* cum, uint64_t x) {
 }
 
 template <int KT, typename TexT, int L>
-__global__ __launch_bounds__(256) void k_shade_prop(ShadeArgs a, int32_t k) {
+// three wavefronts per SIMD, like the forward kernel
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_prop(ShadeArgs a, int32_t k) {
   constexpr int PPW = 64 / L;
   __shared__ uint64_t s_cum[kWavesPerBlock][PPW][SOP_MLP_BINS + 1];
   const int lane = threadIdx.x & 63, li = lane % L;

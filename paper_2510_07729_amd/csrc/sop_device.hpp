@@ -233,11 +233,33 @@ __device__ __forceinline__ double small_atan(double z) {
              z2 * (-1.0 / 11 + z2 * (1.0 / 13)))))));
 }
 
+// atan2 for the rare wide angles, built on the same series: fold into the first octant,
+// then three half-angle steps t -> t / (1 + sqrt(1 + t^2)) take tan(pi/4) to tan(pi/32) <
+// 0.1, where the series is exact to ~1e-16. It keeps no polynomial of its own, so the
+// common path holds no extra constants.
+__device__ __noinline__ double wide_atan2(double y, double x) {
+  const double kPi = 3.14159265358979323846;
+  if (x == 0.0 && y == 0.0) {
+    const double r = signbit(x) ? kPi : 0.0;
+    return signbit(y) ? -r : r;
+  }
+  const double ax = fabs(x), ay = fabs(y);
+  const bool steep = ay > ax;
+  double t = steep ? ax / ay : ay / ax;                  // in [0, 1]
+  t = t / (1.0 + sqrt(fma(t, t, 1.0)));
+  t = t / (1.0 + sqrt(fma(t, t, 1.0)));
+  t = t / (1.0 + sqrt(fma(t, t, 1.0)));
+  double r = 8.0 * small_atan(t);
+  if (steep) r = 0.5 * kPi - r;
+  if (signbit(x)) r = kPi - r;
+  return signbit(y) ? -r : r;
+}
+
 __device__ __forceinline__ double angle_from(double c, double s, double x, double y) {
   // signed angle from direction (c, s) to (x, y), both in one plane, |angle| < pi/2
   const double cr = c * y - s * x, dt = c * x + s * y;
   const double z = cr / dt;
-  return fabs(z) <= 0.2 ? small_atan(z) : atan2(cr, dt);
+  return fabs(z) <= 0.2 ? small_atan(z) : wide_atan2(cr, dt);
 }
 
 __device__ __forceinline__ EnvTaps env_taps64(const double w[3], int H, int W, float u_scale,
