@@ -3,9 +3,10 @@
 //
 // Every Gaussian is turned into its whitening map M = S^-1 R^T (ray in Gaussian units) and
 // registered in the cells of a uniform grid that its cut-off ellipsoid (where
-// opacity * exp(-m^2/2) can reach alpha_min) may overlap: the cells of its axis-aligned box
-// that also pass a separating-axis test along the ellipsoid's own axes, padded for FP32
-// rounding.
+// opacity * exp(-m^2/2) can reach alpha_min) overlaps: the cells of its axis-aligned box
+// that pass a separating-axis test along the ellipsoid's own axes and an exact test (the
+// minimum of the ellipsoid's quadratic form over the cell), all padded for FP32 rounding;
+// one wavefront registers one Gaussian.
 // Four lanes trace one texel's ray; a wavefront covers a 4x4 texel block of one probe so
 // that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
 // composited in the cell whose t-window [t_enter, t_exit) holds its t*. Within a cell the
