@@ -377,7 +377,9 @@ sop_status sop_proposal_infer(const sop_mlp* mlp, const sop_points* pts, float* 
  * loss (in the parameter layout) is written to grad (device [SOP_MLP_PARAMS], may be NULL).
  * When opt is not NULL the parameters are then updated in place by Adam with the state
  * adam_m / adam_v (device [SOP_MLP_PARAMS] each). In the backward pass the output-side
- * gradients are rounded to bfloat16 before they meet a weight or an activation. */
+ * gradients are rounded to bfloat16 before they meet a weight or an activation. The step
+ * uses no atomics: the same inputs give the same loss, gradient and parameters bit for
+ * bit. */
 sop_status sop_proposal_train_step(const sop_mlp* mlp, const sop_points* pts,
                                    const float* targets, const sop_adam* opt, float* adam_m,
                                    float* adam_v, float* loss, float* grad, void* ws,

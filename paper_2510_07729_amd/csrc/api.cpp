@@ -696,7 +696,8 @@ sopk::MlpArgs mlp_args(const sop_mlp* m, const sop_points* pts) {
 }
 
 // Workspace: [weight fragments] then, for training, the transposed bf16 operands
-// x^T [320][B16], h1^T, h2^T, dz1^T, dz2^T [64][B16], dz3^T [256][B16] and a gradient buffer
+// x^T [320][B16], h1^T, h2^T, dz1^T, dz2^T [64][B16], dz3^T [256][B16], a gradient buffer
+// and the per-tile partial sums [B16 / 16][385]
 size_t proposal_ws(sop_op op, int64_t n) {
   Bump b{nullptr, 0, 0};
   (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
@@ -706,6 +707,7 @@ size_t proposal_ws(sop_op op, int64_t n) {
     for (int i = 0; i < 4; ++i) (void)b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
     (void)b.take<uint16_t>((size_t)SOP_MLP_BINS * ld);
     (void)b.take<float>(SOP_MLP_PARAMS);
+    (void)b.take<float>((ld / 16) * sopk::kMlpPart);
   }
   return b.used;
 }
@@ -794,14 +796,11 @@ extern "C" sop_status sop_proposal_train_step(const sop_mlp* mlp, const sop_poin
   a.dz2T = b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
   a.dz3T = b.take<uint16_t>((size_t)SOP_MLP_BINS * ld);
   float* ws_grad = b.take<float>(SOP_MLP_PARAMS);
+  a.part = b.take<float>((ld / 16) * sopk::kMlpPart);
   a.ldT = (int64_t)ld;
   a.targets = targets;
   a.loss = loss;
-  a.grad = grad ? grad : ws_grad;
-  SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(a.grad), 0, SOP_MLP_PARAMS, s),
-          "sop_proposal_train_step");
-  SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(loss), 0, 1, s),
-          "sop_proposal_train_step");
+  a.grad = grad ? grad : ws_grad;          // every entry and the loss are written
   SOP_HIP(sopk::launch_mlp_frags(mlp->params, frags, s), "sop_proposal_train_step");
   SOP_HIP(sopk::launch_mlp_train(a, s), "sop_proposal_train_step");
   if (opt) return sop_adam_update(mlp->params, adam_m, adam_v, a.grad, SOP_MLP_PARAMS, opt, stream);

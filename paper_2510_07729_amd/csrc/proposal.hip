@@ -79,9 +79,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs a) {
 
 // ------------------------------------------------------------------------------------------
 // training: forward + cross entropy + backward of one 16-point tile per wavefront.
-// Writes the transposed bf16 operands of the weight-gradient GEMM (zero for padding points),
-// accumulates bias gradients and the loss with atomics.
+// Writes the transposed bf16 operands of the weight-gradient GEMM (zero for padding points)
+// and the tile's bias-gradient column sums and loss, which the weight-gradient kernel adds
+// up in a fixed order (no atomics: a step is deterministic).
 // ------------------------------------------------------------------------------------------
+constexpr int kPart = kMlpPart;
+
 __device__ __forceinline__ float tile_col_sum(float v) {     // sum over the 16 points
   v += __shfl_xor(v, 1);
   v += __shfl_xor(v, 2);
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
       loss -= tt * (F.z3[mb][t] - lse);
       dz[t] = (expf(F.z3[mb][t] - lse) - tt) * invB * vmask;
       const float cs = tile_col_sum(dz[t]);
-      if (r == 0) unsafeAtomicAdd(a.grad + kOffB3 + 16 * mb + 4 * g + t, cs);
+      if (r == 0) a.part[tile * kPart + 2 * kHid + 16 * mb + 4 * g + t] = cs;
     }
     d3[mb] = pack4(dz[0], dz[1], dz[2], dz[3]);
 #pragma unroll
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
       a.dz3T[(size_t)(16 * mb + 4 * g + t) * a.ldT + col] = (uint16_t)d3[mb][t];
   }
   loss = wave_sum(loss * vmask);
-  if (lane == 0) unsafeAtomicAdd(a.loss, loss * invB);
+  if (lane == 0) a.part[tile * kPart + kPart - 1] = loss * invB;
   // dh2^T = W3 dz3^T, dz2 = dh2 [z2 > 0]
   f32x4 acc[4];
 #pragma unroll
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
     for (int t = 0; t < 4; ++t) {
       dz[t] = F.z2[mb][t] > 0.0f ? acc[mb][t] : 0.0f;
       const float cs = tile_col_sum(dz[t]);
-      if (r == 0) unsafeAtomicAdd(a.grad + kOffB2 + 16 * mb + 4 * g + t, cs);
+      if (r == 0) a.part[tile * kPart + kHid + 16 * mb + 4 * g + t] = cs;
     }
     d2[mb] = pack4(dz[0], dz[1], dz[2], dz[3]);
 #pragma unroll
@@ -194,7 +197,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
     for (int t = 0; t < 4; ++t) {
       dz[t] = F.z1[mb][t] > 0.0f ? acc[mb][t] : 0.0f;
       const float cs = tile_col_sum(dz[t]);
-      if (r == 0) unsafeAtomicAdd(a.grad + kOffB1 + 16 * mb + 4 * g + t, cs);
+      if (r == 0) a.part[tile * kPart + 16 * mb + 4 * g + t] = cs;
     }
     const bf16x4 d1 = pack4(dz[0], dz[1], dz[2], dz[3]);
 #pragma unroll
@@ -220,6 +223,17 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(MlpArgs a) {
   } else if (w < 160) {
     mi = (w - 96) / 16; no = (w - 96) % 16; A = a.h2T; B = a.dz3T; out_w = kBins; off = kOffW3;
   } else {
+    // bias gradients and the loss: the tiles' partial sums added in tile order, so that a
+    // training step is deterministic
+    const int v = (w - 160) * 64 + lane;
+    if (v >= kPart) return;
+    const int64_t tiles = a.ldT / 16;
+    float sum = 0.0f;
+    for (int64_t t = 0; t < tiles; ++t) sum += a.part[t * kPart + v];
+    if (v < kHid) a.grad[kOffB1 + v] = sum;
+    else if (v < 2 * kHid) a.grad[kOffB2 + v - kHid] = sum;
+    else if (v < kPart - 1) a.grad[kOffB3 + v - 2 * kHid] = sum;
+    else *a.loss = sum;
     return;
   }
   const uint16_t* arow = A + (size_t)(16 * mi + r) * a.ldT + 4 * g;
@@ -272,7 +286,8 @@ hipError_t launch_mlp_train(const MlpArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int64_t tiles = a.ldT / 16;
   hipLaunchKernelGGL(k_mlp_train, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(40), dim3(256), 0, s, a);
+  // 160 weight tiles, then ceil(kPart / 64) wavefronts of bias/loss sums
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(40 + (kPart + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

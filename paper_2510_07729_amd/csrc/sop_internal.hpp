@@ -102,6 +102,9 @@ struct ShadeArgs {
 };
 
 // learned proposal network (proposal.hip)
+// per 16-point training tile: column sums of dz1, dz2 (SOP_MLP_HIDDEN each), dz3
+// (SOP_MLP_BINS) and the tile's loss
+constexpr int kMlpPart = 2 * SOP_MLP_HIDDEN + SOP_MLP_BINS + 1;
 struct MlpArgs {
   int64_t n;                 // points (inference) or batch size (training)
   const float* pos;
@@ -117,8 +120,9 @@ struct MlpArgs {
   float* logits;
   // training
   const float* targets;      // [n,256]
-  float* loss;               // [1] (accumulated; zeroed by the caller)
-  float* grad;               // [SOP_MLP_PARAMS] (bias part accumulated; zeroed by the caller)
+  float* loss;               // [1]
+  float* grad;               // [SOP_MLP_PARAMS]
+  float* part;               // [ldT / 16][kMlpPart]: per-tile bias-gradient sums and loss
   uint16_t *xT, *h1T, *h2T, *dz1T, *dz2T, *dz3T;   // [rows][ldT] bf16, transposed operands
   int64_t ldT;               // batch rounded up to 16
 };

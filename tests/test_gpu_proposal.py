@@ -124,6 +124,25 @@ def test_train_gradient_matches_oracle(torch_gpu, B):
     assert np.array_equal(mlp.params.cpu().numpy(), params)
 
 
+def test_train_step_is_deterministic(torch_gpu):
+    log("training steps repeat bit for bit (no atomics)")
+    import torch
+    sc, T = batch(4096, seed=3)
+    params = scenes.mlp_init(seed=8)
+    runs = []
+    for _ in range(2):
+        mlp = gpu_mlp(params, sc)
+        grad = torch.empty(params.size, dtype=torch.float32, device="cuda")
+        loss = sop().sop_proposal_train_step(mlp, gpu_points(sc), dev(T), grad=grad)
+        g0, l0 = grad.clone(), loss.clone()
+        for _ in range(3):                       # three Adam steps on the same batch
+            sop().sop_proposal_train_step(mlp, gpu_points(sc), dev(T), lr=1e-3)
+        torch.cuda.synchronize()
+        runs.append((g0.cpu().numpy(), l0.cpu().numpy(), mlp.params.cpu().numpy()))
+    for a_, b_ in zip(runs[0], runs[1]):
+        assert np.array_equal(a_, b_)
+
+
 def test_adam_matches_oracle(torch_gpu):
     log("Adam update")
     import torch
