@@ -190,7 +190,7 @@ __device__ __forceinline__ float group_sum(float v) {
 // cost for one point).
 template <int L>
 __device__ __forceinline__ int64_t group_slot(int lane) {
-  return ((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * (64 / L) + lane / L;
+  return (die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) + lane / L;
 }
 
 template <int KT, typename TexT, int L>
@@ -199,7 +199,7 @@ template <int KT, typename TexT, int L>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd(ShadeArgs a, int32_t k) {
   const int lane = threadIdx.x & 63, li = lane % L;
   const int64_t slot = group_slot<L>(lane);
-  if (((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
   PointState ps;
   // lanes of a group past the end (or with an invalid order entry) skip the work but take
   // part in the group sums
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ uint64_t s_cum[kWavesPerBlock][PPW][SOP_MLP_BINS + 1];
   const int lane = threadIdx.x & 63, li = lane % L;
   const int64_t slot = group_slot<L>(lane);
-  if (((int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform()) * PPW >= a.n) return;
+  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * PPW >= a.n) return;
   uint64_t* cum = s_cum[threadIdx.x >> 6][lane / L];
   PointState ps;
   const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
@@ -420,7 +420,7 @@ template <int KT, typename TexT>
 __global__ __launch_bounds__(256) void k_shade_prop_net(ShadeArgs a, int32_t k) {
   __shared__ uint32_t s_cum[kWavesPerBlock][16][SOP_MLP_BINS + 1];
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  const int64_t tile = die_block() * kWavesPerBlock + wave_id_uniform();
   if (tile * 16 >= a.n) return;
   const int64_t slot = tile * 16 + r;
   uint32_t* cum = s_cum[threadIdx.x >> 6][r];
@@ -537,7 +537,7 @@ __global__ __launch_bounds__(256) void k_shade_prop_net(ShadeArgs a, int32_t k) 
 template <int KT, typename TexT>
 __global__ __launch_bounds__(256) void k_dump_integrand(ShadeArgs a, int32_t k) {
   __shared__ float s_acc[kWavesPerBlock][SOP_MLP_BINS];
-  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  const int64_t wv = die_block() * kWavesPerBlock + wave_id_uniform();
   if (wv >= a.n) return;
   const int lane = threadIdx.x & 63;
   float* accb = s_acc[threadIdx.x >> 6];
@@ -651,7 +651,7 @@ __device__ __forceinline__ void scatter_env(const ShadeArgs& a, const Sample& s,
 // Used when the grouped kernel below does not apply (res > 32, more than 16384 probes).
 template <int KT, typename TexT>
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
-  const int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + wave_id_uniform();
+  const int64_t wv = die_block() * kWavesPerBlock + wave_id_uniform();
   if (wv >= a.n) return;
   const int lane = threadIdx.x & 63;
   PointState ps;
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int64_t g0 = (int64_t)blockIdx.x * kBatch;
+  const int64_t g0 = die_block() * kBatch;
   const int bn = (int)min((int64_t)kBatch, a.n - g0);
   if (bn <= 0) return;
   const int ne = kBatch * k;

@@ -407,6 +407,15 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Workgroups are dispatched to the 8 dies round-robin (block b runs on die b % 8). This
+// renumbers them so that each die takes a contiguous range of blocks: consecutive
+// (Morton-ordered) points then share one die's L2, which holds the probe maps they read.
+__device__ __forceinline__ int64_t die_block() {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  const int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 __device__ __forceinline__ int wave_id_uniform() {
   return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 }
