@@ -7,10 +7,10 @@
 // that pass a separating-axis test along the ellipsoid's own axes and an exact test (the
 // minimum of the ellipsoid's quadratic form over the cell), all padded for FP32 rounding;
 // one wavefront registers one Gaussian.
-// Four lanes trace one texel's ray; a wavefront covers a 4x4 texel block of one probe so
+// Two lanes trace one texel's ray; a wavefront covers an 8x4 texel block of one probe so
 // that its rays stay coherent. The ray walks the grid cell by cell (3D DDA); a Gaussian is
 // composited in the cell whose t-window [t_enter, t_exit) holds its t*. Within a cell the
-// four lanes split the candidates. Each lane first screens its candidates in FP32 (t* in
+// two lanes split the candidates. Each lane first screens its candidates in FP32 (t* in
 // the window and m^2 under the cut-off, both with margins far above the FP32 error) and
 // keeps the survivors in LDS, then runs the exact FP64 test on those only, so the FP64
 // work is done for about one candidate in six and by all lanes together. Accepted keys
@@ -307,8 +307,8 @@ __device__ __forceinline__ float exact_alpha(const BakeGrid& G, double tsd, doub
   return fminf(G.alpha_max, op * expf(-0.5f * m2));
 }
 
-constexpr int kLpr = 4;    // lanes that trace one ray
-constexpr int kNb = 20;    // sorted candidate keys per lane
+constexpr int kLpr = 2;    // lanes that trace one ray
+constexpr int kNb = 24;    // sorted candidate keys per lane
 constexpr int kCap = 32;   // candidates a lane keeps per screening pass
 // screening margins: |t*_32 - t*| < kScreenT (1 + |t*|) and |m^2_32 - m^2| < kScreenM (1 + m^2)
 // hold with a wide margin (measured: 4e-7 and 8e-5 on the object workload)
@@ -343,6 +343,8 @@ __device__ __forceinline__ double ray_min(double x) {
   return x;
 }
 
+// The kernel needs three wavefronts per SIMD (at most 168 registers; it uses 168): at two
+// it runs ~40% slower, so any change here has to keep the register count.
 __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
                                               int32_t R, float* texels, float* depth,
                                               const int4* order) {

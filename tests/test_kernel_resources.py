@@ -1,0 +1,45 @@
+"""Register budgets of the latency-bound kernels (CPU: hipcc cross-compiles for gfx950).
+
+The bake and the shading forward run three wavefronts per SIMD; one register over the
+budget drops them to two and costs ~40% (bake) or more. These checks compile the sources
+to gfx950 assembly and read the register counts the compiler reports."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2510_07729_amd import build
+
+CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                    "paper_2510_07729_amd", "csrc")
+
+
+def kernel_stats(src: str, tmp_path, symbol_prefix: str) -> dict:
+    try:
+        cc = build.hipcc()
+    except RuntimeError:
+        pytest.skip("hipcc not available")
+    out = tmp_path / (os.path.basename(src) + ".s")
+    cmd = [cc, *[f for f in build.COMMON if f not in ("-fPIC",)], "--cuda-device-only", "-S",
+           "-x", "hip", os.path.join(CSRC, src), "-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    text = out.read_text()
+    start = text.index(symbol_prefix)
+    tail = text[start:]
+    vgpr = int(re.search(r"; NumVgprs: (\d+)", tail).group(1))
+    scratch = int(re.search(r"; ScratchSize: (\d+)", tail).group(1))
+    occ = int(re.search(r"; Occupancy: (\d+)", tail).group(1))
+    return {"vgpr": vgpr, "scratch": scratch, "occupancy": occ}
+
+
+def test_bake_kernel_keeps_three_wavefronts(tmp_path):
+    st = kernel_stats("bake.hip", tmp_path, "_ZN4sopk6k_bakeE")
+    assert st["vgpr"] <= 168 and st["occupancy"] >= 3 and st["scratch"] == 0, st
+
+
+def test_shade_forward_keeps_three_wavefronts(tmp_path):
+    st = kernel_stats("shade.hip", tmp_path, "_ZN4sopk11k_shade_fwdILi8E15HIP_vector_typeIfLj4EELi64EE")
+    assert st["vgpr"] <= 168 and st["occupancy"] >= 3 and st["scratch"] == 0, st
