@@ -111,6 +111,11 @@ def _sig(lib):
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dptr, iptr, iptr]
+    lib.orc_shade_traced.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, C.c_long, dptr,
+                                     dptr, dptr, dptr, C.c_long, dptr, dptr, dptr, dptr,
+                                     C.c_int, C.c_int, C.c_int, u32, C.c_int, C.c_float,
+                                     C.c_double, C.c_double, C.c_double, C.c_double, dptr,
+                                     dptr, dptr, iptr]
 
 
 def lib():
@@ -397,6 +402,45 @@ def bake_rays(gs, probe_pos, res, ray_probe, ray_texel, t_min=0.0, alpha_min=1.0
     if used:
         return out, flags.astype(bool), n_used
     return out, flags.astype(bool)
+
+
+
+def shade_traced(gs, sc, offset, n_dirs=None, seed=None, per_point=False, t_min=0.0,
+                 alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, env=None):
+    """Traced shading of the points of ShadeScene ``sc`` through Gaussians ``gs``: every
+    sample's O and L_in from its own ray, starting at fmaf(offset, n, x) (float32).
+    Returns a dict: rgb [N,3], irr [N,3], samples [N,S,4] (R,G,B,O), ray_amb [N,S] and
+    amb [N] (some ray of the point is ambiguous)."""
+    keep = []
+
+    def d(a):
+        a2, p = _d(a)
+        keep.append(a2)
+        return p
+
+    N = sc.pos.shape[0]
+    S = sc.n_dirs if n_dirs is None else n_dirs
+    sd = sc.seed if seed is None else seed
+    envd = np.ascontiguousarray(sc.env if env is None else env, dtype=np.float64)
+    keep.append(envd)
+    if sc.view is not None:
+        pv, pc, ppf = d(sc.view), None, 1
+    else:
+        pv, pc, ppf = None, d(sc.cam_pos), sc.points_per_frame
+    rgb = np.zeros((N, 3))
+    irr = np.zeros((N, 3))
+    samples = np.zeros((N, S, 4))
+    flags = np.zeros((N, S), np.int32)
+    lib().orc_shade_traced(gs.count, d(gs.mean), d(gs.scale), d(gs.rotation), d(gs.opacity),
+                           d(gs.color), N, d(sc.pos), d(sc.normal), pv, pc, ppf,
+                           d(sc.albedo), d(sc.rough), d(sc.metal), envd.ctypes.data_as(dptr),
+                           envd.shape[0], envd.shape[1], S, sd & 0xFFFFFFFF, int(per_point),
+                           float(offset), t_min, alpha_min, alpha_max, T_min,
+                           rgb.ctypes.data_as(dptr), irr.ctypes.data_as(dptr),
+                           samples.ctypes.data_as(dptr), flags.ctypes.data_as(iptr))
+    del keep
+    amb = flags.astype(bool)
+    return {"rgb": rgb, "irr": irr, "samples": samples, "ray_amb": amb, "amb": amb.any(axis=1)}
 
 
 # ------------------------------------------------------------------------------------------

@@ -701,3 +701,63 @@ void orc_bake_rays(int G, const double* mean, const double* scale, const double*
   }
   free(SI);
 }
+
+/* ------------------------------------------------------------------------------------
+ * Traced shading (the per-sample tracing that the probes stand in for, Sec. 3.1.2): the
+ * estimate of orc_shade (Eq. 6-8 with the Hammersley set of Eq. 7) where O and L_in of
+ * sample j come from a ray through the Gaussians instead of the probes. The ray of sample
+ * j of point i starts at o = fmaf(offset, n, x) per component in float32 (x and n are the
+ * float32 inputs) and runs along w_j; it is blended as a bake ray (trace_ray).
+ * rgb [N][3]; irr [N][3], samples [N][S][4] (R,G,B,O) and ray_flags [N][S] (1 = the ray
+ * is ambiguous, see trace_ray) may be NULL.
+ * ----------------------------------------------------------------------------------*/
+void orc_shade_traced(int G, const double* mean, const double* scale, const double* rot,
+                      const double* opacity, const double* color, long N, const double* pos,
+                      const double* normal, const double* view, const double* cam, long ppf,
+                      const double* albedo, const double* rough, const double* metal,
+                      const double* env, int H, int W, int S, uint32_t seed, int per_point,
+                      float offset, double t_min, double alpha_min, double alpha_max,
+                      double T_min, double* rgb, double* irr, double* samples,
+                      int32_t* ray_flags) {
+  orc_points p = {N, pos, normal, view, cam, ppf, albedo, rough, metal};
+  double* SI = gaussian_inverse_cov(G, scale, rot);
+#pragma omp parallel
+  {
+    orc_hit* hits = (orc_hit*)malloc(sizeof(orc_hit) * (G > 0 ? G : 1));
+#pragma omp for schedule(dynamic, 1)
+    for (long i = 0; i < N; ++i) {
+      double n[3], v[3], a[3], o[3];
+      for (int c = 0; c < 3; ++c) {
+        n[c] = normal[3 * i + c];
+        a[c] = albedo[3 * i + c];
+        o[c] = (double)fmaf(offset, (float)n[c], (float)pos[3 * i + c]);
+      }
+      point_view(&p, i, v);
+      double r = rough[i], m = metal[i];
+      uint32_t rho = orc_rotation24(seed, per_point, (uint32_t)i);
+      double acc[3] = {0, 0, 0}, acc_e[3] = {0, 0, 0};
+      for (int j = 0; j < S; ++j) {
+        double w[3], tr[5], Lenv[3], f[3];
+        double ct = orc_direction(j, S, rho, n, w);
+        int amb = trace_ray(G, mean, SI, opacity, color, o, w, t_min, alpha_min, alpha_max,
+                            T_min, hits, tr, NULL);
+        if (ray_flags) ray_flags[i * S + j] = amb;
+        if (samples)
+          for (int c = 0; c < 4; ++c) samples[(i * S + j) * 4 + c] = tr[c];
+        orc_env_fetch(env, H, W, w, Lenv);
+        orc_brdf(n, v, w, a, r, m, f);
+        for (int c = 0; c < 3; ++c) {
+          double Li = (1.0 - tr[3]) * Lenv[c] + tr[c];
+          acc[c] += f[c] * Li * ct;
+          acc_e[c] += Li * ct;
+        }
+      }
+      for (int c = 0; c < 3; ++c) {
+        rgb[3 * i + c] = 2.0 * OR_PI / S * acc[c];
+        if (irr) irr[3 * i + c] = 2.0 * OR_PI / S * acc_e[c];
+      }
+    }
+    free(hits);
+  }
+  free(SI);
+}
