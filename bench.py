@@ -69,6 +69,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-proposal-study", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=6000)
+    ap.add_argument("--no-trace-study", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -278,6 +279,12 @@ def main() -> int:
                                             out=rgb_p, net=mlp_obj, mix_eps=MIX_EPS))
     proposal_paths = {"two_call_ms": round(t_two, 4), "fused_ms": round(t_fused, 4)}
 
+    trace = None
+    if not args.no_trace_study:
+        trace = trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb_p,
+                            S, phase, (sc.bounds_lo, sc.bounds_hi))
+        print(f"# trace study: {json.dumps(trace)}", file=sys.stderr, flush=True)
+
     study = None
     if not args.no_proposal_study:
         study = proposal_study(torch, dev, args.proposal_steps)
@@ -304,6 +311,7 @@ def main() -> int:
         "shade_roofline": shade_roof,
         "proposal_paths": proposal_paths,
         "proposal_study": study,
+        "trace_study": trace,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -393,6 +401,88 @@ def proposal_study(torch, dev, steps: int) -> dict:
             "speedup_path": ("fused" if t_fused < t_two else "two_call") if s_star else None,
             "two_call_ms_at_S_star": round(t_two, 4) if s_star else None,
             "fused_ms_at_S_star": round(t_fused, 4)}
+
+
+def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb, S, phase,
+                bounds, subset=4096, S_ref=4096, seed_ref=77) -> dict:
+    """Traced shading (every sample's O and L_in from its own ray through the Gaussians)
+    against probe shading on the object workload: the time of each at the step's S, and
+    their errors against a traced reference at S_ref directions on a point subset. The
+    errors are taken on the irradiance output (the cosine-weighted incident light, which
+    holds exactly what the probes approximate, O and L_in, without the noise of sampling
+    narrow specular lobes uniformly); S* is the fewest traced directions whose error is at
+    most the probes' error at S."""
+    import numpy as np
+    dev = pts.pos.device
+    N = pts.n
+    offset = 0.01 * scenes.OBJECT_DIAGONAL
+    H, W = int(env.shape[0]), int(env.shape[1])
+    lib = bake_plan._lib
+    rgb_t = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    # rays of nearby points are traced together: a plan over the shading points orders them
+    torch.cuda.synchronize()
+    t0 = time.time()
+    order = sop.Plan(pts.pos, bounds[0], bounds[1])
+    torch.cuda.synchronize()
+    t_order = (time.time() - t0) * 1e3
+
+    def ws_for(n, s):
+        return sop.workspace(lib.sop_shade_traced_workspace_size(order.handle, n, s, H, W, 0),
+                             dev)
+
+    ws_t = ws_for(N, S)
+    t_trace = time_ms(lambda: sop.sop_shade_traced(bake_plan, env, pts, S, offset,
+                                                   order_by=order, ws=ws_t, out=rgb_t), reps=3)
+    del ws_t
+    rgb_sop, irr_sop = sop.sop_shade(plan, tex, env, pts, S, nb=nb, irradiance=True)
+    rows = torch.from_numpy(np.sort(np.random.default_rng(11).choice(N, subset, replace=False)))
+    rows = rows.to(dev)
+    sub = sop.Points(pts.pos[rows], pts.normal[rows], pts.albedo[rows], pts.rough[rows],
+                     pts.metal[rows], view=pts.view[rows])
+    _, ref = sop.sop_shade_traced(bake_plan, env, sub, S_ref, offset, seed=seed_ref,
+                                  irradiance=True, order_by=order)
+    den = float((ref.double() ** 2).mean())
+
+    def rel_rmse(x):
+        return float(((x.double() - ref.double()) ** 2).mean() / den) ** 0.5
+
+    err_sop = rel_rmse(irr_sop[rows])
+    err_trace = {}
+    for s in (4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        _, irr = sop.sop_shade_traced(bake_plan, env, sub, s, offset, irradiance=True,
+                                      order_by=order)
+        err_trace[s] = rel_rmse(irr)
+    # the probes' own bias: probe shading against traced shading with the same directions
+    rgb_tr_S, irr_tr_S = sop.sop_shade_traced(bake_plan, env, sub, S, offset, irradiance=True,
+                                              order_by=order)
+    bias = float(((irr_sop[rows].double() - irr_tr_S.double()) ** 2).mean() / den) ** 0.5
+    s_star = min((s for s, e in err_trace.items() if e <= err_sop), default=None)
+    t_star = None
+    if s_star is not None:
+        ws_s = ws_for(N, s_star)
+        t_star = time_ms(lambda: sop.sop_shade_traced(bake_plan, env, pts, s_star, offset,
+                                                      order_by=order, ws=ws_s, out=rgb_t),
+                         reps=3)
+        del ws_s
+    t_sop = phase["shade_fwd"]
+    t_bake = phase["bake"] + phase["bake_grid"]
+    return {
+        "workload": "object_scene: 100k Gaussians, 200k points, rays from x + 1% of the "
+                    "diagonal along n, env 256x512",
+        "dirs": S, "trace_ms": round(t_trace, 3), "rays_per_s": round(N * S / (t_trace * 1e-3)),
+        "point_order_ms": round(t_order, 3),
+        "sop_shade_ms": round(t_sop, 4), "sop_bake_ms": round(t_bake, 3),
+        "speedup_same_dirs": round(t_trace / t_sop, 2),
+        "speedup_same_dirs_with_bake": round(t_trace / (t_sop + t_bake), 3),
+        "error_on": "irradiance", "ref_dirs": S_ref, "ref_points": subset,
+        "rel_rmse_sop": round(err_sop, 5),
+        "rel_rmse_sop_vs_trace_same_dirs": round(bias, 5),
+        "rel_rmse_trace": {str(k): round(v, 5) for k, v in err_trace.items()},
+        "S_star": s_star, "trace_ms_at_S_star": None if t_star is None else round(t_star, 3),
+        "speedup_matched": None if t_star is None else round(t_star / t_sop, 2),
+        "speedup_matched_with_bake": None if t_star is None else round(t_star / (t_sop + t_bake),
+                                                                       3),
+    }
 
 
 def copy_calibration(torch, dev) -> int:

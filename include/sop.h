@@ -317,6 +317,41 @@ sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n
                     sop_stream stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Traced shading: the per-sample ray tracing that the probes stand in for (Sec. 3.1.2:
+ * occlusion and indirect light are read from the probes instead of tracing the Gaussians
+ * for every sample; Sec. 4 compares rendering with probes against tracing). The estimate
+ * of sop_shade with the Hammersley sampler (same directions, BRDF and sums), where O(w_j)
+ * and L_in(w_j) of sample j of point i come from one ray through the Gaussians of `gauss`:
+ * the ray starts at o_i = fmaf(offset, n_i, x_i) (per component, IEEE single precision),
+ * runs along w_j and is blended exactly as sop_bake blends a texel's ray, with the plan's
+ * t_min, alpha_min, alpha_max and T_min: L_in = sum T alpha color, O = sum T alpha.
+ *   - order_by (may be NULL): a plan whose grid orders the points so that rays of nearby
+ *     points are traced together. Any plan over the same bounds serves; one built over
+ *     the shading points themselves has the finest cells for them. The results do not
+ *     depend on it.
+ *   - opts: n_dirs, seed, rotate_per_point and out_irradiance are used and the sampler
+ *     must be SOP_SAMPLER_HAMMERSLEY (else SOP_ERR_UNSUPPORTED); k, radius, probs and net
+ *     are ignored.
+ *   - offset: finite and >= 0, world units along the normal.
+ *   - samples (may be NULL): device [N,S,4] f32, 16-byte aligned; receives (L_in rgb, O)
+ *     of every sample in the caller's point order. When NULL the workspace holds them.
+ * Writes rgb[N,3] (and out_irradiance). If the last update of `gauss` overflowed its grid,
+ * the samples and so rgb are NaN (sop_bake_plan_check reports it). Workspace:
+ * sop_shade_traced_workspace_size with the same order_by, N, S, environment and samples. */
+sop_status sop_shade_traced(const sop_bake_plan* gauss, const sop_plan* order_by,
+                            const sop_envmap* env, const sop_points* pts,
+                            const sop_shade_opts* opts, float offset, float* rgb,
+                            float* samples, void* ws, size_t ws_bytes, sop_stream stream);
+
+/* Workspace bytes of sop_shade_traced for n_points points, n_dirs directions and an
+ * env_height x env_width environment; with_samples != 0 when the call passes `samples`
+ * (otherwise the workspace also holds the 16 * n_points * n_dirs bytes of samples).
+ * order_by as in the call (may be NULL). Returns 0 on an invalid argument. */
+size_t sop_shade_traced_workspace_size(const sop_plan* order_by, int64_t n_points,
+                                       int32_t n_dirs, int32_t env_height, int32_t env_width,
+                                       int32_t with_samples);
+
+/* ----------------------------------------------------------------------------------------
  * Learned direction proposal: an extension of the Monte Carlo estimate of Eq. 7 (the paper
  * uses a fixed Hammersley set; here the directions can instead be importance sampled from a
  * per-point distribution that a small network predicts, trained on integrand samples that

@@ -100,6 +100,9 @@ SIGNATURES = {
     "sop_bake_plan_check": (c_i32, [c_vp, c_vp]),
     "sop_bake_plan_destroy": (c_i32, [c_vp]),
     "sop_bake": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "sop_shade_traced": (c_i32, [c_vp, c_vp, P(sop_envmap), P(sop_points), P(sop_shade_opts),
+                                 c_f32, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_shade_traced_workspace_size": (C.c_size_t, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32]),
     "sop_proposal_workspace_size": (C.c_size_t, [c_i32, c_i64]),
     "sop_proposal_infer": (c_i32, [P(sop_mlp), P(sop_points), c_vp, c_vp, c_vp, C.c_size_t,
                                    c_vp]),

@@ -1056,6 +1056,113 @@ extern "C" sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos
 }
 
 // ------------------------------------------------------------------------------------------
+// traced shading
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Workspace layout: [direction table, environment references] [order, order scratch]
+// [samples when the caller passes none]
+size_t traced_ws(const sop_plan* order_by, int64_t N, int32_t S, int32_t H, int32_t W,
+                 bool with_samples) {
+  Bump b{nullptr, 0, 0};
+  (void)b.take<double4>((size_t)S);
+  (void)b.take<double2>((size_t)W + 2);
+  (void)b.take<double2>((size_t)H + 2);
+  if (order_by) {
+    (void)b.take<int32_t>((size_t)N);
+    carve_knn(b, order_by, N);
+  }
+  if (!with_samples) (void)b.take<float4>((size_t)N * S);
+  return b.used;
+}
+
+}  // namespace
+
+extern "C" size_t sop_shade_traced_workspace_size(const sop_plan* order_by, int64_t n_points,
+                                                  int32_t n_dirs, int32_t env_height,
+                                                  int32_t env_width, int32_t with_samples) {
+  if (n_points < 0 || n_dirs < 1 || n_dirs > SOP_MAX_DIRS || env_height < 0 || env_width < 0)
+    return 0;
+  const size_t need =
+      traced_ws(order_by, n_points, n_dirs, env_height, env_width, with_samples != 0);
+  return need > 0 ? need : 256;
+}
+
+extern "C" sop_status sop_shade_traced(const sop_bake_plan* gauss, const sop_plan* order_by,
+                                       const sop_envmap* env, const sop_points* pts,
+                                       const sop_shade_opts* opts, float offset, float* rgb,
+                                       float* samples, void* ws, size_t ws_bytes,
+                                       sop_stream stream) {
+  if (!gauss) return fail(SOP_ERR_INVALID_ARGUMENT, "gauss is NULL");
+  if (!opts) return fail(SOP_ERR_INVALID_ARGUMENT, "opts is NULL");
+  sop_status st = validate_points(pts);
+  if (st != SOP_OK) return st;
+  if ((st = validate_env(env)) != SOP_OK) return st;
+  if (opts->n_dirs < 1 || opts->n_dirs > SOP_MAX_DIRS)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
+  if (opts->sampler != SOP_SAMPLER_HAMMERSLEY)
+    return fail(SOP_ERR_UNSUPPORTED, "traced shading uses the Hammersley sampler only");
+  if (!(offset >= 0.0f) || !std::isfinite(offset))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "offset must be finite and >= 0");
+  if (pts->count > 0 && (!rgb || !aligned(rgb, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "rgb is NULL or misaligned");
+  if (samples && !aligned(samples, 16))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "samples not 16-byte aligned");
+  if (opts->out_irradiance && !aligned(opts->out_irradiance, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "out_irradiance misaligned");
+  const int64_t N = pts->count;
+  const int32_t S = opts->n_dirs;
+  // one wavefront per 32 points and direction, four per workgroup
+  if ((N + 31) / 32 > ((int64_t)INT32_MAX * 4) / S)
+    return fail(SOP_ERR_UNSUPPORTED, "too many samples for one launch");
+  const size_t need = traced_ws(order_by, N, S, env->height, env->width, samples != nullptr);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (N == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = N;
+  a.pos = pts->pos;
+  a.nrm = pts->normal;
+  a.view = pts->view;
+  a.cam = pts->cam_pos;
+  a.ppf = pts->points_per_frame > 0 ? pts->points_per_frame : 1;
+  a.albedo = pts->albedo;
+  a.rough = pts->roughness;
+  a.metal = pts->metallic;
+  set_dirs(a, env, opts);
+  a.rgb = rgb;
+  a.irr = opts->out_irradiance;
+  Bump b{(char*)ws, 0, ws_bytes};
+  if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
+  int32_t* order = nullptr;
+  if (order_by) {
+    order = b.take<int32_t>((size_t)N);
+    KnnScratch ks = carve_knn(b, order_by, N);
+    SOP_HIP(sopk::launch_point_order(order_by->view(), pts->pos, N, ks.point_cell, ks.counts,
+                                     ks.offsets, ks.scan_tmp, order, s),
+            "sop_shade_traced");
+  }
+  float4* buf = samples ? reinterpret_cast<float4*>(samples) : b.take<float4>((size_t)N * S);
+  sopk::TraceArgs t;
+  t.n = N;
+  t.S = S;
+  t.pos = pts->pos;
+  t.nrm = pts->normal;
+  t.order = order;
+  t.dir_tab = a.dir_tab;
+  t.seed = opts->seed;
+  t.per_point = opts->rotate_per_point ? 1 : 0;
+  t.offset = offset;
+  t.out = buf;
+  SOP_HIP(sopk::launch_trace_samples(gauss->grid, t, s), "sop_shade_traced");
+  a.order = order;
+  a.traced = buf;
+  SOP_HIP(sopk::launch_shade_traced(a, s), "sop_shade_traced");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
 extern "C" const char* sop_status_string(sop_status s) {
   switch (s) {
     case SOP_OK: return "ok";

@@ -343,60 +343,18 @@ __device__ __forceinline__ double ray_min(double x) {
   return x;
 }
 
-// The kernel needs three wavefronts per SIMD (at most 168 registers; it uses 168): at two
-// it runs ~40% slower, so any change here has to keep the register count.
-__global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
-                                              int32_t R, float* texels, float* depth,
-                                              const int4* order) {
-  // kLpr lanes trace one ray and split each cell's candidates between them; a wavefront
-  // holds 64/kLpr rays of one probe, taken in Z order inside 8x8 texel tiles so that they
-  // stay coherent; consecutive workgroups take consecutive probes of the order
-  const int32_t tiles_x = (R + 7) >> 3;
-  const int64_t per_probe = (int64_t)tiles_x * tiles_x * 64;
-  const int lane = threadIdx.x & 63;
-  const int g = lane & (kLpr - 1);
-  const int64_t ray = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / kLpr) + lane / kLpr;
-  if (ray >= (int64_t)P * per_probe) return;      // whole groups leave together
-  const int32_t slot = (int32_t)(ray / per_probe);
-  const int32_t p = order ? order[slot].w : slot;
-  if ((uint32_t)p >= (uint32_t)P) return;
-  const int32_t within = (int32_t)(ray % per_probe);
-  const int32_t tile = within >> 6, q = within & 63;
-  const int32_t ti = (tile % tiles_x) * 8 + ((q & 1) | ((q >> 1) & 2) | ((q >> 2) & 4));
-  const int32_t tj = (tile / tiles_x) * 8 + (((q >> 1) & 1) | ((q >> 2) & 2) | ((q >> 3) & 4));
-  if (ti >= R || tj >= R) return;
-  const size_t texel = (size_t)p * R * R + (size_t)tj * R + ti;
+// Blended result of one ray: (R, G, B) = sum T alpha color, O = sum T alpha and
+// dt = sum T alpha t* (the depth numerator); every lane of the ray returns the same values.
+struct RayResult {
+  float r, g, b, o, dt;
+};
 
-  if (G.overflow && *G.overflow) {
-    if (g == 0) {
-      const float nan = __int_as_float(0x7FC00000);
-      reinterpret_cast<float4*>(texels)[texel] = make_float4(nan, nan, nan, nan);
-      if (depth) depth[texel] = nan;
-    }
-    return;
-  }
-
-  __shared__ int32_t screened[4][kCap][64];      // per wavefront: kept candidates per lane
-  int32_t* mylist = &screened[threadIdx.x >> 6][0][lane];
-  const v3 o = mk3(probe_pos[3 * p], probe_pos[3 * p + 1], probe_pos[3 * p + 2]);
-  // ray direction in FP64 (the candidate test below runs in FP64: a Gaussian of scale 0.01
-  // one unit away turns a 1e-7 direction error into 1e-5 in its Mahalanobis distance);
-  // the grid walk uses its FP32 rounding
-  double d64[3];
-  {
-    double px = 2.0 * (ti + 0.5) / (double)R - 1.0, py = 2.0 * (tj + 0.5) / (double)R - 1.0;
-    const double z = 1.0 - fabs(px) - fabs(py);
-    if (z < 0.0) {
-      const double fx = (1.0 - fabs(py)) * (px < 0.0 ? -1.0 : 1.0);
-      const double fy = (1.0 - fabs(px)) * (py < 0.0 ? -1.0 : 1.0);
-      px = fx;
-      py = fy;
-    }
-    const double il = 1.0 / sqrt(px * px + py * py + z * z);
-    d64[0] = px * il;
-    d64[1] = py * il;
-    d64[2] = z * il;
-  }
+// Traces the ray o + t d64 through the registered Gaussians. The kLpr consecutive lanes
+// that share the ray call it together with their rank g in the ray; mylist is the lane's
+// column of the wavefront's LDS candidate list.
+__device__ __forceinline__ RayResult trace_ray(const BakeGrid& G, const v3& o,
+                                               const double (&d64)[3], int g,
+                                               int32_t* mylist) {
   const v3 d = mk3((float)d64[0], (float)d64[1], (float)d64[2]);
   const float dd[3] = {d.x, d.y, d.z}, oo[3] = {o.x, o.y, o.z};
 
@@ -582,9 +540,128 @@ __global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos
       c[axis] += step[axis];
     }
   }
+  RayResult res;
+  res.r = Cr;
+  res.g = Cg;
+  res.b = Cb;
+  res.o = Wt;
+  res.dt = Dp;
+  return res;
+}
+
+// The kernel needs three wavefronts per SIMD (at most 168 registers; it uses 168): at two
+// it runs ~40% slower, so any change here has to keep the register count.
+__global__ __launch_bounds__(256) void k_bake(BakeGrid G, const float* probe_pos, int32_t P,
+                                              int32_t R, float* texels, float* depth,
+                                              const int4* order) {
+  // kLpr lanes trace one ray and split each cell's candidates between them; a wavefront
+  // holds 64/kLpr rays of one probe, taken in Z order inside 8x8 texel tiles so that they
+  // stay coherent; consecutive workgroups take consecutive probes of the order
+  const int32_t tiles_x = (R + 7) >> 3;
+  const int64_t per_probe = (int64_t)tiles_x * tiles_x * 64;
+  const int lane = threadIdx.x & 63;
+  const int g = lane & (kLpr - 1);
+  const int64_t ray = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 / kLpr) + lane / kLpr;
+  if (ray >= (int64_t)P * per_probe) return;      // whole groups leave together
+  const int32_t slot = (int32_t)(ray / per_probe);
+  const int32_t p = order ? order[slot].w : slot;
+  if ((uint32_t)p >= (uint32_t)P) return;
+  const int32_t within = (int32_t)(ray % per_probe);
+  const int32_t tile = within >> 6, q = within & 63;
+  const int32_t ti = (tile % tiles_x) * 8 + ((q & 1) | ((q >> 1) & 2) | ((q >> 2) & 4));
+  const int32_t tj = (tile / tiles_x) * 8 + (((q >> 1) & 1) | ((q >> 2) & 2) | ((q >> 3) & 4));
+  if (ti >= R || tj >= R) return;
+  const size_t texel = (size_t)p * R * R + (size_t)tj * R + ti;
+
+  if (G.overflow && *G.overflow) {
+    if (g == 0) {
+      const float nan = __int_as_float(0x7FC00000);
+      reinterpret_cast<float4*>(texels)[texel] = make_float4(nan, nan, nan, nan);
+      if (depth) depth[texel] = nan;
+    }
+    return;
+  }
+
+  __shared__ int32_t screened[4][kCap][64];      // per wavefront: kept candidates per lane
+  int32_t* mylist = &screened[threadIdx.x >> 6][0][lane];
+  const v3 o = mk3(probe_pos[3 * p], probe_pos[3 * p + 1], probe_pos[3 * p + 2]);
+  // ray direction in FP64 (the candidate test below runs in FP64: a Gaussian of scale 0.01
+  // one unit away turns a 1e-7 direction error into 1e-5 in its Mahalanobis distance);
+  // the grid walk uses its FP32 rounding
+  double d64[3];
+  {
+    double px = 2.0 * (ti + 0.5) / (double)R - 1.0, py = 2.0 * (tj + 0.5) / (double)R - 1.0;
+    const double z = 1.0 - fabs(px) - fabs(py);
+    if (z < 0.0) {
+      const double fx = (1.0 - fabs(py)) * (px < 0.0 ? -1.0 : 1.0);
+      const double fy = (1.0 - fabs(px)) * (py < 0.0 ? -1.0 : 1.0);
+      px = fx;
+      py = fy;
+    }
+    const double il = 1.0 / sqrt(px * px + py * py + z * z);
+    d64[0] = px * il;
+    d64[1] = py * il;
+    d64[2] = z * il;
+  }
+  const RayResult res = trace_ray(G, o, d64, g, mylist);
   if (g == 0) {
-    reinterpret_cast<float4*>(texels)[texel] = make_float4(Cr, Cg, Cb, Wt);
-    if (depth) depth[texel] = Wt > 0.0f ? Dp / Wt : 0.0f;
+    reinterpret_cast<float4*>(texels)[texel] = make_float4(res.r, res.g, res.b, res.o);
+    if (depth) depth[texel] = res.o > 0.0f ? res.dt / res.o : 0.0f;
+  }
+}
+
+// Traced shading rays: sample j of point p starts at fmaf(offset, n_p, x_p) (per component,
+// FP32) and runs along the sample's world direction, entry j of the shading call's
+// direction table turned into the frame of n_p exactly as the shading kernels turn it. A
+// wavefront takes 64/kLpr consecutive points of the processing order with one direction,
+// so that its rays start close together and leave their surface at the same angle (which
+// keeps their lengths alike); the wavefronts of a workgroup take consecutive directions of
+// the same points.
+__global__ __launch_bounds__(256) void k_trace_samples(BakeGrid G, TraceArgs t) {
+  constexpr int kRays = 64 / kLpr;
+  const int lane = threadIdx.x & 63;
+  const int g = lane & (kLpr - 1);
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t chunks = (t.n + kRays - 1) / kRays;
+  if (wave >= chunks * t.S) return;               // whole wavefronts leave together
+  const int64_t chunk = wave / t.S;
+  const int32_t j = (int32_t)(wave - chunk * t.S);
+  const int64_t slot = chunk * kRays + lane / kLpr;
+  if (slot >= t.n) return;                         // the lanes of a ray leave together
+  int64_t p = slot;
+  if (t.order) {
+    const int32_t q = t.order[slot];
+    if ((uint64_t)q >= (uint64_t)t.n) return;
+    p = q;
+  }
+  if (G.overflow && *G.overflow) {
+    if (g == 0) {
+      const float nan = __int_as_float(0x7FC00000);
+      t.out[p * t.S + j] = make_float4(nan, nan, nan, nan);
+    }
+    return;
+  }
+
+  __shared__ int32_t screened[4][kCap][64];
+  int32_t* mylist = &screened[threadIdx.x >> 6][0][lane];
+  const float nx = t.nrm[3 * p], ny = t.nrm[3 * p + 1], nz = t.nrm[3 * p + 2];
+  const v3 o = mk3(fmaf(t.offset, nx, t.pos[3 * p]), fmaf(t.offset, ny, t.pos[3 * p + 1]),
+                   fmaf(t.offset, nz, t.pos[3 * p + 2]));
+  const double4 e = t.dir_tab[j];
+  double da = e.x, db = e.y;
+  if (t.per_point) {
+    double sr, cr;
+    sincospi((double)rotation24(t.seed, true, (uint32_t)p) * 0x1p-23, &sr, &cr);
+    da = e.x * cr - e.y * sr;
+    db = e.x * sr + e.y * cr;
+  }
+  double d64[3];
+  world_dir64(make_frame64(nx, ny, nz), da, db, e.z, d64);
+  const RayResult res = trace_ray(G, o, d64, g, mylist);
+  // the point index is read again rather than held through the trace (registers)
+  if (g == 0) {
+    const int64_t q = t.order ? (int64_t)__builtin_nontemporal_load(&t.order[slot]) : slot;
+    t.out[q * t.S + j] = make_float4(res.r, res.g, res.b, res.o);
   }
 }
 
@@ -627,6 +704,15 @@ hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int
   const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(k_bake, dim3((unsigned)blocks), dim3(256), 0, s, G, probe_pos, P, R,
                      texels, depth, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_samples(const BakeGrid& G, const TraceArgs& t, hipStream_t s) {
+  const int64_t chunks = (t.n + (64 / kLpr) - 1) / (64 / kLpr);
+  const int64_t blocks = (chunks * t.S + 3) / 4;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > INT32_MAX || !t.pos || !t.nrm || !t.dir_tab || !t.out) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trace_samples, dim3((unsigned)blocks), dim3(256), 0, s, G, t);
   return hipGetLastError();
 }
 

@@ -241,6 +241,66 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// Traced shading: the estimate of k_shade_fwd with L_in and O of every sample read from its
+// traced ray (a.traced, [n,S] in the caller's point order) instead of the probes.
+template <int L>
+__global__ __launch_bounds__(256) void k_shade_traced(ShadeArgs a) {
+  const int lane = threadIdx.x & 63, li = lane % L;
+  const int64_t slot = group_slot<L>(lane);
+  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+  PointState ps;
+  const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
+  if (L == 64 && !valid) return;
+  float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
+  if (valid) {
+    const float4* tr = a.traced + ps.p * a.S;
+    for (int j = li; j < a.S; j += L) {
+      const double4 e = a.dir_tab[j];
+      const double da = e.x * ps.cr - e.y * ps.sr;
+      const double db = e.x * ps.sr + e.y * ps.cr;
+      double w64[3];
+      world_dir64(ps.F, da, db, e.z, w64);
+      const float ct = (float)e.z;
+      const EnvTaps et = env_taps64(w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
+      float Le[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float* ep = a.env + 3 * (size_t)et.off[t];
+        Le[0] += et.w[t] * ep[0];
+        Le[1] += et.w[t] * ep[1];
+        Le[2] += et.w[t] * ep[2];
+      }
+      const float4 q = tr[j];
+      const float Lin[3] = {q.x, q.y, q.z};
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, w64), ct);
+      const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - q.w) * Le[c] + Lin[c];
+        acc[c] += fcos(ps.M, bt, al[c], ct) * Li;
+        acc_e[c] += Li * ct;
+      }
+    }
+  }
+  float r[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc[c]) * a.scale;
+  if (valid && li == 0) {
+    a.rgb[3 * ps.p] = r[0];
+    a.rgb[3 * ps.p + 1] = r[1];
+    a.rgb[3 * ps.p + 2] = r[2];
+  }
+  if (a.irr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc_e[c]) * a.scale;
+    if (valid && li == 0) {
+      a.irr[3 * ps.p] = r[0];
+      a.irr[3 * ps.p + 1] = r[1];
+      a.irr[3 * ps.p + 2] = r[2];
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Learned direction proposal: importance-sampled estimate of Eq. 7. Directions are drawn
 // from 16x16 bins over the hemispherical octahedral square of the local frame,
@@ -1064,6 +1124,17 @@ static hipError_t dispatch(bool fwd, const ShadeArgs& a, int32_t k, int32_t form
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   return dispatch(true, a, k, format, s);
 }
+hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (!a.traced) return hipErrorInvalidValue;
+  switch (lanes_for(a.S)) {
+    case 16: hipLaunchKernelGGL(k_shade_traced<16>, grid_for(a.n, 16), dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_shade_traced<32>, grid_for(a.n, 32), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_shade_traced<64>, grid_for(a.n, 64), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 size_t batched_lds_bytes(int32_t R) {
   return (size_t)kBatch * R * R * 4 * sizeof(float) + 5 * kMaxEntries * 4 +
          (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kEnvRuns * sizeof(EnvRun);

@@ -84,6 +84,7 @@ struct ShadeArgs {
   int32_t per_point;
   float* rgb;
   float* irr;
+  const float4* traced;     // [n,S] (L_in rgb, O) per sample (traced shading)
   // learned proposal sampler / training targets
   const float* probs;       // [n,256] bin distributions
   float mix_eps;
@@ -140,6 +141,8 @@ hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipSt
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+// traced shading: the estimate of launch_shade_fwd with a.traced for L_in and O
+hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_shade_prop_net(const ShadeArgs& a, int32_t k, int32_t format,
                                  hipStream_t s);
 hipError_t launch_query(const ShadeArgs& a, int32_t k, int32_t format, const float* dirs,
@@ -169,6 +172,20 @@ hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* co
 hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_t* cell_start,
                              int32_t* cursor, int32_t* entries, int32_t capacity,
                              int32_t* overflow, hipStream_t s);
+// traced shading: one ray per (point, direction) sample
+struct TraceArgs {
+  int64_t n;                // points
+  int32_t S;                // directions per point
+  const float* pos;         // [n,3]
+  const float* nrm;         // [n,3]
+  const int32_t* order;     // [n] processing order (a permutation) or NULL
+  const double4* dir_tab;   // [S] local directions of the call (see dir_entry)
+  uint32_t seed;            // direction rotation seed
+  int32_t per_point;        // 1: one rotation per point
+  float offset;             // ray origin fmaf(offset, n, x)
+  float4* out;              // [n,S] (L_in rgb, O), caller's point order
+};
+hipError_t launch_trace_samples(const BakeGrid& G, const TraceArgs& t, hipStream_t s);
 hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
                        float* texels, float* depth, const int4* order, hipStream_t s);
 

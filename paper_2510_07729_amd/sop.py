@@ -459,3 +459,35 @@ def sop_bake(plan: BakePlan, probe_pos: torch.Tensor, res: int, depth: bool = Tr
                                order_by.handle if order_by is not None else None,
                                _stream()), "sop_bake")
     return tex, dep
+
+
+def sop_shade_traced(plan: BakePlan, env: torch.Tensor, pts: Points, n_dirs: int,
+                     offset: float, seed: int = 0, rotate_per_point: bool = False,
+                     irradiance: bool = False, order_by: Optional[Plan] = None,
+                     samples: bool = False, ws: Optional[torch.Tensor] = None,
+                     out: Optional[torch.Tensor] = None,
+                     samples_out: Optional[torch.Tensor] = None):
+    """Traced shading: rgb [N,3] with every sample's O and L_in from its own ray through
+    the plan's Gaussians, starting at fmaf(offset, n, x). Returns rgb, or a tuple
+    (rgb, irradiance [N,3] when asked, samples [N,S,4] when asked); order_by (a probe Plan)
+    orders the points for ray coherence without changing the result."""
+    dev = pts.pos.device
+    n = pts.n
+    rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
+    smp = samples_out
+    if samples and smp is None:
+        smp = torch.empty((n, int(n_dirs), 4), dtype=torch.float32, device=dev)
+    lib = plan._lib
+    oh = order_by.handle if order_by is not None else None
+    if ws is None:
+        nbytes = lib.sop_shade_traced_workspace_size(oh, n, int(n_dirs), int(env.shape[0]),
+                                                     int(env.shape[1]), int(smp is not None))
+        ws = workspace(nbytes, dev)
+    o = shade_opts(n_dirs, 1, seed, math.inf, rotate_per_point, irr)
+    e, cp = _env(env), pts.c()
+    L.check(lib.sop_shade_traced(plan.handle, oh, C.byref(e), C.byref(cp), C.byref(o),
+                                 float(offset), _ptr(rgb, torch.float32, "rgb"), _ptr(smp),
+                                 ws.data_ptr(), ws.numel(), _stream()), "sop_shade_traced")
+    res = (rgb,) + ((irr,) if irradiance else ()) + ((smp,) if smp is not None else ())
+    return res[0] if len(res) == 1 else res

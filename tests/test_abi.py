@@ -129,3 +129,44 @@ def test_errors_are_thread_local():
     t.join()
     assert "count" in lib.sop_last_error().decode()
     assert "pos" in other["msg"]
+
+
+def test_traced_shading_validation():
+    """Every call below fails validation, so the stand-in plan pointer is never read."""
+    lib = L.load()
+    fake = C.c_void_p(0x1000)
+    pts = L.sop_points()
+    pts.count = 10
+    for f in ("pos", "normal", "view", "albedo", "roughness", "metallic"):
+        setattr(pts, f, 0x1000)
+    env = L.sop_envmap()
+    env.height, env.width, env.texels = 4, 8, 0x1000
+    o = L.sop_shade_opts()
+    o.n_dirs = 16
+    rgb = 0x2000
+    big = 1 << 30
+
+    def call(gauss=fake, opts=o, offset=0.01, samples=None, ws_bytes=big, ws=0x10000):
+        return lib.sop_shade_traced(gauss, None, C.byref(env), C.byref(pts),
+                                    C.byref(opts) if opts is not None else None, offset, rgb,
+                                    samples, ws, ws_bytes, None)
+
+    assert call(gauss=None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert call(opts=None) == L.SOP_ERR_INVALID_ARGUMENT
+    for bad in (-1e-3, math.inf, math.nan):
+        assert call(offset=bad) == L.SOP_ERR_INVALID_ARGUMENT
+        assert "offset" in lib.sop_last_error().decode()
+    assert call(samples=0x2004) == L.SOP_ERR_INVALID_ARGUMENT       # not 16-byte aligned
+    o.sampler = L.SOP_SAMPLER_PROPOSAL
+    assert call() == L.SOP_ERR_UNSUPPORTED
+    o.sampler = L.SOP_SAMPLER_HAMMERSLEY
+    o.n_dirs = 0
+    assert call() == L.SOP_ERR_INVALID_ARGUMENT
+    o.n_dirs = 16
+    need = lib.sop_shade_traced_workspace_size(None, 10, 16, 4, 8, 0)
+    assert need >= 10 * 16 * 16
+    assert lib.sop_shade_traced_workspace_size(None, 10, 16, 4, 8, 1) < need
+    assert call(ws_bytes=need - 256) == L.SOP_ERR_WORKSPACE_TOO_SMALL
+    assert lib.sop_shade_traced_workspace_size(None, 10, 0, 4, 8, 0) == 0
+    assert lib.sop_shade_traced_workspace_size(None, 10, 5000, 4, 8, 0) == 0
+    assert lib.sop_shade_traced_workspace_size(None, -1, 16, 4, 8, 0) == 0
