@@ -70,6 +70,9 @@ def main() -> int:
     ap.add_argument("--no-proposal-study", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=6000)
     ap.add_argument("--no-trace-study", action="store_true")
+    ap.add_argument("--trace-only", action="store_true",
+                    help="only traced shading of the object workload at 128 directions "
+                         "(1 warm-up + 3 timed calls; for kernel traces of that path)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -88,6 +91,8 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     if args.copy_calibration:
         return copy_calibration(torch, dev)
+    if args.trace_only:
+        return trace_only(torch, dev, sop, scenes)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
 
     # ------------------------------------------------------------------ workload (untimed)
@@ -483,6 +488,34 @@ def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb,
         "speedup_matched_with_bake": None if t_star is None else round(t_star / (t_sop + t_bake),
                                                                        3),
     }
+
+
+def trace_only(torch, dev, sop, scenes) -> int:
+    """Traced shading of the object workload (200k points, 128 directions, 100k Gaussians):
+    one warm-up and three timed calls, points ordered by a plan over themselves."""
+    import numpy as np
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    gs = scenes.object_gaussians()
+    sc = scenes.object_scene(textures=np.zeros((1, 2, 2, 4), np.float32))
+    bplan = sop.BakePlan(d(gs.mean), d(gs.scale), d(gs.rotation), d(gs.opacity), d(gs.color))
+    pts = sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                     view=d(sc.view))
+    env = d(sc.env)
+    order = sop.Plan(pts.pos, sc.bounds_lo, sc.bounds_hi)
+    off = 0.01 * scenes.OBJECT_DIAGONAL
+    rgb = sop.sop_shade_traced(bplan, env, pts, sc.n_dirs, off, order_by=order)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        sop.sop_shade_traced(bplan, env, pts, sc.n_dirs, off, order_by=order, out=rgb)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    print(json.dumps({"traced_shade_ms": round(ms, 3), "points": sc.n, "dirs": sc.n_dirs,
+                      "gaussians": gs.count,
+                      "rays_per_s": round(sc.n * sc.n_dirs / (ms * 1e-3))}), flush=True)
+    return 0
 
 
 def copy_calibration(torch, dev) -> int:

@@ -319,7 +319,7 @@ sop_status sop_bake(const sop_bake_plan* plan, const float* probe_pos, int32_t n
 /* ----------------------------------------------------------------------------------------
  * Traced shading: the per-sample ray tracing that the probes stand in for (Sec. 3.1.2:
  * occlusion and indirect light are read from the probes instead of tracing the Gaussians
- * for every sample; Sec. 4 compares rendering with probes against tracing). The estimate
+ * for every sample; the composition table of Sec. 4.2 compares the two). The estimate
  * of sop_shade with the Hammersley sampler (same directions, BRDF and sums), where O(w_j)
  * and L_in(w_j) of sample j of point i come from one ray through the Gaussians of `gauss`:
  * the ray starts at o_i = fmaf(offset, n_i, x_i) (per component, IEEE single precision),
