@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sop_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c"), os.path.join(_HERE, "shadow_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -111,6 +111,13 @@ def _sig(lib):
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dptr, iptr, iptr]
+    u64p = C.POINTER(C.c_uint64)
+    lib.orc_env_masses.argtypes = [fptr, C.c_int, u32p, u64p]
+    lib.orc_env_masses.restype = C.c_uint64
+    lib.orc_env_draw.argtypes = [u32p, u64p, C.c_int, C.c_int, C.c_int, u32, u32, dptr, dptr]
+    lib.orc_env_draw.restype = C.c_int
+    lib.orc_shadow_ratio.argtypes = [C.c_long, dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr,
+                                     C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr]
     lib.orc_shade_traced.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, C.c_long, dptr,
                                      dptr, dptr, dptr, C.c_long, dptr, dptr, dptr, dptr,
                                      C.c_int, C.c_int, C.c_int, u32, C.c_int, C.c_float,
@@ -442,6 +449,55 @@ def shade_traced(gs, sc, offset, n_dirs=None, seed=None, per_point=False, t_min=
     amb = flags.astype(bool)
     return {"rgb": rgb, "irr": irr, "samples": samples, "ray_amb": amb, "amb": amb.any(axis=1)}
 
+
+
+# ------------------------------------------------------------------------------------------
+# cast-shadow ratio (Eq. 15-18) on an octahedral environment map
+# ------------------------------------------------------------------------------------------
+def env_masses(env):
+    """Integer texel masses of an octahedral environment [R,R,3] (float32 decisions):
+    (mass [R*R] uint32, prefix [R*R+1] uint64)."""
+    env = np.ascontiguousarray(env, np.float32)
+    R = env.shape[0]
+    mass = np.zeros(R * R, np.uint32)
+    prefix = np.zeros(R * R + 1, np.uint64)
+    lib().orc_env_masses(env.ctypes.data_as(fptr), R, mass.ctypes.data_as(C.POINTER(C.c_uint32)),
+                         prefix.ctypes.data_as(C.POINTER(C.c_uint64)))
+    return mass, prefix
+
+
+def env_draw(mass, prefix, R, S, j, seed, i):
+    """Draw j of S for point i: (texel, direction [3], pdf)."""
+    mass = np.ascontiguousarray(mass, np.uint32)
+    prefix = np.ascontiguousarray(prefix, np.uint64)
+    w = np.zeros(3)
+    pdf = C.c_double()
+    t = lib().orc_env_draw(mass.ctypes.data_as(C.POINTER(C.c_uint32)),
+                           prefix.ctypes.data_as(C.POINTER(C.c_uint64)), R, S, j,
+                           seed & 0xFFFFFFFF, i & 0xFFFFFFFF, w.ctypes.data_as(dptr),
+                           C.byref(pdf))
+    return t, w, pdf.value
+
+
+def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sampler=0):
+    """Cast-shadow ratio of the points with normals [N,3]: probe maps [P,R,R,4] (channel 3 =
+    the object's occlusion O'), neighbours (idx, w) [N,K], octahedral environment [Re,Re,3].
+    sampler 0 = Hammersley, 1 = environment importance sampling. Returns a dict with ratio
+    [N,3], irr [N,3] (the unshadowed estimate) and texels [N,S] (importance draws)."""
+    normal, pn = _d(normal)
+    tex, pt = _d(np.asarray(texels, np.float64))
+    idx, pi = _i(idx)
+    w, pw = _d(w)
+    env, pe = _f(env)
+    N = normal.shape[0]
+    ratio = np.zeros((N, 3))
+    irr = np.zeros((N, 3))
+    tx = np.zeros((N, S), np.int32)
+    lib().orc_shadow_ratio(N, pn, pt, tex.shape[1], pi, pw, idx.shape[1], pe, env.shape[0], S,
+                           seed & 0xFFFFFFFF, int(per_point), int(sampler),
+                           ratio.ctypes.data_as(dptr), irr.ctypes.data_as(dptr),
+                           tx.ctypes.data_as(iptr))
+    return {"ratio": ratio, "irr": irr, "texels": tx}
 
 # ------------------------------------------------------------------------------------------
 # learned direction proposal (features, network, training, bin sampler, shading, targets)

@@ -1,0 +1,141 @@
+/*
+ * shadow_oracle.c - CPU FP64 oracle of the cast-shadow ratio (test infrastructure only: the
+ * tests, the smoke check and the benchmark's CPU baseline use it; the GPU library shares no
+ * code with it).
+ *
+ * ComGS Sec. 3.2 (occlusion caching) and Sec. 3.3 (rendering). For a Lambertian scene point
+ * with normal n the shadow that a placed object casts is S = L_o' / L_o (Eq. 17), where
+ *   L_o  = f_d * integral of L_i(w) (w.n)+ dw                (Eq. 15)
+ *   L_o' = f_d * integral of L_i(w) (1 - O'(w)) (w.n)+ dw    (Eq. 16)
+ * per colour channel (f_d cancels). O'(w) is the occlusion the object adds, read from the
+ * probes of the shadow region as in Eq. 9 (channel 3 of their maps). L_i is an octahedral
+ * environment map [R][R][3] (the paper's own representation of the estimated lighting),
+ * read with bilinear filtering and mirror wrap exactly like the probe maps. Both integrals
+ * are estimated with the same S samples:
+ *   - Hammersley: the hemisphere set of the shading step (Eq. 7), density 1/(2 pi);
+ *   - environment importance sampling (Eq. 18): texel t with probability m_t / C (integer
+ *     masses from the texel intensities, orc_env_masses), the direction uniform in the
+ *     texel's square of the octahedral map, and the density as Eq. 18 states it with its
+ *     normalisation read as I_t / sum(I): pdf = (m_t / C) * R^2 / (4 pi), every texel being
+ *     given the mean solid angle 4 pi / R^2 (the paper's "roughly uniform texel areas").
+ * Samples below the horizon add nothing to either sum. A channel with L_o = 0 has S = 1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#define SH_PI 3.14159265358979323846
+#define SH_MASS_BITS 14
+
+uint32_t orc_hash24(uint32_t seed, uint32_t i, uint32_t j, uint32_t k);
+uint32_t orc_rotation24(uint32_t seed, int per_point, uint32_t point_index);
+double orc_direction(int j, int S, uint32_t rho24, const double n[3], double w[3]);
+void orc_oct_decode(double u, double v, int R, double w[3]);
+void orc_oct_fetch(const double* tex, int R, int C, const double w[3], double* out);
+void orc_interp(const double* tex, int R, const int32_t* nb_idx, const double* nb_w, int K,
+                const double w[3], double Lin[3], double* O);
+
+/* intensity of a texel in IEEE single precision: (r + g) + b, 0 unless positive */
+static float texel_intensity(const float* e) {
+  float I = (e[0] + e[1]) + e[2];
+  return I > 0.0f ? I : 0.0f;
+}
+
+/* Integer masses of the environment texels, decided in IEEE single precision:
+ * m_t = 1 + floor(I_t * (2^14 / I_max)) with one float32 division and one float32 product
+ * (every texel keeps mass >= 1; with I_max = 0 every mass is 1). prefix [R*R + 1] receives
+ * the exclusive prefix sums, prefix[R*R] = C, which is returned. */
+uint64_t orc_env_masses(const float* env, int R, uint32_t* mass, uint64_t* prefix) {
+  const int T = R * R;
+  float imax = 0.0f;
+  for (int t = 0; t < T; ++t) {
+    float I = texel_intensity(env + 3 * t);
+    if (I > imax) imax = I;
+  }
+  const float f = imax > 0.0f ? (float)(1 << SH_MASS_BITS) / imax : 0.0f;
+  uint64_t c = 0;
+  for (int t = 0; t < T; ++t) {
+    float q = texel_intensity(env + 3 * t) * f;
+    uint32_t m = 1u + (uint32_t)floorf(q);
+    mass[t] = m;
+    prefix[t] = c;
+    c += m;
+  }
+  prefix[T] = c;
+  return c;
+}
+
+/* Draw j of S for point i, stratified over the mass line: x = (j C + ((r C) >> 24)) / S in
+ * integers with r = hash24(seed, i, j, 0); the texel t with prefix[t] <= x < prefix[t+1];
+ * the position (col + xu, row + xv) in texel units with xu, xv = (hash24(seed, i, j, 1|2)
+ * + 1/2) / 2^24; the direction is the octahedral decode of that position. Returns t and
+ * the density of Eq. 18, *pdf = (m_t / C) R^2 / (4 pi). */
+int orc_env_draw(const uint32_t* mass, const uint64_t* prefix, int R, int S, int j,
+                 uint32_t seed, uint32_t i, double w[3], double* pdf) {
+  const int T = R * R;
+  const uint64_t C = prefix[T];
+  const uint64_t r = orc_hash24(seed, i, (uint32_t)j, 0);
+  const uint64_t x = ((uint64_t)j * C + ((r * C) >> 24)) / (uint64_t)S;
+  int lo = 0, hi = T;                      /* prefix[lo] <= x < prefix[hi] */
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (prefix[mid] <= x) lo = mid; else hi = mid;
+  }
+  const double xu = ((double)orc_hash24(seed, i, (uint32_t)j, 1) + 0.5) / 16777216.0;
+  const double xv = ((double)orc_hash24(seed, i, (uint32_t)j, 2) + 0.5) / 16777216.0;
+  orc_oct_decode((double)(lo % R) + xu, (double)(lo / R) + xv, R, w);
+  *pdf = (double)mass[lo] / (double)C * (double)T / (4.0 * SH_PI);
+  return lo;
+}
+
+/* Shadow ratio of N points. normal [N][3]; tex [P][Rp][Rp][4] probe maps (channel 3 = O');
+ * idx/nbw [N][K] neighbours (Eq. 9-11); env [Re][Re][3] float32 (its intensities decide
+ * the masses). sampler 0 = Hammersley, 1 = environment importance sampling.
+ * ratio [N][3]; irr [N][3] (may be NULL) = (1/S) sum E cos+ / pdf (L_o / f_d); texels
+ * [N][S] (may be NULL) = the texel of each importance draw (-1 for Hammersley). */
+void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
+                      const int32_t* idx, const double* nbw, int K, const float* env, int Re,
+                      int S, uint32_t seed, int per_point, int sampler, double* ratio,
+                      double* irr, int32_t* texels) {
+  const int T = Re * Re;
+  double* env64 = (double*)malloc(sizeof(double) * 3 * (size_t)T);
+  for (long q = 0; q < 3L * T; ++q) env64[q] = (double)env[q];
+  uint32_t* mass = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)T);
+  uint64_t* prefix = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)T + 1));
+  orc_env_masses(env, Re, mass, prefix);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < N; ++i) {
+    const double n[3] = {normal[3 * i], normal[3 * i + 1], normal[3 * i + 2]};
+    const uint32_t rho = orc_rotation24(seed, per_point, (uint32_t)i);
+    double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
+    for (int j = 0; j < S; ++j) {
+      double w[3], ct, wt;
+      if (sampler == 0) {
+        ct = orc_direction(j, S, rho, n, w);
+        wt = 2.0 * SH_PI;
+        if (texels) texels[i * S + j] = -1;
+      } else {
+        double pdf;
+        int t = orc_env_draw(mass, prefix, Re, S, j, seed, (uint32_t)i, w, &pdf);
+        if (texels) texels[i * S + j] = t;
+        ct = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+        wt = 1.0 / pdf;
+      }
+      if (!(ct > 0.0)) continue;
+      double E[3], Lin[3], O;
+      orc_oct_fetch(env64, Re, 3, w, E);
+      orc_interp(tex, Rp, idx + i * K, nbw + i * K, K, w, Lin, &O);
+      for (int c = 0; c < 3; ++c) {
+        num[c] += E[c] * (1.0 - O) * ct * wt;
+        den[c] += E[c] * ct * wt;
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      ratio[3 * i + c] = den[c] != 0.0 ? num[c] / den[c] : 1.0;
+      if (irr) irr[3 * i + c] = den[c] / S;
+    }
+  }
+  free(prefix);
+  free(mass);
+  free(env64);
+}
