@@ -70,6 +70,10 @@ def main() -> int:
     ap.add_argument("--no-proposal-study", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=6000)
     ap.add_argument("--no-trace-study", action="store_true")
+    ap.add_argument("--no-shadow-study", action="store_true")
+    ap.add_argument("--shadow-only", action="store_true",
+                    help="only the cast-shadow ratio of the shadow workload with both samplers "
+                         "(1 warm-up + 3 timed calls each; for kernel traces of that path)")
     ap.add_argument("--trace-only", action="store_true",
                     help="only traced shading of the object workload at 128 directions "
                          "(1 warm-up + 3 timed calls; for kernel traces of that path)")
@@ -93,6 +97,8 @@ def main() -> int:
         return copy_calibration(torch, dev)
     if args.trace_only:
         return trace_only(torch, dev, sop, scenes)
+    if args.shadow_only:
+        return shadow_only(torch, dev, sop, scenes)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
 
     # ------------------------------------------------------------------ workload (untimed)
@@ -290,6 +296,11 @@ def main() -> int:
                             S, phase, (sc.bounds_lo, sc.bounds_hi))
         print(f"# trace study: {json.dumps(trace)}", file=sys.stderr, flush=True)
 
+    shadow = None
+    if not args.no_shadow_study:
+        shadow = shadow_study(torch, sop, scenes, time_ms, bake_plan, R)
+        print(f"# shadow study: {json.dumps(shadow)}", file=sys.stderr, flush=True)
+
     study = None
     if not args.no_proposal_study:
         study = proposal_study(torch, dev, args.proposal_steps)
@@ -317,6 +328,7 @@ def main() -> int:
         "proposal_paths": proposal_paths,
         "proposal_study": study,
         "trace_study": trace,
+        "shadow_study": shadow,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -488,6 +500,99 @@ def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb,
         "speedup_matched_with_bake": None if t_star is None else round(t_star / (t_sop + t_bake),
                                                                        3),
     }
+
+
+def shadow_setup(torch, sop, scenes, bake_plan, R, dev):
+    """The shadow workload on the GPU: 2048 ground probes baked from the object's Gaussians
+    (channel 3 = the object's occlusion O'), their plan and the ground points' neighbours."""
+    import numpy as np
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    sc = scenes.shadow_scene(textures=np.zeros((1, 2, 2, 4), np.float32))
+    probes = d(sc.probe_pos)
+    plan = sop.Plan(probes, sc.bounds_lo, sc.bounds_hi)
+    tex, _ = sop.sop_bake(bake_plan, probes, R, depth=False, order_by=plan)
+    pts = sop.Points(d(sc.pos), d(sc.normal), None, None, None)
+    nb = sop.sop_knn(plan, pts, sc.k)
+    return sc, plan, tex, d(sc.env), pts, nb
+
+
+def shadow_study(torch, sop, scenes, time_ms, bake_plan, R, subset=4096, S_ref=4096) -> dict:
+    """Cast-shadow ratio of the ground under the object with the Hammersley set and with
+    environment importance sampling (Eq. 18) at S = 64: time of each, and their errors
+    against a Hammersley reference at S_ref on a point subset, over the points the object
+    shadows (reference ratio below 0.98 in some channel); S* is the fewest importance
+    samples whose error is at most the Hammersley error at 64."""
+    import numpy as np
+    from paper_2510_07729_amd import _lib as L
+    dev = torch.device("cuda", 0)
+    sc, plan, tex, env, pts, nb = shadow_setup(torch, sop, scenes, bake_plan, R, dev)
+    N, S = sc.n, sc.n_dirs
+    out = torch.empty((N, 3), dtype=torch.float32, device=dev)
+
+    def run(n_dirs, sampler, p=pts, nbl=nb, o=out):
+        return sop.sop_shadow_ratio(plan, tex, env, p, n_dirs, nb=nbl, sampler=sampler, out=o)
+
+    t_ham = time_ms(lambda: run(S, L.SOP_SHADOW_HAMMERSLEY))
+    t_env = time_ms(lambda: run(S, L.SOP_SHADOW_ENV))
+    rows = torch.from_numpy(np.sort(np.random.default_rng(13).choice(N, subset, replace=False)))
+    rows = rows.to(dev)
+    sub = sop.Points(pts.pos[rows], pts.normal[rows], None, None, None)
+    nb_s = sop.sop_knn(plan, sub, sc.k)
+    ref = sop.sop_shadow_ratio(plan, tex, env, sub, S_ref, nb=nb_s,
+                               sampler=L.SOP_SHADOW_HAMMERSLEY, seed=101).double()
+    shadowed = (ref < 0.98).any(dim=1)
+    n_sh = int(shadowed.sum())
+
+    def err(x):
+        x = x.double()
+        return float(((x[shadowed] - ref[shadowed]) ** 2).mean().sqrt()) if n_sh else 0.0
+
+    e = {"hammersley": {}, "env": {}}
+    for s_ in (4, 8, 16, 32, 64, 128, 256):
+        for name, smp in (("hammersley", L.SOP_SHADOW_HAMMERSLEY), ("env", L.SOP_SHADOW_ENV)):
+            e[name][str(s_)] = round(err(sop.sop_shadow_ratio(plan, tex, env, sub, s_, nb=nb_s,
+                                                              sampler=smp)), 5)
+    target = e["hammersley"][str(S)]
+    s_star = min((int(k) for k, v in e["env"].items() if v <= target), default=None)
+    t_star = None if s_star is None else time_ms(lambda: run(s_star, L.SOP_SHADOW_ENV))
+    mean_ratio = float(run(S, L.SOP_SHADOW_HAMMERSLEY).mean())
+    return {
+        "workload": "shadow_scene: object over a ground plane, 2048 ground probes (32x32) "
+                    "baked from the object's 100k Gaussians, 500k ground points, 256x256 "
+                    "octahedral sky with a sun, K=8",
+        "dirs": S, "points": N, "hammersley_ms": round(t_ham, 4), "env_ms": round(t_env, 4),
+        "samples_per_s_hammersley": round(N * S / (t_ham * 1e-3)),
+        "samples_per_s_env": round(N * S / (t_env * 1e-3)),
+        "mean_ratio": round(mean_ratio, 4),
+        "ref_dirs": S_ref, "ref_points": subset, "shadowed_points": n_sh,
+        "rmse_ratio": e, "S_star_env": s_star,
+        "env_ms_at_S_star": None if t_star is None else round(t_star, 4),
+        "speedup_matched": None if t_star is None else round(t_ham / t_star, 3),
+    }
+
+
+def shadow_only(torch, dev, sop, scenes) -> int:
+    """The shadow ratio of the shadow workload with both samplers at S = 64: one warm-up and
+    three timed calls each (the probes baked from the object's Gaussians once)."""
+    import numpy as np
+    from paper_2510_07729_amd import _lib as L
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    gs = scenes.object_gaussians()
+    bplan = sop.BakePlan(d(gs.mean), d(gs.scale), d(gs.rotation), d(gs.opacity), d(gs.color))
+    sc, plan, tex, env, pts, nb = shadow_setup(torch, sop, scenes, bplan, 32, dev)
+    res = {}
+    for name, smp in (("hammersley", L.SOP_SHADOW_HAMMERSLEY), ("env", L.SOP_SHADOW_ENV)):
+        out = sop.sop_shadow_ratio(plan, tex, env, pts, sc.n_dirs, nb=nb, sampler=smp)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            sop.sop_shadow_ratio(plan, tex, env, pts, sc.n_dirs, nb=nb, sampler=smp, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(e0.elapsed_time(e1) / 3, 4)
+    print(json.dumps(res), flush=True)
+    return 0
 
 
 def trace_only(torch, dev, sop, scenes) -> int:

@@ -159,7 +159,8 @@ sop_status sop_plan_info(const sop_plan* plan, int32_t* n_probes, int32_t grid_d
  * to sum 1 (Eq. 10-11 with n_p read as the shading normal).
  * --------------------------------------------------------------------------------------*/
 
-/* Writes order[N], idx[N,K] and w[N,K] (see sop_neighbors). order may be NULL. */
+/* Writes order[N], idx[N,K] and w[N,K] (see sop_neighbors). order may be NULL. Reads the
+ * points' positions and normals only (the other fields of pts may be NULL). */
 sop_status sop_knn(const sop_plan* plan, const sop_points* pts, int32_t k, float radius,
                    int32_t* order, int32_t* idx, float* w,
                    void* ws, size_t ws_bytes, sop_stream stream);
@@ -350,6 +351,66 @@ sop_status sop_shade_traced(const sop_bake_plan* gauss, const sop_plan* order_by
 size_t sop_shade_traced_workspace_size(const sop_plan* order_by, int64_t n_points,
                                        int32_t n_dirs, int32_t env_height, int32_t env_width,
                                        int32_t with_samples);
+
+/* ----------------------------------------------------------------------------------------
+ * Cast-shadow ratio (Sec. 3.2, occlusion caching; Sec. 3.3, rendering). For a Lambertian
+ * scene point with normal n the shadow of a placed object is S = L_o' / L_o (Eq. 17) with
+ * L_o = f_d * integral L_i(w) (w.n)+ dw (Eq. 15) and
+ * L_o' = f_d * integral L_i(w) (1 - O'(w)) (w.n)+ dw (Eq. 16), per colour channel (f_d
+ * cancels). O' is the object's occlusion, read from the probes of the shadow region
+ * exactly as sop_query reads O (channel 3 of their maps; their RGB is not used). L_i is an
+ * octahedral environment map, bilinear with mirror wrap like the probe maps. Both
+ * integrals are estimated with the same S samples (samples below the horizon add nothing):
+ *   SOP_SHADOW_HAMMERSLEY: the direction set of sop_shade, density 1/(2 pi);
+ *   SOP_SHADOW_ENV: environment importance sampling (Eq. 18). Texel t has intensity
+ *     I_t = (r + g) + b (0 unless positive) and mass m_t = 1 + floor(I_t * (2^14 / I_max))
+ *     (one IEEE single-precision division and one product; every mass is 1 when
+ *     I_max = 0), C = sum m_t. Draw j of point i: x = (j C + ((h(i,j,0) C) >> 24)) / S in
+ *     integers, the texel t with M_t <= x < M_t + m_t (M_t = mass of the texels before t),
+ *     the direction = octahedral decode of (column + (h(i,j,1) + 1/2)/2^24,
+ *     row + (h(i,j,2) + 1/2)/2^24) in texel units, and the density of Eq. 18 with its
+ *     normalisation read as I_t / sum(I): pdf = (m_t / C) R^2 / (4 pi). Here
+ *     h(i,j,k) = pcg(pcg(pcg(seed) ^ i) ^ (4 j + k)) >> 8 (pcg as for the directions).
+ * ratio_c = sum_j L_c (1 - O') cos+ / pdf  /  sum_j L_c cos+ / pdf, and 1 where the
+ * denominator is 0.
+ * --------------------------------------------------------------------------------------*/
+
+/* Octahedral environment map: +z at the centre of the square, layout [row v][column u][3]
+ * like sop_probe_maps (channels R, G, B). */
+typedef struct sop_env_oct {
+  int32_t      res;              /* R_e, 2 <= R_e <= 1024                                  */
+  const float* texels;           /* device [R_e,R_e,3]                                     */
+} sop_env_oct;
+
+typedef enum sop_shadow_sampler {
+  SOP_SHADOW_HAMMERSLEY = 0,     /* hemisphere Hammersley set (Eq. 7)                      */
+  SOP_SHADOW_ENV = 1             /* environment importance sampling (Eq. 18)               */
+} sop_shadow_sampler;
+
+typedef struct sop_shadow_opts {
+  int32_t  n_dirs;               /* S, 1 <= S <= SOP_MAX_DIRS                              */
+  int32_t  k;                    /* K, 1 <= K <= SOP_MAX_K (ignored when nb != NULL)        */
+  float    radius;               /* FRNN radius in world units, +inf = unlimited           */
+  uint32_t seed;                 /* direction rotation / draw seed                         */
+  int32_t  rotate_per_point;     /* Hammersley: 0 one rotation per call, 1 one per point   */
+  int32_t  sampler;              /* sop_shadow_sampler                                     */
+  float*   out_irradiance;       /* optional device [N,3]: (1/S) sum_j L cos+ / pdf, the
+                                    unshadowed L_o / f_d                                   */
+} sop_shadow_opts;
+
+/* Writes ratio[N,3]. The probes of `plan` and `maps` are those of the shadow region; the
+ * points' positions and normals are used (the other point fields may be NULL). nb may be
+ * NULL (the search then runs with opts->k and opts->radius). Workspace:
+ * sop_shadow_workspace_size. */
+sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_maps* maps,
+                            const sop_env_oct* env, const sop_points* pts,
+                            const sop_neighbors* nb, const sop_shadow_opts* opts, float* ratio,
+                            void* ws, size_t ws_bytes, sop_stream stream);
+
+/* Workspace bytes of sop_shadow_ratio (direction table, texel masses and their prefix sums,
+ * and the neighbour search unless with_neighbors != 0). Returns 0 on an invalid argument. */
+size_t sop_shadow_workspace_size(const sop_plan* plan, int64_t n_points, int32_t k,
+                                 int32_t n_dirs, int32_t env_res, int32_t with_neighbors);
 
 /* ----------------------------------------------------------------------------------------
  * Learned direction proposal: an extension of the Monte Carlo estimate of Eq. 7 (the paper

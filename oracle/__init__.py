@@ -117,7 +117,8 @@ def _sig(lib):
     lib.orc_env_draw.argtypes = [u32p, u64p, C.c_int, C.c_int, C.c_int, u32, u32, dptr, dptr]
     lib.orc_env_draw.restype = C.c_int
     lib.orc_shadow_ratio.argtypes = [C.c_long, dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr,
-                                     C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr]
+                                     C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr,
+                                     C.POINTER(C.c_uint32)]
     lib.orc_shade_traced.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, C.c_long, dptr,
                                      dptr, dptr, dptr, C.c_long, dptr, dptr, dptr, dptr,
                                      C.c_int, C.c_int, C.c_int, u32, C.c_int, C.c_float,
@@ -479,11 +480,13 @@ def env_draw(mass, prefix, R, S, j, seed, i):
     return t, w, pdf.value
 
 
-def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sampler=0):
+def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sampler=0,
+                 ids=None):
     """Cast-shadow ratio of the points with normals [N,3]: probe maps [P,R,R,4] (channel 3 =
     the object's occlusion O'), neighbours (idx, w) [N,K], octahedral environment [Re,Re,3].
     sampler 0 = Hammersley, 1 = environment importance sampling. Returns a dict with ratio
-    [N,3], irr [N,3] (the unshadowed estimate) and texels [N,S] (importance draws)."""
+    [N,3], irr [N,3] (the unshadowed estimate) and texels [N,S] (importance draws). ids:
+    the points' indices in the full set they come from (keys of draws and rotations)."""
     normal, pn = _d(normal)
     tex, pt = _d(np.asarray(texels, np.float64))
     idx, pi = _i(idx)
@@ -496,7 +499,10 @@ def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sample
     lib().orc_shadow_ratio(N, pn, pt, tex.shape[1], pi, pw, idx.shape[1], pe, env.shape[0], S,
                            seed & 0xFFFFFFFF, int(per_point), int(sampler),
                            ratio.ctypes.data_as(dptr), irr.ctypes.data_as(dptr),
-                           tx.ctypes.data_as(iptr))
+                           tx.ctypes.data_as(iptr),
+                           None if ids is None else
+                           np.ascontiguousarray(ids, np.uint32).ctypes.data_as(
+                               C.POINTER(C.c_uint32)))
     return {"ratio": ratio, "irr": irr, "texels": tx}
 
 # ------------------------------------------------------------------------------------------

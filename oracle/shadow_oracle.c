@@ -92,11 +92,13 @@ int orc_env_draw(const uint32_t* mass, const uint64_t* prefix, int R, int S, int
  * idx/nbw [N][K] neighbours (Eq. 9-11); env [Re][Re][3] float32 (its intensities decide
  * the masses). sampler 0 = Hammersley, 1 = environment importance sampling.
  * ratio [N][3]; irr [N][3] (may be NULL) = (1/S) sum E cos+ / pdf (L_o / f_d); texels
- * [N][S] (may be NULL) = the texel of each importance draw (-1 for Hammersley). */
+ * [N][S] (may be NULL) = the texel of each importance draw (-1 for Hammersley). ids [N]
+ * (may be NULL: 0..N-1) are the point indices that key the draws and rotations, so that a
+ * subset of a larger set of points can be evaluated with the indices it has there. */
 void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
                       const int32_t* idx, const double* nbw, int K, const float* env, int Re,
                       int S, uint32_t seed, int per_point, int sampler, double* ratio,
-                      double* irr, int32_t* texels) {
+                      double* irr, int32_t* texels, const uint32_t* ids) {
   const int T = Re * Re;
   double* env64 = (double*)malloc(sizeof(double) * 3 * (size_t)T);
   for (long q = 0; q < 3L * T; ++q) env64[q] = (double)env[q];
@@ -106,7 +108,8 @@ void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
 #pragma omp parallel for schedule(dynamic, 16)
   for (long i = 0; i < N; ++i) {
     const double n[3] = {normal[3 * i], normal[3 * i + 1], normal[3 * i + 2]};
-    const uint32_t rho = orc_rotation24(seed, per_point, (uint32_t)i);
+    const uint32_t id = ids ? ids[i] : (uint32_t)i;
+    const uint32_t rho = orc_rotation24(seed, per_point, id);
     double num[3] = {0, 0, 0}, den[3] = {0, 0, 0};
     for (int j = 0; j < S; ++j) {
       double w[3], ct, wt;
@@ -116,7 +119,7 @@ void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
         if (texels) texels[i * S + j] = -1;
       } else {
         double pdf;
-        int t = orc_env_draw(mass, prefix, Re, S, j, seed, (uint32_t)i, w, &pdf);
+        int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, w, &pdf);
         if (texels) texels[i * S + j] = t;
         ct = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
         wt = 1.0 / pdf;

@@ -27,6 +27,7 @@ SOP_OP_KNN, SOP_OP_QUERY, SOP_OP_SHADE, SOP_OP_SHADE_BACKWARD = 0, 1, 2, 3
 SOP_OP_DUMP_INTEGRAND, SOP_OP_PROPOSAL_INFER, SOP_OP_PROPOSAL_TRAIN = 4, 5, 6
 SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL, SOP_SAMPLER_PROPOSAL_NET = 0, 1, 2
 SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
+SOP_SHADOW_HAMMERSLEY, SOP_SHADOW_ENV = 0, 1
 
 
 class sop_probe_set(C.Structure):
@@ -56,6 +57,15 @@ class sop_shade_opts(C.Structure):
     _fields_ = [("n_dirs", c_i32), ("k", c_i32), ("radius", c_f32), ("seed", c_u32),
                 ("rotate_per_point", c_i32), ("sampler", c_i32), ("out_irradiance", c_vp),
                 ("probs", c_vp), ("mix_eps", c_f32), ("net", c_vp)]
+
+
+class sop_env_oct(C.Structure):
+    _fields_ = [("res", c_i32), ("texels", c_vp)]
+
+
+class sop_shadow_opts(C.Structure):
+    _fields_ = [("n_dirs", c_i32), ("k", c_i32), ("radius", c_f32), ("seed", c_u32),
+                ("rotate_per_point", c_i32), ("sampler", c_i32), ("out_irradiance", c_vp)]
 
 
 class sop_gaussians(C.Structure):
@@ -100,6 +110,10 @@ SIGNATURES = {
     "sop_bake_plan_check": (c_i32, [c_vp, c_vp]),
     "sop_bake_plan_destroy": (c_i32, [c_vp]),
     "sop_bake": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp]),
+    "sop_shadow_ratio": (c_i32, [c_vp, P(sop_probe_maps), P(sop_env_oct), P(sop_points),
+                                 P(sop_neighbors), P(sop_shadow_opts), c_vp, c_vp, C.c_size_t,
+                                 c_vp]),
+    "sop_shadow_workspace_size": (C.c_size_t, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32]),
     "sop_shade_traced": (c_i32, [c_vp, c_vp, P(sop_envmap), P(sop_points), P(sop_shade_opts),
                                  c_f32, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
     "sop_shade_traced_workspace_size": (C.c_size_t, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32]),

@@ -343,9 +343,15 @@ extern "C" sop_status sop_knn(const sop_plan* plan, const sop_points* pts, int32
                               float radius, int32_t* order, int32_t* idx, float* w, void* ws,
                               size_t ws_bytes, sop_stream stream) {
   if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
-  sop_status st = validate_points(pts);
+  // the search reads positions and normals only
+  if (!pts) return fail(SOP_ERR_INVALID_ARGUMENT, "pts is NULL");
+  if (pts->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "pts->count < 0");
+  if (pts->count > INT32_MAX) return fail(SOP_ERR_UNSUPPORTED, "more than 2^31-1 points");
+  if (pts->count > 0 && (!pts->pos || !pts->normal || !aligned(pts->pos, 4) ||
+                         !aligned(pts->normal, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "pts->pos/normal NULL or misaligned");
+  sop_status st = validate_k_radius(k, radius);
   if (st != SOP_OK) return st;
-  if ((st = validate_k_radius(k, radius)) != SOP_OK) return st;
   if (pts->count > 0 && (!idx || !w || !aligned(idx, 4) || !aligned(w, 4) ||
                          (order && !aligned(order, 4))))
     return fail(SOP_ERR_INVALID_ARGUMENT, "idx/w NULL or misaligned");
@@ -1159,6 +1165,122 @@ extern "C" sop_status sop_shade_traced(const sop_bake_plan* gauss, const sop_pla
   a.order = order;
   a.traced = buf;
   SOP_HIP(sopk::launch_shade_traced(a, s), "sop_shade_traced");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// cast-shadow ratio
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Workspace layout: [direction table] [texel masses] [mass prefix sums] [tile sums]
+// [intensity maximum] [order, idx, w] [search scratch]
+size_t shadow_ws(const sop_plan* plan, int64_t N, int32_t k, int32_t S, int32_t Re,
+                 bool with_nb) {
+  Bump b{nullptr, 0, 0};
+  (void)b.take<double4>((size_t)S);
+  (void)b.take<uint32_t>((size_t)Re * Re);
+  (void)b.take<uint64_t>((size_t)Re * Re + 1);
+  (void)b.take<uint64_t>(((size_t)Re * Re + 1023) / 1024);
+  (void)b.take<float>(1);
+  if (!with_nb) {
+    carve_nb(b, N, k);
+    carve_knn(b, plan, N);
+  }
+  return b.used;
+}
+
+}  // namespace
+
+extern "C" size_t sop_shadow_workspace_size(const sop_plan* plan, int64_t n_points, int32_t k,
+                                            int32_t n_dirs, int32_t env_res,
+                                            int32_t with_neighbors) {
+  if (!plan || n_points < 0 || n_dirs < 1 || n_dirs > SOP_MAX_DIRS || env_res < 2 ||
+      env_res > 1024)
+    return 0;
+  if (!with_neighbors && (k < 1 || k > SOP_MAX_K)) return 0;
+  const size_t need = shadow_ws(plan, n_points, k, n_dirs, env_res, with_neighbors != 0);
+  return need > 0 ? need : 256;
+}
+
+extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_maps* maps,
+                                       const sop_env_oct* env, const sop_points* pts,
+                                       const sop_neighbors* nb, const sop_shadow_opts* opts,
+                                       float* ratio, void* ws, size_t ws_bytes,
+                                       sop_stream stream) {
+  if (!plan) return fail(SOP_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (!opts) return fail(SOP_ERR_INVALID_ARGUMENT, "opts is NULL");
+  if (!pts) return fail(SOP_ERR_INVALID_ARGUMENT, "pts is NULL");
+  if (pts->count < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "pts->count < 0");
+  if (pts->count > INT32_MAX) return fail(SOP_ERR_UNSUPPORTED, "more than 2^31-1 points");
+  if (pts->count > 0 && (!pts->pos || !pts->normal || !aligned(pts->pos, 4) ||
+                         !aligned(pts->normal, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "pts->pos/normal NULL or misaligned");
+  sop_status st = validate_maps(plan, maps);
+  if (st != SOP_OK) return st;
+  if (!env) return fail(SOP_ERR_INVALID_ARGUMENT, "env is NULL");
+  if (env->res < 2 || env->res > 1024)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "env->res out of [2, 1024]");
+  if (!env->texels || !aligned(env->texels, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "env->texels is NULL or misaligned");
+  if (nb) {
+    if ((st = validate_nb(nb)) != SOP_OK) return st;
+  } else if ((st = validate_k_radius(opts->k, opts->radius)) != SOP_OK) {
+    return st;
+  }
+  if (opts->n_dirs < 1 || opts->n_dirs > SOP_MAX_DIRS)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
+  if (opts->sampler != SOP_SHADOW_HAMMERSLEY && opts->sampler != SOP_SHADOW_ENV)
+    return fail(SOP_ERR_UNSUPPORTED, "unknown shadow sampler");
+  if (pts->count > 0 && (!ratio || !aligned(ratio, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "ratio is NULL or misaligned");
+  if (opts->out_irradiance && !aligned(opts->out_irradiance, 4))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "out_irradiance misaligned");
+  const int32_t k = nb ? nb->k : opts->k;
+  const size_t need = shadow_ws(plan, pts->count, k, opts->n_dirs, env->res, nb != nullptr);
+  if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  if (pts->count == 0) return SOP_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  sopk::ShadeArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = pts->count;
+  a.pos = pts->pos;
+  a.nrm = pts->normal;
+  a.P = plan->P;
+  a.tex = maps->texels;
+  a.R = maps->res;
+  a.env = env->texels;
+  a.env_res = env->res;
+  a.S = opts->n_dirs;
+  a.seed = opts->seed;
+  a.per_point = opts->rotate_per_point ? 1 : 0;
+  a.shadow_sampler = opts->sampler;
+  a.rgb = ratio;
+  a.irr = opts->out_irradiance;
+  Bump b{(char*)ws, 0, ws_bytes};
+  double4* tab = b.take<double4>((size_t)opts->n_dirs);
+  const int32_t T = env->res * env->res;
+  uint32_t* mass = b.take<uint32_t>((size_t)T);
+  uint64_t* prefix = b.take<uint64_t>((size_t)T + 1);
+  uint64_t* tile_tmp = b.take<uint64_t>(((size_t)T + 1023) / 1024);
+  float* imax = b.take<float>(1);
+  if (opts->sampler == SOP_SHADOW_HAMMERSLEY) {
+    a.dir_tab = tab;
+    // the table's environment references are not used here (width/height 0)
+    SOP_HIP(sopk::launch_dir_table(opts->n_dirs, opts->seed, a.per_point, 0, 0, tab, nullptr,
+                                   nullptr, s),
+            "sop_shadow_ratio");
+  } else {
+    a.env_mass = mass;
+    a.env_prefix = prefix;
+    SOP_HIP(sopk::launch_env_cdf(env->texels, T, mass, prefix, tile_tmp, imax, s),
+            "sop_shadow_ratio");
+  }
+  int32_t kk;
+  if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
+                       &a.nb_w, &kk)) != SOP_OK)
+    return st;
+  SOP_HIP(sopk::launch_shadow_ratio(a, kk, maps->format, s), "sop_shadow_ratio");
   return SOP_OK;
 }
 

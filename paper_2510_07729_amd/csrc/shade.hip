@@ -302,15 +302,203 @@ __global__ __launch_bounds__(256) void k_shade_traced(ShadeArgs a) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Cast-shadow ratio (Sec. 3.2 occlusion caching, Eq. 15-17) on an octahedral environment,
+// with the Hammersley set or environment importance sampling (Eq. 18).
+// ------------------------------------------------------------------------------------------
+
+// intensity of an environment texel in IEEE single precision: (r + g) + b, 0 unless > 0
+__device__ __forceinline__ float env_intensity(const float* e) {
+  const float I = (e[0] + e[1]) + e[2];
+  return I > 0.0f ? I : 0.0f;
+}
+
+// Texel masses m_t = 1 + floor(I_t * (2^14 / I_max)) (one IEEE division, one product; all 1
+// when I_max = 0) and their exclusive prefix sums, prefix[T] = the total, in four coalesced
+// passes: the maximum (one workgroup), masses and a scan inside tiles of 1024 texels, a
+// scan of the tile totals (one workgroup; T <= 2^20), and the tile offsets added.
+constexpr int kCdfTile = 1024;
+
+__global__ __launch_bounds__(1024) void k_env_max(const float* env, int32_t T, float* imax) {
+  __shared__ float smax[1024];
+  const int tid = threadIdx.x;
+  float m = 0.0f;
+  for (int t = tid; t < T; t += 1024) m = fmaxf(m, env_intensity(env + 3 * (size_t)t));
+  smax[tid] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) smax[tid] = fmaxf(smax[tid], smax[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) *imax = smax[0];
+}
+
+// inclusive scan of one value per thread over a 1024-thread workgroup (Hillis-Steele)
+__device__ __forceinline__ uint64_t block_scan_1024(uint64_t v, uint64_t* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint64_t add = tid >= o ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  return sh[tid];
+}
+
+__global__ __launch_bounds__(1024) void k_env_tiles(const float* env, int32_t T,
+                                                    const float* imax, uint32_t* mass,
+                                                    uint64_t* prefix, uint64_t* tile_sum) {
+  __shared__ uint64_t sh[1024];
+  const float im = *imax;
+  const float f = im > 0.0f ? __fdiv_rn(16384.0f, im) : 0.0f;
+  const int t = blockIdx.x * kCdfTile + threadIdx.x;
+  uint32_t m = 0;
+  if (t < T) {
+    m = 1u + (uint32_t)floorf(__fmul_rn(env_intensity(env + 3 * (size_t)t), f));
+    mass[t] = m;
+  }
+  const uint64_t inc = block_scan_1024(m, sh);
+  if (t < T) prefix[t] = inc - m;
+  if (threadIdx.x == 1023) tile_sum[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(1024) void k_env_tile_scan(int32_t ntiles, uint64_t* tile_sum,
+                                                        uint64_t* prefix, int32_t T) {
+  __shared__ uint64_t sh[1024];
+  const int b = threadIdx.x;
+  const uint64_t v = b < ntiles ? tile_sum[b] : 0;
+  const uint64_t inc = block_scan_1024(v, sh);
+  if (b < ntiles) tile_sum[b] = inc - v;           // offset of tile b
+  if (b == 1023) prefix[T] = inc;
+}
+
+__global__ __launch_bounds__(1024) void k_env_add(int32_t T, const uint64_t* tile_off,
+                                                  uint64_t* prefix) {
+  const int t = blockIdx.x * kCdfTile + threadIdx.x;
+  if (t < T && blockIdx.x > 0) prefix[t] += tile_off[blockIdx.x];
+}
+
+// L lanes per point (64/L points per wavefront, in processing order; L = 64 for S > 32),
+// lane l of a point takes directions l, l+L, ...; the estimates of Eq. 15 and 16 share
+// every sample, and the ratio is formed after the lane-group sums.
+template <int KT, typename TexT, int L>
+__global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
+  const int lane = threadIdx.x & 63, li = lane % L;
+  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+  const int64_t slot = group_slot<L>(lane);
+  bool valid = slot < a.n;
+  int64_t p = valid ? slot : 0;
+  if (valid && a.order) {
+    int32_t o = a.order[slot];
+    if (L == 64) o = __builtin_amdgcn_readfirstlane(o);
+    if ((uint64_t)o >= (uint64_t)a.n) valid = false;
+    else p = o;
+  }
+  if (L == 64 && !valid) return;
+  double n64[3] = {0.0, 0.0, 1.0};
+  if (valid) {
+    n64[0] = a.nrm[3 * p];
+    n64[1] = a.nrm[3 * p + 1];
+    n64[2] = a.nrm[3 * p + 2];
+  }
+  Neighbors<KT> nb;
+  if (valid) nb.load(a, p, k);
+  const int kn = KT > 0 ? KT : nb.count(k);
+  const bool importance = a.shadow_sampler == 1;
+  Frame64 F;
+  double cr = 1.0, sr = 0.0;
+  if (!importance) {
+    F = make_frame64(n64[0], n64[1], n64[2]);
+    if (a.per_point) sincospi((double)rotation24(a.seed, true, (uint32_t)p) * 0x1p-23, &sr, &cr);
+  }
+  const int32_t Re = a.env_res;
+  const int32_t T = Re * Re;
+  const uint64_t C = a.env_prefix ? a.env_prefix[T] : 0;
+  const uint32_t sh = pcg_hash(a.seed);
+  const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
+  const size_t RR = (size_t)a.R * a.R;
+  float num[3] = {0.0f, 0.0f, 0.0f}, den[3] = {0.0f, 0.0f, 0.0f};
+  for (int j = li; valid && j < a.S; j += L) {
+    double w64[3];
+    float ct, wt;
+    if (!importance) {
+      const double4 e = a.dir_tab[j];
+      world_dir64(F, e.x * cr - e.y * sr, e.x * sr + e.y * cr, e.z, w64);
+      ct = (float)e.z;
+      wt = 6.283185307179586f;
+    } else {
+      // the j-th of S slices of the mass line, then the texel whose stretch holds x
+      const uint64_t r = hash24(sh, (uint32_t)p, (uint32_t)j, 0);
+      const uint64_t x = ((uint64_t)j * C + ((r * C) >> 24)) / (uint64_t)a.S;
+      int lo = 0, hi = T;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.env_prefix[mid] <= x) lo = mid; else hi = mid;
+      }
+      const double xu = ((double)hash24(sh, (uint32_t)p, (uint32_t)j, 1) + 0.5) * 0x1p-24;
+      const double xv = ((double)hash24(sh, (uint32_t)p, (uint32_t)j, 2) + 0.5) * 0x1p-24;
+      oct_decode64((double)(lo % Re) + xu, (double)(lo / Re) + xv, Re, w64);
+      const double cd = w64[0] * n64[0] + w64[1] * n64[1] + w64[2] * n64[2];
+      if (!(cd > 0.0)) continue;
+      ct = (float)cd;
+      // 1 / pdf with pdf = (m_t / C) T / (4 pi)
+      wt = (float)(12.566370614359172 * (double)C / ((double)a.env_mass[lo] * (double)T));
+    }
+    const Taps te = oct_taps64(w64, Re);
+    float E[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float* ep = a.env + 3 * (size_t)te.off[t];
+      E[0] += te.w[t] * ep[0];
+      E[1] += te.w[t] * ep[1];
+      E[2] += te.w[t] * ep[2];
+    }
+    const Taps tt = oct_taps64(w64, a.R);
+    float O = 0.0f;
+#pragma unroll
+    for (int s2 = 0; s2 < kn; ++s2) {
+      const int32_t id = nb.id(s2, a, p, k);
+      if (id < 0) continue;
+      const float wk = nb.wt(s2, a, p, k);
+      const TexT* Tp = tex + (size_t)id * RR;
+      // only the occlusion channel is read (a quarter of each texel)
+      float q[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) q[t] = load_occlusion(Tp, (size_t)tt.off[t]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) O += wk * tt.w[t] * q[t];
+    }
+    const float cw = ct * wt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      num[c] += E[c] * (1.0f - O) * cw;
+      den[c] += E[c] * cw;
+    }
+  }
+  float rn[3], rd[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    rn[c] = group_sum<L>(num[c]);
+    rd[c] = group_sum<L>(den[c]);
+  }
+  if (valid && li == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.rgb[3 * p + c] = rd[c] != 0.0f ? rn[c] / rd[c] : 1.0f;
+    if (a.irr) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.irr[3 * p + c] = rd[c] / (float)a.S;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Learned direction proposal: importance-sampled estimate of Eq. 7. Directions are drawn
 // from 16x16 bins over the hemispherical octahedral square of the local frame,
 // (u,v) = (x+y, x-y)/(|x|+|y|+z), with integer bin masses (decided in IEEE single
 // precision, so every bin choice is exact), and each sample is weighted by 1/pdf,
 // pdf = (c_b / C) * 128 * l^3 with l = |(px,py,z)|.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t hash24(uint32_t seed_h, uint32_t i, uint32_t j, uint32_t k) {
-  return pcg_hash(pcg_hash(seed_h ^ i) ^ (4u * j + k)) >> 8;
-}
 
 // unit local direction of square point (u,v); returns l = |(px, py, z)|
 __device__ __forceinline__ double bin_dir(double u, double v, double wl[3]) {
@@ -1135,6 +1323,49 @@ hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t* prefix,
+                          uint64_t* tile_tmp, float* imax, hipStream_t s) {
+  if (T < 1 || T > (1 << 20) || !env || !mass || !prefix || !tile_tmp || !imax)
+    return hipErrorInvalidValue;
+  const int ntiles = (T + kCdfTile - 1) / kCdfTile;
+  hipLaunchKernelGGL(k_env_max, dim3(1), dim3(1024), 0, s, env, T, imax);
+  hipLaunchKernelGGL(k_env_tiles, dim3(ntiles), dim3(1024), 0, s, env, T, imax, mass, prefix,
+                     tile_tmp);
+  hipLaunchKernelGGL(k_env_tile_scan, dim3(1), dim3(1024), 0, s, ntiles, tile_tmp, prefix, T);
+  hipLaunchKernelGGL(k_env_add, dim3(ntiles), dim3(1024), 0, s, T, tile_tmp, prefix);
+  return hipGetLastError();
+}
+
+template <int KT, int L>
+static void launch_shadow_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const dim3 grid = grid_for(a.n, L);
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shadow_ratio<KT, uint2, L>), grid, dim3(256), 0, s, a, k);
+  else
+    hipLaunchKernelGGL((k_shadow_ratio<KT, float4, L>), grid, dim3(256), 0, s, a, k);
+}
+
+template <int KT>
+static void launch_shadow_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  switch (lanes_for(a.S)) {
+    case 16: launch_shadow_l<KT, 16>(a, k, format, s); break;
+    case 32: launch_shadow_l<KT, 32>(a, k, format, s); break;
+    default: launch_shadow_l<KT, 64>(a, k, format, s); break;
+  }
+}
+
+hipError_t launch_shadow_ratio(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (a.shadow_sampler == 1 && (!a.env_mass || !a.env_prefix)) return hipErrorInvalidValue;
+  if (a.shadow_sampler == 0 && !a.dir_tab) return hipErrorInvalidValue;
+  switch (k) {
+    case 4: launch_shadow_kt<4>(a, k, format, s); break;
+    case 8: launch_shadow_kt<8>(a, k, format, s); break;
+    default: launch_shadow_kt<0>(a, k, format, s); break;
+  }
+  return hipGetLastError();
+}
+
 size_t batched_lds_bytes(int32_t R) {
   return (size_t)kBatch * R * R * 4 * sizeof(float) + 5 * kMaxEntries * 4 +
          (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kEnvRuns * sizeof(EnvRun);
@@ -1176,12 +1407,12 @@ __global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, doub
                                                    double2* row_ref) {
   const int32_t j = blockIdx.x * 256 + threadIdx.x;
   if (j < S) tab[j] = dir_entry(j, S, rho);
-  if (j < W + 2) {
+  if (col_ref && j < W + 2) {
     double sn, cs;
     sincospi(2.0 * ((double)(j - 1) + 0.5) / (double)W - 1.0, &sn, &cs);
     col_ref[j] = make_double2(cs, sn);
   }
-  if (j < H + 2) {
+  if (row_ref && j < H + 2) {
     double sn, cs;
     sincospi(((double)(j - 1) + 0.5) / (double)H, &sn, &cs);
     row_ref[j] = make_double2(cs, sn);
@@ -1191,7 +1422,8 @@ __global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, doub
 hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,
                             double4* tab, double2* col_ref, double2* row_ref, hipStream_t s) {
   const uint32_t rho = per_point ? 0u : rotation24(seed, false, 0u);
-  const int32_t n = max(S, max(W + 2, H + 2));
+  // the environment tables are optional (NULL: not formed)
+  const int32_t n = max(S, max(col_ref ? W + 2 : 0, row_ref ? H + 2 : 0));
   hipLaunchKernelGGL(k_dir_table, dim3((n + 255) / 256), dim3(256), 0, s, S, rho, tab, H, W,
                      col_ref, row_ref);
   return hipGetLastError();

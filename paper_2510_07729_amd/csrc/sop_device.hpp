@@ -38,6 +38,11 @@ __host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
   return (word >> 22u) ^ word;
 }
 
+// 24 random bits for (point i, draw j, stream k) from the hashed seed seed_h = pcg_hash(seed)
+__device__ __forceinline__ uint32_t hash24(uint32_t seed_h, uint32_t i, uint32_t j, uint32_t k) {
+  return pcg_hash(pcg_hash(seed_h ^ i) ^ (4u * j + k)) >> 8;
+}
+
 __host__ __device__ __forceinline__ uint32_t rotation24(uint32_t seed, bool per_point,
                                                        uint32_t i) {
   return (per_point ? pcg_hash(seed ^ pcg_hash(i)) : pcg_hash(seed)) >> 8;
@@ -139,6 +144,22 @@ __device__ __forceinline__ Taps oct_taps(v3 w, int R, float halfR) {
 // Same taps from an FP64 direction: the bilinear weights of the probe textures then carry
 // no FP32 coordinate rounding (it would be amplified in the texture gradient of entries
 // that receive only small weights).
+// direction of texture coordinate (u, v) in texel units of an R x R octahedral map, FP64
+__device__ __forceinline__ void oct_decode64(double u, double v, int R, double w[3]) {
+  double px = 2.0 * u / (double)R - 1.0, py = 2.0 * v / (double)R - 1.0;
+  const double z = 1.0 - fabs(px) - fabs(py);
+  if (z < 0.0) {
+    const double fx = (1.0 - fabs(py)) * (px < 0.0 ? -1.0 : 1.0);
+    const double fy = (1.0 - fabs(px)) * (py < 0.0 ? -1.0 : 1.0);
+    px = fx;
+    py = fy;
+  }
+  const double il = 1.0 / sqrt(px * px + py * py + z * z);
+  w[0] = px * il;
+  w[1] = py * il;
+  w[2] = z * il;
+}
+
 __device__ __forceinline__ Taps oct_taps64(const double w[3], int R) {
   const double s = fabs(w[0]) + fabs(w[1]) + fabs(w[2]);
   const double inv = 1.0 / s;
@@ -174,6 +195,13 @@ __device__ __forceinline__ Taps oct_taps64(const double w[3], int R) {
 }
 
 __device__ __forceinline__ float4 load_texel(const float4* tex, size_t i) { return tex[i]; }
+// channel 3 (occlusion) of texel i alone: 4 bytes (f32 maps) or 2 bytes (f16 maps)
+__device__ __forceinline__ float load_occlusion(const float4* tex, size_t i) {
+  return reinterpret_cast<const float*>(tex)[4 * i + 3];
+}
+__device__ __forceinline__ float load_occlusion(const uint2* tex, size_t i) {
+  return __half2float(reinterpret_cast<const __half*>(tex)[4 * i + 3]);
+}
 __device__ __forceinline__ float4 load_texel(const uint2* tex, size_t i) {
   const uint2 u = tex[i];
   const __half2 a = *reinterpret_cast<const __half2*>(&u.x);

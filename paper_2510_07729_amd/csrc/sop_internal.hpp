@@ -85,6 +85,11 @@ struct ShadeArgs {
   float* rgb;
   float* irr;
   const float4* traced;     // [n,S] (L_in rgb, O) per sample (traced shading)
+  // cast-shadow ratio: octahedral environment in env, its texel masses and their prefix
+  const uint32_t* env_mass; // [Re*Re]
+  const uint64_t* env_prefix;  // [Re*Re + 1], env_prefix[Re*Re] = total mass
+  int32_t env_res;
+  int32_t shadow_sampler;   // 0 Hammersley, 1 environment importance sampling
   // learned proposal sampler / training targets
   const float* probs;       // [n,256] bin distributions
   float mix_eps;
@@ -141,6 +146,12 @@ hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipSt
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+// cast-shadow ratio: texel masses and prefix of an octahedral environment [T <= 2^20
+// texels]; tile_tmp holds ceil(T/1024) values, imax one
+hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t* prefix,
+                          uint64_t* tile_tmp, float* imax, hipStream_t s);
+// ratio [n,3] in a.rgb (optional unshadowed estimate in a.irr)
+hipError_t launch_shadow_ratio(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // traced shading: the estimate of launch_shade_fwd with a.traced for L_in and O
 hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s);
 hipError_t launch_shade_prop_net(const ShadeArgs& a, int32_t k, int32_t format,

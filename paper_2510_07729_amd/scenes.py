@@ -22,6 +22,11 @@ surface, object views of 800x800 and scene views up to 1920x1080):
 * ``mlp_init`` / ``bin_probs``  proposal network weights and bin distributions.
 * ``gbuffer_frames``  8 pinhole cameras (1920x1080, f=3200 px) on a sphere of radius 3
                       looking at the unit sphere; 16,384 probes with 32x32 f16 maps.
+* ``shadow_scene``    the object standing over a ground plane: 2048 shadow-region probes
+                      placed by farthest point sampling on the plane around it (a square
+                      twice the object's extent) and raised by 1% of its diagonal, 500k
+                      ground points with normal +z, a 256x256 octahedral sky whose sun holds
+                      about 70% of its energy and whose lower half is dimmed, S=64, K=8.
 """
 from __future__ import annotations
 
@@ -33,7 +38,7 @@ import numpy as np
 
 F32 = np.float32
 
-CFG_TINY, CFG_OBJECT, CFG_DIFF, CFG_FRAMES, CFG_PROPOSAL = 1, 2, 3, 4, 5
+CFG_TINY, CFG_OBJECT, CFG_DIFF, CFG_FRAMES, CFG_PROPOSAL, CFG_SHADOW = 1, 2, 3, 4, 5, 6
 
 
 def rng(cfg: int, stream: int, seed: int = 0) -> np.random.Generator:
@@ -352,3 +357,82 @@ def random_gaussians(g: np.random.Generator, n: int, center=(0.0, 0.0, 0.0), spr
     return GaussianScene(mean.astype(F32), scale.astype(F32), q.astype(F32),
                          g.uniform(0.3, 1.0, size=n).astype(F32),
                          g.uniform(0.0, 1.0, size=(n, 3)).astype(F32))
+
+
+# ------------------------------------------------------------------------------------------
+# cast shadows: the object over a ground plane, probes of the shadow region, octahedral sky
+# ------------------------------------------------------------------------------------------
+SHADOW_PLANE_Z = -0.55      # just below the object (its lowest point is at z = -0.5)
+SHADOW_HALF = 2.2           # half side of the shadow region: twice the object's extent
+SHADOW_BOUNDS = (np.array([-2.4, -2.4, -0.8], F32), np.array([2.4, 2.4, 0.8], F32))
+
+
+@dataclasses.dataclass
+class ShadowScene:
+    probe_pos: np.ndarray            # [P,3] f32, the shadow-region probes
+    bounds_lo: np.ndarray
+    bounds_hi: np.ndarray
+    texels: np.ndarray               # [P,R,R,4] f32 (channel 3: the object's occlusion O')
+    env: np.ndarray                  # [Re,Re,3] f32 octahedral sky
+    pos: np.ndarray                  # [N,3] f32 ground points
+    normal: np.ndarray               # [N,3] f32
+    n_dirs: int
+    k: int
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def subset(self, rows: np.ndarray) -> "ShadowScene":
+        return dataclasses.replace(self, pos=self.pos[rows].copy(),
+                                   normal=self.normal[rows].copy())
+
+
+def octahedral_sky(g: np.random.Generator, res: int, sigma: float = 1.0,
+                   sun=(0.3, 0.35), gain: float = 1000.0, width: float = 0.02,
+                   ground: float = 0.2) -> np.ndarray:
+    """Octahedral sky [res,res,3] shaped like an outdoor HDR map: lognormal(0, sigma)
+    texels, those outside the square's central diamond (the lower hemisphere of the map)
+    dimmed by ``ground``, plus a warm sun blob of peak ``gain`` centred at the fraction
+    ``sun`` of the square (texel space, x then y; inside the diamond). With the defaults the
+    sun holds about 70% of the energy at res 256."""
+    base = g.lognormal(0.0, sigma, size=(res, res, 3))
+    c = (np.arange(res) + 0.5) / res
+    lower = (np.abs(c[None, :] - 0.5) + np.abs(c[:, None] - 0.5)) > 0.5
+    base[lower] *= ground
+    d2 = (c[None, :] - sun[0]) ** 2 + (c[:, None] - sun[1]) ** 2
+    blob = gain * np.exp(-d2 / (2.0 * width * width))
+    return (base + blob[..., None] * np.array([1.0, 0.9, 0.7])).astype(F32)
+
+
+@functools.lru_cache(maxsize=4)
+def shadow_probes(n_probes: int = 2048, n_candidates: int = 65536, seed: int = 0):
+    """Probes of the shadow region: FPS over uniform samples of the ground square, raised
+    along the plane's normal by 1% of the object's diagonal (the placement of the object's
+    own probes)."""
+    g = rng(CFG_SHADOW, 1, seed)
+    xy = g.uniform(-SHADOW_HALF, SHADOW_HALF, size=(n_candidates, 2))
+    pts = np.column_stack([xy, np.full(n_candidates, SHADOW_PLANE_Z)])
+    sel = farthest_point_sampling(pts, n_probes)
+    out = pts[sel] + np.array([0.0, 0.0, 0.01 * OBJECT_DIAGONAL])
+    return out.astype(F32)
+
+
+def shadow_scene(n_points: int = 500_000, n_probes: int = 2048, res: int = 32,
+                 env_res: int = 256, n_dirs: int = 64, k: int = 8,
+                 textures: Optional[np.ndarray] = None, seed: int = 0) -> ShadowScene:
+    """Shadow workload. ``textures`` are the shadow probes' maps (the bake of the object's
+    Gaussians in the full pipeline); by default synthetic maps with the tiny scene's
+    distributions (O' = 1 - exp(-tau), tau ~ U(0, 2)) so that the scene stands on its own."""
+    ppos = shadow_probes(n_probes, seed=seed)
+    if textures is None:
+        textures = probe_textures(rng(CFG_SHADOW, 2, seed), n_probes, res)
+    g = rng(CFG_SHADOW, 3, seed)
+    xy = g.uniform(-SHADOW_HALF, SHADOW_HALF, size=(n_points, 2))
+    pos = np.column_stack([xy, np.full(n_points, SHADOW_PLANE_Z)]).astype(F32)
+    nrm = np.tile(np.array([0.0, 0.0, 1.0], F32), (n_points, 1))
+    env = octahedral_sky(rng(CFG_SHADOW, 4, seed), env_res)
+    lo, hi = SHADOW_BOUNDS
+    return ShadowScene(ppos, lo.copy(), hi.copy(), textures, env, pos, nrm, n_dirs, k,
+                       seed=seed)

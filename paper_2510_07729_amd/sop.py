@@ -491,3 +491,37 @@ def sop_shade_traced(plan: BakePlan, env: torch.Tensor, pts: Points, n_dirs: int
                                  ws.data_ptr(), ws.numel(), _stream()), "sop_shade_traced")
     res = (rgb,) + ((irr,) if irradiance else ()) + ((smp,) if smp is not None else ())
     return res[0] if len(res) == 1 else res
+
+
+def sop_shadow_ratio(plan: Plan, texels: torch.Tensor, env_oct: torch.Tensor, pts: Points,
+                     n_dirs: int, k: int = 4, nb: Optional[Neighbors] = None, seed: int = 0,
+                     radius: float = math.inf, rotate_per_point: bool = False,
+                     sampler: int = L.SOP_SHADOW_HAMMERSLEY, irradiance: bool = False,
+                     ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+    """Cast-shadow ratio [N,3] of the points under the octahedral environment env_oct
+    [Re,Re,3], the object's occlusion read from channel 3 of the shadow-region probe maps
+    texels [P,R,R,4]; with irradiance=True also the unshadowed estimate [N,3]."""
+    dev = pts.pos.device
+    n = pts.n
+    ratio = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
+    irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
+    kk = nb.k if nb is not None else k
+    lib = plan._lib
+    if ws is None:
+        ws = workspace(lib.sop_shadow_workspace_size(plan.handle, n, kk, int(n_dirs),
+                                                     int(env_oct.shape[0]), int(nb is not None)),
+                       dev)
+    o = L.sop_shadow_opts()
+    o.n_dirs, o.k, o.radius, o.seed = int(n_dirs), int(kk), float(radius), int(seed) & 0xFFFFFFFF
+    o.rotate_per_point, o.sampler = int(rotate_per_point), int(sampler)
+    o.out_irradiance = _ptr(irr, torch.float32, "irradiance")
+    e = L.sop_env_oct()
+    e.res = int(env_oct.shape[0])
+    e.texels = _ptr(env_oct, torch.float32, "env_oct")
+    m, cp = _maps(texels), pts.c()
+    nbc = nb.c() if nb is not None else None
+    L.check(lib.sop_shadow_ratio(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+                                 C.byref(nbc) if nbc is not None else None, C.byref(o),
+                                 _ptr(ratio, torch.float32, "ratio"), ws.data_ptr(), ws.numel(),
+                                 _stream()), "sop_shadow_ratio")
+    return (ratio, irr) if irradiance else ratio

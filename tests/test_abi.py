@@ -170,3 +170,13 @@ def test_traced_shading_validation():
     assert lib.sop_shade_traced_workspace_size(None, 10, 0, 4, 8, 0) == 0
     assert lib.sop_shade_traced_workspace_size(None, 10, 5000, 4, 8, 0) == 0
     assert lib.sop_shade_traced_workspace_size(None, -1, 16, 4, 8, 0) == 0
+
+
+def test_shadow_ratio_validation():
+    lib = L.load()
+    o = L.sop_shadow_opts()
+    o.n_dirs, o.k, o.radius = 16, 4, math.inf
+    assert lib.sop_shadow_ratio(None, None, None, None, None, C.byref(o), None, None, 0,
+                                None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert "plan" in lib.sop_last_error().decode()
+    assert lib.sop_shadow_workspace_size(None, 10, 4, 16, 64, 0) == 0
