@@ -15,7 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sop_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c"), os.path.join(_HERE, "shadow_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "proposal_oracle.c"), os.path.join(_HERE, "shadow_oracle.c"),
+         os.path.join(_HERE, "placement_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -119,6 +120,10 @@ def _sig(lib):
     lib.orc_shadow_ratio.argtypes = [C.c_long, dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr,
                                      C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr,
                                      C.POINTER(C.c_uint32)]
+    lib.orc_fps.argtypes = [fptr, C.c_long, C.c_int, C.c_long, iptr]
+    lib.orc_place.argtypes = [fptr, fptr, iptr, C.c_int, C.c_float, fptr]
+    lib.orc_sops_loss.argtypes = [fptr, fptr, C.c_long, dptr, dptr]
+    lib.orc_lam_loss.argtypes = [fptr, fptr, C.c_long, dptr, dptr, dptr]
     lib.orc_shade_traced.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, C.c_long, dptr,
                                      dptr, dptr, dptr, C.c_long, dptr, dptr, dptr, dptr,
                                      C.c_int, C.c_int, C.c_int, u32, C.c_int, C.c_float,
@@ -504,6 +509,50 @@ def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sample
                            np.ascontiguousarray(ids, np.uint32).ctypes.data_as(
                                C.POINTER(C.c_uint32)))
     return {"ratio": ratio, "irr": irr, "texels": tx}
+
+
+# ------------------------------------------------------------------------------------------
+# probe placement (farthest point sampling + normal offset) and the L_lam / L_sops losses
+# ------------------------------------------------------------------------------------------
+def fps(pts, P, start=0):
+    """Indices [P] of the farthest point sampling of pts [M,3] (float32 decisions)."""
+    pts, pp = _f(pts)
+    out = np.zeros(P, np.int32)
+    lib().orc_fps(pp, pts.shape[0], P, int(start), out.ctypes.data_as(iptr))
+    return out
+
+
+def place(pts, normals, chosen, offset):
+    """Probe positions [P,3] = fmaf(offset, n, x) of the chosen points (float32)."""
+    pts, pp = _f(pts)
+    normals, pn = _f(normals)
+    chosen, pc = _i(chosen)
+    out = np.zeros((chosen.shape[0], 3), np.float32)
+    lib().orc_place(pp, pn, pc, chosen.shape[0], float(offset), out.ctypes.data_as(fptr))
+    return out
+
+
+def sops_loss(tex, target):
+    """(loss [2] = (L1(L_in, L_tr), L1(O, O_tr)), grad [...,4]) of probe textures."""
+    tex, pt = _f(tex)
+    target, pg = _f(target)
+    T = tex.size // 4
+    loss = np.zeros(2)
+    grad = np.zeros(tex.shape)
+    lib().orc_sops_loss(pt, pg, T, loss.ctypes.data_as(dptr), grad.ctypes.data_as(dptr))
+    return loss, grad
+
+
+def lam_loss(rough, metal):
+    """(loss [2] = (L1(R, 1), L1(M, 0)), g_rough [N], g_metal [N])."""
+    rough, pr = _f(rough)
+    metal, pm = _f(metal)
+    N = rough.shape[0]
+    loss = np.zeros(2)
+    gr, gm = np.zeros(N), np.zeros(N)
+    lib().orc_lam_loss(pr, pm, N, loss.ctypes.data_as(dptr), gr.ctypes.data_as(dptr),
+                       gm.ctypes.data_as(dptr))
+    return loss, gr, gm
 
 # ------------------------------------------------------------------------------------------
 # learned direction proposal (features, network, training, bin sampler, shading, targets)
