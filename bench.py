@@ -71,6 +71,10 @@ def main() -> int:
     ap.add_argument("--proposal-steps", type=int, default=6000)
     ap.add_argument("--no-trace-study", action="store_true")
     ap.add_argument("--no-shadow-study", action="store_true")
+    ap.add_argument("--no-place-study", action="store_true")
+    ap.add_argument("--place-only", action="store_true",
+                    help="only probe placement and the losses of the object workload (for "
+                         "kernel traces of that path)")
     ap.add_argument("--shadow-only", action="store_true",
                     help="only the cast-shadow ratio of the shadow workload with both samplers "
                          "(1 warm-up + 3 timed calls each; for kernel traces of that path)")
@@ -99,6 +103,12 @@ def main() -> int:
         return trace_only(torch, dev, sop, scenes)
     if args.shadow_only:
         return shadow_only(torch, dev, sop, scenes)
+    if args.place_only:
+        import numpy as np
+        tex = torch.from_numpy(scenes.probe_textures(scenes.rng(scenes.CFG_OBJECT, 1, 0), 4096,
+                                                     32)).to(dev)
+        print(json.dumps(place_study(torch, sop, scenes, time_ms_plain, tex)), flush=True)
+        return 0
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
 
     # ------------------------------------------------------------------ workload (untimed)
@@ -301,6 +311,11 @@ def main() -> int:
         shadow = shadow_study(torch, sop, scenes, time_ms, bake_plan, R)
         print(f"# shadow study: {json.dumps(shadow)}", file=sys.stderr, flush=True)
 
+    place = None
+    if not args.no_place_study:
+        place = place_study(torch, sop, scenes, time_ms, tex)
+        print(f"# place study: {json.dumps(place)}", file=sys.stderr, flush=True)
+
     study = None
     if not args.no_proposal_study:
         study = proposal_study(torch, dev, args.proposal_steps)
@@ -329,6 +344,7 @@ def main() -> int:
         "proposal_study": study,
         "trace_study": trace,
         "shadow_study": shadow,
+        "place_study": place,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -499,6 +515,64 @@ def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb,
         "speedup_matched": None if t_star is None else round(t_star / t_sop, 2),
         "speedup_matched_with_bake": None if t_star is None else round(t_star / (t_sop + t_bake),
                                                                        3),
+    }
+
+
+def time_ms_plain(fn, reps=10):
+    """Average milliseconds of fn() on the current stream (one untimed call first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record()
+    for _ in range(reps):
+        fn()
+    a1.record()
+    torch.cuda.synchronize()
+    return a0.elapsed_time(a1) / reps
+
+
+def place_study(torch, sop, scenes, time_ms, tex) -> dict:
+    """Probe placement of the object workload on the GPU (4096 probes by farthest point
+    sampling over 65,536 surface samples, raised by 1% of the diagonal) and the losses of
+    the reconstruction step: L_sops of the step's baked maps against a perturbed copy (the
+    traced targets) with its gradient, L_lam of 200k points; their HBM rates against the
+    8 TB/s peak (bytes: both maps read and the gradient written; roughness and metallic read,
+    their gradients written)."""
+    import numpy as np
+    dev = tex.device
+    pts, nrm = scenes.object_surface(scenes.rng(scenes.CFG_OBJECT, 10, 0), 65536)
+    pts_t = torch.from_numpy(pts.astype(np.float32)).to(dev)
+    nrm_t = torch.from_numpy(nrm.astype(np.float32)).to(dev)
+    off = 0.01 * scenes.OBJECT_DIAGONAL
+    t_fps = time_ms(lambda: sop.sop_place_probes(pts_t, nrm_t, 4096, 0, off), reps=3)
+    target = tex * 0.97 + 0.01
+    T = tex.numel() // 4
+    ws = sop.workspace(sop.L.load().sop_loss_workspace_size(T), dev)
+    loss_o = torch.empty(2, dtype=torch.float32, device=dev)
+    grad_o = torch.empty_like(tex)
+    # the C entry point with its arguments built once: the call costs a few microseconds of
+    # host time, not the tens a wrapper that allocates its outputs would add to a ~35 us kernel
+    lib = sop.L.load()
+    args = (tex.data_ptr(), target.data_ptr(), T, loss_o.data_ptr(), grad_o.data_ptr(),
+            ws.data_ptr(), ws.numel(), sop._stream())
+    sop.L.check(lib.sop_sops_loss(*args), "sop_sops_loss")
+    t_sops = time_ms(lambda: lib.sop_sops_loss(*args), reps=50)
+    g = np.random.default_rng(3)
+    r = torch.from_numpy(g.uniform(0.05, 1, 200_000).astype(np.float32)).to(dev)
+    m = torch.from_numpy(g.uniform(0, 1, 200_000).astype(np.float32)).to(dev)
+    t_lam = time_ms(lambda: sop.sop_lam_loss(r, m), reps=20)
+    b_sops = 3 * 16 * T
+    b_lam = 4 * 4 * 200_000
+    return {
+        "workload": "object: 4096 probes from 65,536 surface samples; L_sops on the 4096 "
+                    "baked 32x32 maps; L_lam on 200k points",
+        "fps_ms": round(t_fps, 3), "fps_picks": 4096, "fps_points": 65536,
+        "sops_loss_ms": round(t_sops, 4), "sops_bytes": b_sops,
+        "sops_GBps": round(b_sops / (t_sops * 1e-3) / 1e9, 1),
+        "sops_hbm_frac": round(b_sops / (t_sops * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "lam_loss_ms": round(t_lam, 4), "lam_bytes": b_lam,
+        "lam_GBps": round(b_lam / (t_lam * 1e-3) / 1e9, 1),
     }
 
 

@@ -413,6 +413,50 @@ size_t sop_shadow_workspace_size(const sop_plan* plan, int64_t n_points, int32_t
                                  int32_t n_dirs, int32_t env_res, int32_t with_neighbors);
 
 /* ----------------------------------------------------------------------------------------
+ * Probe placement (Sec. 3.1.2, automatic placement of SOPs): farthest point sampling over
+ * a surface point cloud with normals, then every pick raised along its normal. The first
+ * pick is `start`; pick k is the point whose squared distance to its nearest earlier pick
+ * is largest, the squared distance taken in IEEE single precision as
+ * ((dx*dx + dy*dy) + dz*dz), dx = x_j - x_q, without fused multiply-adds; ties go to the
+ * lowest index. Probe k = fmaf(offset, n_c, x_c) per component of its pick c.
+ * --------------------------------------------------------------------------------------*/
+
+/* pts, normals: device [M,3], 1 <= M <= 2^31 - 1; 1 <= n_probes <= M; 0 <= start < M;
+ * offset finite. Writes probe_pos [n_probes,3] and, when not NULL, chosen [n_probes] (the
+ * picks' indices). Enqueues one short kernel per pick. Workspace:
+ * sop_place_workspace_size(M). */
+sop_status sop_place_probes(const float* pts, const float* normals, int64_t n_points,
+                            int32_t n_probes, int64_t start, float offset, int32_t* chosen,
+                            float* probe_pos, void* ws, size_t ws_bytes, sop_stream stream);
+
+size_t sop_place_workspace_size(int64_t n_points, int32_t n_probes);
+
+/* ----------------------------------------------------------------------------------------
+ * Losses of the reconstruction step (Sec. 3.1.2): L_sops = L1(L_in, L_tr) + L1(O, O_tr)
+ * supervises the probe textures with the traced ones, and L_lam = L1(R, 1) + L1(M, 0)
+ * regularises the materials. L1 is the mean absolute difference over the elements (RGB
+ * channels together, O apart); gradients take sign(x - y) / n with sign(0) = 0. Each call
+ * writes its two terms to loss[0], loss[1] (device, float) from per-workgroup partial sums
+ * in double precision added in a fixed order (the same inputs give the same loss).
+ * --------------------------------------------------------------------------------------*/
+
+/* tex, target: device [T,4] (R,G,B,O) f32, 16-byte aligned (for instance [P,R_t,R_t,4]
+ * maps: T = P R_t^2). loss[0] = L1(L_in, L_tr), loss[1] = L1(O, O_tr); grad (may be NULL,
+ * [T,4]) is OVERWRITTEN with d(loss[0] + loss[1]) / d tex. Workspace:
+ * sop_loss_workspace_size(T). */
+sop_status sop_sops_loss(const float* tex, const float* target, int64_t n_texels, float* loss,
+                         float* grad, void* ws, size_t ws_bytes, sop_stream stream);
+
+/* rough, metal: device [N]. loss[0] = L1(R, 1), loss[1] = L1(M, 0); g_rough, g_metal (may be
+ * NULL, [N]) are OVERWRITTEN with the gradients of loss[0] + loss[1]. Workspace:
+ * sop_loss_workspace_size(N). */
+sop_status sop_lam_loss(const float* rough, const float* metal, int64_t n_points, float* loss,
+                        float* g_rough, float* g_metal, void* ws, size_t ws_bytes,
+                        sop_stream stream);
+
+size_t sop_loss_workspace_size(int64_t n_elements);
+
+/* ----------------------------------------------------------------------------------------
  * Learned direction proposal: an extension of the Monte Carlo estimate of Eq. 7 (the paper
  * uses a fixed Hammersley set; here the directions can instead be importance sampled from a
  * per-point distribution that a small network predicts, trained on integrand samples that

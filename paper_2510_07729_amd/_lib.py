@@ -114,6 +114,12 @@ SIGNATURES = {
                                  P(sop_neighbors), P(sop_shadow_opts), c_vp, c_vp, C.c_size_t,
                                  c_vp]),
     "sop_shadow_workspace_size": (C.c_size_t, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32]),
+    "sop_place_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i64, c_f32, c_vp, c_vp, c_vp,
+                                 C.c_size_t, c_vp]),
+    "sop_place_workspace_size": (C.c_size_t, [c_i64, c_i32]),
+    "sop_sops_loss": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_lam_loss": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_loss_workspace_size": (C.c_size_t, [c_i64]),
     "sop_shade_traced": (c_i32, [c_vp, c_vp, P(sop_envmap), P(sop_points), P(sop_shade_opts),
                                  c_f32, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
     "sop_shade_traced_workspace_size": (C.c_size_t, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32]),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(HERE, "libsop.so")
-SOURCES = ["grid.hip", "shade.hip", "bake.hip", "proposal.hip", "api.cpp"]
+SOURCES = ["grid.hip", "shade.hip", "bake.hip", "proposal.hip", "place.hip", "api.cpp"]
 ARCH = "gfx950"
 
 

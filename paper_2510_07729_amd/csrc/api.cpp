@@ -1285,6 +1285,93 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
 }
 
 // ------------------------------------------------------------------------------------------
+// probe placement and the losses of the reconstruction step
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Workspace layout: [distances to the nearest pick] [three 64-bit slots] [picks, used when
+// the caller passes no array for them]
+size_t place_ws(int64_t M, int32_t P) {
+  Bump b{nullptr, 0, 0};
+  (void)b.take<float>((size_t)M);
+  (void)b.take<uint64_t>(3);
+  (void)b.take<int32_t>((size_t)P);
+  return b.used;
+}
+
+}  // namespace
+
+extern "C" size_t sop_place_workspace_size(int64_t n_points, int32_t n_probes) {
+  if (n_points < 1 || n_points > INT32_MAX || n_probes < 1 || n_probes > n_points) return 0;
+  return place_ws(n_points, n_probes);
+}
+
+extern "C" sop_status sop_place_probes(const float* pts, const float* normals,
+                                       int64_t n_points, int32_t n_probes, int64_t start,
+                                       float offset, int32_t* chosen, float* probe_pos,
+                                       void* ws, size_t ws_bytes, sop_stream stream) {
+  if (n_points < 1 || n_points > INT32_MAX)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_points out of [1, 2^31-1]");
+  if (n_probes < 1 || n_probes > n_points)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "n_probes out of [1, n_points]");
+  if (start < 0 || start >= n_points)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "start out of [0, n_points)");
+  if (!std::isfinite(offset)) return fail(SOP_ERR_INVALID_ARGUMENT, "offset is not finite");
+  if (!pts || !normals || !probe_pos || !aligned(pts, 4) || !aligned(normals, 4) ||
+      !aligned(probe_pos, 4) || (chosen && !aligned(chosen, 4)))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "pts/normals/probe_pos NULL or misaligned");
+  sop_status st = validate_ws(ws, ws_bytes, place_ws(n_points, n_probes));
+  if (st != SOP_OK) return st;
+  Bump b{(char*)ws, 0, ws_bytes};
+  float* dist = b.take<float>((size_t)n_points);
+  uint64_t* slots = b.take<uint64_t>(3);
+  int32_t* picks = b.take<int32_t>((size_t)n_probes);
+  SOP_HIP(sopk::launch_place_probes(pts, normals, n_points, n_probes, start, offset, dist, slots,
+                                    chosen ? chosen : picks, probe_pos, (hipStream_t)stream),
+          "sop_place_probes");
+  return SOP_OK;
+}
+
+extern "C" size_t sop_loss_workspace_size(int64_t n_elements) {
+  if (n_elements < 0) return 0;
+  Bump b{nullptr, 0, 0};
+  (void)b.take<double>(sopk::loss_partials(n_elements));
+  return b.used;
+}
+
+extern "C" sop_status sop_sops_loss(const float* tex, const float* target, int64_t n_texels,
+                                    float* loss, float* grad, void* ws, size_t ws_bytes,
+                                    sop_stream stream) {
+  if (n_texels < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "n_texels < 0");
+  if (!loss || !aligned(loss, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "loss NULL or misaligned");
+  if (n_texels > 0 && (!tex || !target || !aligned(tex, 16) || !aligned(target, 16) ||
+                       (grad && !aligned(grad, 16))))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "tex/target/grad NULL or not 16-byte aligned");
+  sop_status st = validate_ws(ws, ws_bytes, sop_loss_workspace_size(n_texels));
+  if (st != SOP_OK) return st;
+  SOP_HIP(sopk::launch_sops_loss(tex, target, n_texels, loss, grad, (double*)ws,
+                                 (hipStream_t)stream),
+          "sop_sops_loss");
+  return SOP_OK;
+}
+
+extern "C" sop_status sop_lam_loss(const float* rough, const float* metal, int64_t n_points,
+                                   float* loss, float* g_rough, float* g_metal, void* ws,
+                                   size_t ws_bytes, sop_stream stream) {
+  if (n_points < 0) return fail(SOP_ERR_INVALID_ARGUMENT, "n_points < 0");
+  if (!loss || !aligned(loss, 4)) return fail(SOP_ERR_INVALID_ARGUMENT, "loss NULL or misaligned");
+  if (n_points > 0 && (!rough || !metal || !aligned(rough, 4) || !aligned(metal, 4) ||
+                       (g_rough && !aligned(g_rough, 4)) || (g_metal && !aligned(g_metal, 4))))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "rough/metal/gradients NULL or misaligned");
+  sop_status st = validate_ws(ws, ws_bytes, sop_loss_workspace_size(n_points));
+  if (st != SOP_OK) return st;
+  SOP_HIP(sopk::launch_lam_loss(rough, metal, n_points, loss, g_rough, g_metal, (double*)ws,
+                                (hipStream_t)stream),
+          "sop_lam_loss");
+  return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
 extern "C" const char* sop_status_string(sop_status s) {
   switch (s) {
     case SOP_OK: return "ok";

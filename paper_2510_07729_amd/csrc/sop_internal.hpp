@@ -200,4 +200,17 @@ hipError_t launch_trace_samples(const BakeGrid& G, const TraceArgs& t, hipStream
 hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int32_t R,
                        float* texels, float* depth, const int4* order, hipStream_t s);
 
+// place.hip --------------------------------------------------------------------------------
+// farthest point sampling of P of M points from `start` (dist [M] and slots [3] scratch),
+// chosen [P], probes out [P,3] = fmaf(offset, n, x)
+hipError_t launch_place_probes(const float* pts, const float* nrm, int64_t M, int32_t P,
+                               int64_t start, float offset, float* dist, uint64_t* slots,
+                               int32_t* chosen, float* out, hipStream_t s);
+// doubles of partial sums the loss launches need for n elements
+size_t loss_partials(int64_t n);
+hipError_t launch_sops_loss(const float* tex, const float* tgt, int64_t T, float* loss,
+                            float* grad, double* part, hipStream_t s);
+hipError_t launch_lam_loss(const float* rough, const float* metal, int64_t N, float* loss,
+                           float* g_rough, float* g_metal, double* part, hipStream_t s);
+
 }  // namespace sopk

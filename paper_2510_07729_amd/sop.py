@@ -525,3 +525,57 @@ def sop_shadow_ratio(plan: Plan, texels: torch.Tensor, env_oct: torch.Tensor, pt
                                  _ptr(ratio, torch.float32, "ratio"), ws.data_ptr(), ws.numel(),
                                  _stream()), "sop_shadow_ratio")
     return (ratio, irr) if irradiance else ratio
+
+
+def sop_place_probes(pts: torch.Tensor, normals: torch.Tensor, n_probes: int, start: int = 0,
+                     offset: float = 0.0, ws: Optional[torch.Tensor] = None):
+    """Farthest point sampling of n_probes of the surface points pts [M,3] (normals [M,3])
+    from `start`, each pick raised by `offset` along its normal: (probe_pos [P,3],
+    chosen [P] int32)."""
+    lib = L.load()
+    M, dev = int(pts.shape[0]), pts.device
+    out = torch.empty((int(n_probes), 3), dtype=torch.float32, device=dev)
+    chosen = torch.empty(int(n_probes), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = workspace(lib.sop_place_workspace_size(M, int(n_probes)), dev)
+    L.check(lib.sop_place_probes(_ptr(pts, torch.float32, "pts"),
+                                 _ptr(normals, torch.float32, "normals"), M, int(n_probes),
+                                 int(start), float(offset), _ptr(chosen, torch.int32, "chosen"),
+                                 _ptr(out, torch.float32, "probe_pos"), ws.data_ptr(),
+                                 ws.numel(), _stream()), "sop_place_probes")
+    return out, chosen
+
+
+def sop_sops_loss(tex: torch.Tensor, target: torch.Tensor, grad: bool = True,
+                  ws: Optional[torch.Tensor] = None, loss_out: Optional[torch.Tensor] = None,
+                  grad_out: Optional[torch.Tensor] = None):
+    """L_sops of probe textures [...,4] against the traced ones: (loss [2] =
+    (L1(L_in, L_tr), L1(O, O_tr)), gradient of their sum w.r.t. tex or None)."""
+    lib = L.load()
+    T, dev = int(tex.numel() // 4), tex.device
+    loss = loss_out if loss_out is not None else torch.empty(2, dtype=torch.float32, device=dev)
+    g = (grad_out if grad_out is not None else torch.empty_like(tex)) if grad else None
+    if ws is None:
+        ws = workspace(lib.sop_loss_workspace_size(T), dev)
+    L.check(lib.sop_sops_loss(_ptr(tex, torch.float32, "tex"),
+                              _ptr(target, torch.float32, "target"), T,
+                              _ptr(loss, torch.float32, "loss"), _ptr(g), ws.data_ptr(),
+                              ws.numel(), _stream()), "sop_sops_loss")
+    return loss, g
+
+
+def sop_lam_loss(rough: torch.Tensor, metal: torch.Tensor, grad: bool = True,
+                 ws: Optional[torch.Tensor] = None):
+    """L_lam of the materials: (loss [2] = (L1(R, 1), L1(M, 0)), g_rough, g_metal)."""
+    lib = L.load()
+    N, dev = int(rough.numel()), rough.device
+    loss = torch.empty(2, dtype=torch.float32, device=dev)
+    gr = torch.empty_like(rough) if grad else None
+    gm = torch.empty_like(metal) if grad else None
+    if ws is None:
+        ws = workspace(lib.sop_loss_workspace_size(N), dev)
+    L.check(lib.sop_lam_loss(_ptr(rough, torch.float32, "rough"),
+                             _ptr(metal, torch.float32, "metal"), N,
+                             _ptr(loss, torch.float32, "loss"), _ptr(gr), _ptr(gm),
+                             ws.data_ptr(), ws.numel(), _stream()), "sop_lam_loss")
+    return loss, gr, gm

@@ -180,3 +180,25 @@ def test_shadow_ratio_validation():
                                 None) == L.SOP_ERR_INVALID_ARGUMENT
     assert "plan" in lib.sop_last_error().decode()
     assert lib.sop_shadow_workspace_size(None, 10, 4, 16, 64, 0) == 0
+
+
+def test_placement_and_loss_validation():
+    lib = L.load()
+    big = 1 << 20
+    assert lib.sop_place_probes(0x1000, 0x1000, 0, 1, 0, 0.0, None, 0x2000, 0x10000, big,
+                                None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_place_probes(0x1000, 0x1000, 10, 11, 0, 0.0, None, 0x2000, 0x10000, big,
+                                None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_place_probes(0x1000, 0x1000, 10, 5, 10, 0.0, None, 0x2000, 0x10000, big,
+                                None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_place_probes(0x1000, 0x1000, 10, 5, 0, math.inf, None, 0x2000, 0x10000, big,
+                                None) == L.SOP_ERR_INVALID_ARGUMENT
+    need = lib.sop_place_workspace_size(10, 5)
+    assert need > 0 and lib.sop_place_workspace_size(10, 11) == 0
+    assert lib.sop_place_probes(0x1000, 0x1000, 10, 5, 0, 0.0, None, 0x2000, 0x10000,
+                                need - 256, None) == L.SOP_ERR_WORKSPACE_TOO_SMALL
+    assert lib.sop_sops_loss(0x1008, 0x1000, 4, 0x2000, None, 0x10000, big,
+                             None) == L.SOP_ERR_INVALID_ARGUMENT          # not 16-byte aligned
+    assert lib.sop_lam_loss(None, 0x1000, 4, 0x2000, None, None, 0x10000, big,
+                            None) == L.SOP_ERR_INVALID_ARGUMENT
+    assert lib.sop_loss_workspace_size(-1) == 0

@@ -1,0 +1,109 @@
+"""GPU parity of probe placement (farthest point sampling + normal offset) and of the L_sops
+and L_lam losses against the oracle. Picks are integer decisions taken on both sides with
+the same single-precision squared distances, so they must agree exactly; the probe
+positions (one fmaf per component) too."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_07729_amd import scenes
+from tests.gpu_util import TOL, dev, log, parity_err, report
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def gpu_place(pts, nrm, P, start=0, offset=0.0):
+    from paper_2510_07729_amd import sop
+    pos, chosen = sop.sop_place_probes(dev(pts), dev(nrm), P, start, offset)
+    return pos.cpu().numpy(), chosen.cpu().numpy()
+
+
+def check_place(pts, nrm, P, start, offset, label):
+    pos, chosen = gpu_place(pts, nrm, P, start, offset)
+    ref = oracle.fps(pts, P, start)
+    mism = int(np.sum(chosen != ref))
+    log(f"{label}: {P} picks of {pts.shape[0]}, {mism} differ")
+    assert mism == 0
+    assert np.array_equal(pos, oracle.place(pts, nrm, ref, offset))
+
+
+@pytest.mark.parametrize("M,P,start", [(1000, 100, 7), (4099, 333, 4098), (300, 300, 0)])
+def test_fps_random_clouds(torch_gpu, M, P, start):
+    g = np.random.default_rng(M)
+    pts = g.uniform(-1, 1, (M, 3)).astype(F32)
+    nrm = scenes.unit_vectors(g, M).astype(F32)
+    check_place(pts, nrm, P, start, 0.03, f"cloud M={M}")
+
+
+def test_fps_exact_ties_on_a_grid(torch_gpu):
+    # integer grid: many picks tie exactly, the lowest index must win on both sides
+    g = np.stack(np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij"), -1)
+    pts = g.reshape(-1, 3).astype(F32)
+    nrm = np.tile(np.array([0, 0, 1], F32), (pts.shape[0], 1))
+    check_place(pts, nrm, 64, 0, 0.5, "grid 8^3")
+
+
+def test_fps_degenerate_counts(torch_gpu):
+    pts = np.array([[0.5, -0.25, 1.0]], F32)
+    nrm = np.array([[0, 1, 0]], F32)
+    check_place(pts, nrm, 1, 0, 0.125, "one point")
+    g = np.random.default_rng(1)
+    pts = g.uniform(-1, 1, (50, 3)).astype(F32)
+    nrm = scenes.unit_vectors(g, 50).astype(F32)
+    check_place(pts, nrm, 1, 13, -0.01, "one pick")
+    pts[10:20] = pts[3]                         # duplicates: zero distances everywhere
+    check_place(pts, nrm, 50, 3, 0.0, "duplicates, P = M")
+
+
+def test_fps_object_surface_full_size(torch_gpu):
+    """The object workload's placement: 4096 probes from 65,536 surface samples, raised by
+    1% of the diagonal."""
+    pts, nrm = scenes.object_surface(scenes.rng(scenes.CFG_OBJECT, 10, 0), 65536)
+    check_place(pts.astype(F32), nrm.astype(F32), 4096, 0, 0.01 * scenes.OBJECT_DIAGONAL,
+                "object surface")
+
+
+def test_sops_loss_object_maps(torch_gpu):
+    from paper_2510_07729_amd import sop
+    log("L_sops: 4096 maps of 32x32 (4.19M texels), a tenth of them equal to the target")
+    g = np.random.default_rng(2)
+    tex = scenes.probe_textures(g, 4096, 32)
+    tgt = scenes.probe_textures(g, 4096, 32)
+    eq = g.random(tex.shape[:3]) < 0.1
+    tgt[eq] = tex[eq]
+    loss, grad = sop.sop_sops_loss(dev(tex), dev(tgt))
+    rl, rg = oracle.sops_loss(tex, tgt)
+    e = report("L_sops loss", parity_err(loss.cpu().numpy(), rl))
+    e = max(e, report("L_sops grad", parity_err(grad.cpu().numpy(), rg)))
+    assert e <= TOL
+    assert np.all(grad.cpu().numpy()[eq] == 0.0)
+    loss2, _ = sop.sop_sops_loss(dev(tex), dev(tgt), grad=False)
+    assert np.array_equal(loss.cpu().numpy(), loss2.cpu().numpy())     # fixed order
+
+
+def test_lam_loss(torch_gpu):
+    from paper_2510_07729_amd import sop
+    log("L_lam: 200,001 points, some at r = 1 and m = 0 exactly")
+    g = np.random.default_rng(4)
+    r = g.uniform(0.05, 1.0, 200_001).astype(F32)
+    m = g.uniform(0.0, 1.0, 200_001).astype(F32)
+    r[::7] = 1.0
+    m[::5] = 0.0
+    loss, gr, gm = sop.sop_lam_loss(dev(r), dev(m))
+    rl, rgr, rgm = oracle.lam_loss(r, m)
+    e = report("L_lam loss", parity_err(loss.cpu().numpy(), rl))
+    e = max(e, report("L_lam grads", parity_err(np.concatenate([gr.cpu().numpy(),
+                                                                gm.cpu().numpy()]),
+                                                np.concatenate([rgr, rgm]))))
+    assert e <= TOL
+    z = sop.sop_lam_loss(dev(r[:0]), dev(m[:0]))[0].cpu().numpy()
+    assert np.all(z == 0.0)
