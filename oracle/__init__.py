@@ -74,10 +74,11 @@ def _sig(lib):
     lib.orc_query.argtypes = [dptr, C.c_int, iptr, dptr, C.c_int, C.c_long, dptr, C.c_int,
                               dptr, dptr]
     lib.orc_shade.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr, dptr,
-                              dptr, C.c_int, dptr, C.c_int, C.c_int, iptr, dptr, C.c_int,
-                              C.c_int, u32, C.c_int, dptr, dptr]
+                              dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int, iptr, dptr,
+                              C.c_int, C.c_int, u32, C.c_int, dptr, dptr]
     lib.orc_shade_backward.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
-                                       dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, iptr,
+                                       dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int,
+                                       iptr,
                                        dptr, C.c_int, C.c_int, u32, C.c_int, dptr, dptr, dptr,
                                        dptr, dptr, dptr, dptr, dptr, dptr, dptr, dptr]
     u64 = C.c_uint64
@@ -104,10 +105,12 @@ def _sig(lib):
     lib.orc_prop_pdf.argtypes = [fptr, fl, dptr]
     lib.orc_prop_samples.argtypes = [fptr, fl, C.c_int, u32, u32, iptr, dptr, dptr]
     lib.orc_prop_shade.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr, dptr,
-                                   dptr, C.c_int, dptr, C.c_int, C.c_int, iptr, dptr, C.c_int,
+                                   dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int, iptr, dptr,
+                                   C.c_int,
                                    fptr, fl, C.c_int, u32, dptr, dptr]
     lib.orc_dump_integrand.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
-                                       dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, iptr, dptr,
+                                       dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int,
+                                       iptr, dptr,
                                        C.c_int, C.c_int, u32, dptr]
     lib.orc_bake_rays.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   C.c_long, iptr, iptr, C.c_double, C.c_double, C.c_double,
@@ -126,7 +129,8 @@ def _sig(lib):
     lib.orc_lam_loss.argtypes = [fptr, fptr, C.c_long, dptr, dptr, dptr]
     lib.orc_shade_traced.argtypes = [C.c_int, dptr, dptr, dptr, dptr, dptr, C.c_long, dptr,
                                      dptr, dptr, dptr, C.c_long, dptr, dptr, dptr, dptr,
-                                     C.c_int, C.c_int, C.c_int, u32, C.c_int, C.c_float,
+                                     C.c_int, C.c_int, C.c_int, C.c_int, u32, C.c_int,
+                                     C.c_float,
                                      C.c_double, C.c_double, C.c_double, C.c_double, dptr,
                                      dptr, dptr, iptr]
 
@@ -339,8 +343,9 @@ def _scene_args(sc, albedo=None, rough=None, metal=None, texels=None, env=None):
     _, pm = d(sc.metal if metal is None else metal)
     tex, ptex = d(sc.texels.astype(np.float64) if texels is None else texels)
     envd, penv = d(sc.env if env is None else env)
+    # octahedral environments are read like probe maps (H = W = their side)
     return keep, (pos.shape[0], ppos, pn, pv, pc, ppf, pa, pr, pm, ptex, tex.shape[1], penv,
-                  envd.shape[0], envd.shape[1])
+                  envd.shape[0], envd.shape[1], int(getattr(sc, "env_oct", False)))
 
 
 def shade(sc, idx, w, albedo=None, rough=None, metal=None, texels=None, env=None,
@@ -447,7 +452,8 @@ def shade_traced(gs, sc, offset, n_dirs=None, seed=None, per_point=False, t_min=
     lib().orc_shade_traced(gs.count, d(gs.mean), d(gs.scale), d(gs.rotation), d(gs.opacity),
                            d(gs.color), N, d(sc.pos), d(sc.normal), pv, pc, ppf,
                            d(sc.albedo), d(sc.rough), d(sc.metal), envd.ctypes.data_as(dptr),
-                           envd.shape[0], envd.shape[1], S, sd & 0xFFFFFFFF, int(per_point),
+                           envd.shape[0], envd.shape[1], int(getattr(sc, "env_oct", False)), S,
+                           sd & 0xFFFFFFFF, int(per_point),
                            float(offset), t_min, alpha_min, alpha_max, T_min,
                            rgb.ctypes.data_as(dptr), irr.ctypes.data_as(dptr),
                            samples.ctypes.data_as(dptr), flags.ctypes.data_as(iptr))

@@ -51,7 +51,8 @@
 uint32_t orc_pcg_hash(uint32_t v);
 uint32_t orc_bitreverse32(uint32_t x);
 void orc_frame(const double n[3], double t[3], double b[3]);
-void orc_env_fetch(const double* env, int H, int W, const double w[3], double out[3]);
+void orc_env_fetch_any(const double* env, int H, int W, int oct, const double w[3],
+                       double out[3]);
 void orc_interp(const double* tex, int R, const int32_t* nb_idx, const double* nb_w, int K,
                 const double w[3], double Lin[3], double* O);
 void orc_brdf(const double n[3], const double v[3], const double l[3], const double a[3],
@@ -349,10 +350,11 @@ static void view_of(const double* view, const double* cam, long ppf, const doubl
 /* f L_i cos at a world direction w with local cosine ct (Eq. 6 integrand with Eq. 8) */
 static void integrand(const double n[3], const double v[3], const double a[3], double r,
                       double m, const double* tex, int R, const double* env, int H, int W,
-                      const int32_t* nb_idx, const double* nb_w, int K, const double w[3],
+                      int env_oct, const int32_t* nb_idx, const double* nb_w, int K,
+                      const double w[3],
                       double ct, double out[3], double Li_out[3]) {
   double Lenv[3], Lin[3], O, f[3];
-  orc_env_fetch(env, H, W, w, Lenv);
+  orc_env_fetch_any(env, H, W, env_oct, w, Lenv);
   orc_interp(tex, R, nb_idx, nb_w, K, w, Lin, &O);
   orc_brdf(n, v, w, a, r, m, f);
   for (int c = 0; c < 3; ++c) {
@@ -370,8 +372,9 @@ static void integrand(const double n[3], const double v[3], const double a[3], d
 void orc_prop_shade(long N, const double* pos, const double* normal, const double* view,
                     const double* cam, long ppf, const double* albedo, const double* rough,
                     const double* metal, const double* tex, int R, const double* env, int H,
-                    int W, const int32_t* idx, const double* wts, int K, const float* probs,
-                    float eps, int S, uint32_t seed, double* rgb, double* irr) {
+                    int W, int env_oct, const int32_t* idx, const double* wts, int K,
+                    const float* probs, float eps, int S, uint32_t seed, double* rgb,
+                    double* irr) {
 #pragma omp parallel for schedule(dynamic, 16)
   for (long i = 0; i < N; ++i) {
     double n[3], v[3], a[3], t[3], bt[3];
@@ -385,7 +388,7 @@ void orc_prop_shade(long N, const double* pos, const double* normal, const doubl
       double wl[3], pdf, w[3], y[3], Li[3];
       prop_draw(cm, total, S, seed, (uint32_t)i, j, wl, &pdf);
       for (int c = 0; c < 3; ++c) w[c] = t[c] * wl[0] + bt[c] * wl[1] + n[c] * wl[2];
-      integrand(n, v, a, rough[i], metal[i], tex, R, env, H, W, idx + (size_t)K * i,
+      integrand(n, v, a, rough[i], metal[i], tex, R, env, H, W, env_oct, idx + (size_t)K * i,
                 wts + (size_t)K * i, K, w, wl[2], y, Li);
       for (int c = 0; c < 3; ++c) {
         acc[c] += y[c] / pdf;
@@ -410,8 +413,8 @@ void orc_prop_shade(long N, const double* pos, const double* normal, const doubl
 void orc_dump_integrand(long N, const double* pos, const double* normal, const double* view,
                         const double* cam, long ppf, const double* albedo, const double* rough,
                         const double* metal, const double* tex, int R, const double* env,
-                        int H, int W, const int32_t* idx, const double* wts, int K, int n_pb,
-                        uint32_t seed, double* T) {
+                        int H, int W, int env_oct, const int32_t* idx, const double* wts, int K,
+                        int n_pb, uint32_t seed, double* T) {
 #pragma omp parallel for schedule(dynamic, 8)
   for (long i = 0; i < N; ++i) {
     double n[3], v[3], a[3], t[3], bt[3];
@@ -429,7 +432,7 @@ void orc_dump_integrand(long N, const double* pos, const double* normal, const d
         double wl[3], w[3], y[3];
         double l = bin_direction(u, vv, wl);
         for (int c = 0; c < 3; ++c) w[c] = t[c] * wl[0] + bt[c] * wl[1] + n[c] * wl[2];
-        integrand(n, v, a, rough[i], metal[i], tex, R, env, H, W, idx + (size_t)K * i,
+        integrand(n, v, a, rough[i], metal[i], tex, R, env, H, W, env_oct, idx + (size_t)K * i,
                   wts + (size_t)K * i, K, w, wl[2], y, NULL);
         double lum = 0.2126 * y[0] + 0.7152 * y[1] + 0.0722 * y[2];
         acc += lum / (l * l * l);

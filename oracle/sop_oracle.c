@@ -167,6 +167,28 @@ void orc_env_fetch(const double* env, int H, int W, const double w[3], double ou
   }
 }
 
+/* Environment of a shading call: the equirectangular map above, or with oct an octahedral
+ * map [W][W][3] (the paper's own representation of the lighting) read exactly like a probe
+ * map: octahedral encode, bilinear taps with mirror wrap. */
+void orc_env_taps_any(const double w[3], int H, int W, int oct, int32_t tap[4], double wt[4]) {
+  if (!oct) {
+    orc_env_taps(w, H, W, tap, wt);
+    return;
+  }
+  double uv[2];
+  orc_oct_encode(w, W, uv);
+  orc_oct_taps(uv[0], uv[1], W, tap, wt);
+}
+
+void orc_env_fetch_any(const double* env, int H, int W, int oct, const double w[3],
+                       double out[3]) {
+  if (!oct) {
+    orc_env_fetch(env, H, W, w, out);
+    return;
+  }
+  orc_oct_fetch(env, W, 3, w, out);
+}
+
 /* ------------------------------------------------------------------------------------
  * Local frame around the normal: Duff et al., "Building an Orthonormal Basis, Revisited"
  * (JCGT 2017), branchless form with sign(0) = +1.
@@ -383,7 +405,7 @@ static void point_view(const orc_points* p, long i, double v[3]) {
 }
 
 static void shade_point(const orc_points* pts, long i, const double* tex, int R,
-                        const double* env, int H, int W, const int32_t* nb_idx,
+                        const double* env, int H, int W, int env_oct, const int32_t* nb_idx,
                         const double* nb_w, int K, int S, uint32_t seed, int per_point,
                         double rgb[3], double irr[3]) {
   double n[3], v[3], a[3];
@@ -396,7 +418,7 @@ static void shade_point(const orc_points* pts, long i, const double* tex, int R,
     double w[3];
     double ct = orc_direction(j, S, rho, n, w);
     double Lenv[3], Lin[3], O, f[3];
-    orc_env_fetch(env, H, W, w, Lenv);
+    orc_env_fetch_any(env, H, W, env_oct, w, Lenv);
     orc_interp(tex, R, nb_idx, nb_w, K, w, Lin, &O);
     orc_brdf(n, v, w, a, r, m, f);
     for (int c = 0; c < 3; ++c) {
@@ -414,12 +436,12 @@ static void shade_point(const orc_points* pts, long i, const double* tex, int R,
 void orc_shade(long N, const double* pos, const double* normal, const double* view,
                const double* cam, long ppf, const double* albedo, const double* rough,
                const double* metal, const double* tex, int R, const double* env, int H, int W,
-               const int32_t* idx, const double* w, int K, int S, uint32_t seed,
+               int env_oct, const int32_t* idx, const double* w, int K, int S, uint32_t seed,
                int per_point, double* rgb, double* irr) {
   orc_points p = {N, pos, normal, view, cam, ppf, albedo, rough, metal};
 #pragma omp parallel for schedule(dynamic, 16)
   for (long i = 0; i < N; ++i)
-    shade_point(&p, i, tex, R, env, H, W, idx + i * K, w + i * K, K, S, seed, per_point,
+    shade_point(&p, i, tex, R, env, H, W, env_oct, idx + i * K, w + i * K, K, S, seed, per_point,
                 rgb + 3 * i, irr ? irr + 3 * i : NULL);
 }
 
@@ -440,8 +462,8 @@ void orc_shade(long N, const double* pos, const double* normal, const double* vi
 void orc_shade_backward(long N, const double* pos, const double* normal, const double* view,
                         const double* cam, long ppf, const double* albedo, const double* rough,
                         const double* metal, const double* tex, int R, const double* env,
-                        int H, int W, const int32_t* idx, const double* wts, int K, int S,
-                        uint32_t seed, int per_point, const double* grad, double* g_albedo,
+                        int H, int W, int env_oct, const int32_t* idx, const double* wts, int K,
+                        int S, uint32_t seed, int per_point, const double* grad, double* g_albedo,
                         double* g_rough, double* g_metal, double* g_tex, double* g_env,
                         double* m_albedo, double* m_rough, double* m_metal, double* m_tex,
                         double* m_env) {
@@ -465,7 +487,7 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
       double w[3];
       double ct = orc_direction(j, S, rho, n, w);
       double Lenv[3], Lin[3], O, f[3];
-      orc_env_fetch(env, H, W, w, Lenv);
+      orc_env_fetch_any(env, H, W, env_oct, w, Lenv);
       orc_interp(tex, R, nb_idx, nb_w, K, w, Lin, &O);
       orc_brdf(n, v, w, a, r, m, f);
       /* BRDF pieces again for the material derivatives */
@@ -539,7 +561,7 @@ void orc_shade_backward(long N, const double* pos, const double* normal, const d
       if (g_env) {
         int32_t tap[4];
         double bt[4];
-        orc_env_taps(w, H, W, tap, bt);
+        orc_env_taps_any(w, H, W, env_oct, tap, bt);
         for (int t = 0; t < 4; ++t)
           for (int c = 0; c < 3; ++c) {
 #pragma omp atomic
@@ -715,8 +737,8 @@ void orc_shade_traced(int G, const double* mean, const double* scale, const doub
                       const double* opacity, const double* color, long N, const double* pos,
                       const double* normal, const double* view, const double* cam, long ppf,
                       const double* albedo, const double* rough, const double* metal,
-                      const double* env, int H, int W, int S, uint32_t seed, int per_point,
-                      float offset, double t_min, double alpha_min, double alpha_max,
+                      const double* env, int H, int W, int env_oct, int S, uint32_t seed,
+                      int per_point, float offset, double t_min, double alpha_min, double alpha_max,
                       double T_min, double* rgb, double* irr, double* samples,
                       int32_t* ray_flags) {
   orc_points p = {N, pos, normal, view, cam, ppf, albedo, rough, metal};
@@ -744,7 +766,7 @@ void orc_shade_traced(int G, const double* mean, const double* scale, const doub
         if (ray_flags) ray_flags[i * S + j] = amb;
         if (samples)
           for (int c = 0; c < 4; ++c) samples[(i * S + j) * 4 + c] = tr[c];
-        orc_env_fetch(env, H, W, w, Lenv);
+        orc_env_fetch_any(env, H, W, env_oct, w, Lenv);
         orc_brdf(n, v, w, a, r, m, f);
         for (int c = 0; c < 3; ++c) {
           double Li = (1.0 - tr[3]) * Lenv[c] + tr[c];

@@ -108,6 +108,7 @@ class ShadeScene:
     k: int
     radius: float = float("inf")
     seed: int = 0
+    env_oct: bool = False            # env is an octahedral map [R,R,3] (else equirect [H,W,3])
 
     @property
     def n(self) -> int:
