@@ -72,6 +72,7 @@ def main() -> int:
     ap.add_argument("--no-trace-study", action="store_true")
     ap.add_argument("--no-shadow-study", action="store_true")
     ap.add_argument("--no-place-study", action="store_true")
+    ap.add_argument("--no-env-study", action="store_true")
     ap.add_argument("--place-only", action="store_true",
                     help="only probe placement and the losses of the object workload (for "
                          "kernel traces of that path)")
@@ -311,6 +312,27 @@ def main() -> int:
         shadow = shadow_study(torch, sop, scenes, time_ms, bake_plan, R)
         print(f"# shadow study: {json.dumps(shadow)}", file=sys.stderr, flush=True)
 
+    envs = None
+    if not args.no_env_study:
+        import numpy as np
+        sky = torch.from_numpy(np.random.default_rng(5).lognormal(0.0, 1.5, (256, 256, 3))
+                               .astype(np.float32)).to(dev)
+        oct_env = sop.OctEnv(sky)
+        g_sky = torch.zeros_like(sky)
+        ws_fo = sop.workspace(plan.workspace_size(L.SOP_OP_SHADE, N, K, S, (256, 256), True), dev)
+        ws_bo = sop.workspace(plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, N, K, S, (256, 256),
+                                                  True), dev)
+        t_fo = time_ms(lambda: sop.sop_shade(plan, tex, oct_env, pts, S, nb=nb_p, ws=ws_fo,
+                                             out=rgb))
+        t_bo = time_ms(lambda: sop.sop_shade_backward(plan, tex, oct_env, pts, grad, S, nb=nb_p,
+                                                      g_env=g_sky, g_tex=g_tex, ws=ws_bo))
+        envs = {"workload": "object: 200k points, S=128, K=8; the step's 256x512 "
+                            "equirectangular sky against a 256x256 octahedral one",
+                "equirect_fwd_ms": round(phase["shade_fwd"], 4),
+                "equirect_bwd_ms": round(phase["shade_bwd"], 4),
+                "octahedral_fwd_ms": round(t_fo, 4), "octahedral_bwd_ms": round(t_bo, 4)}
+        print(f"# env study: {json.dumps(envs)}", file=sys.stderr, flush=True)
+
     place = None
     if not args.no_place_study:
         place = place_study(torch, sop, scenes, time_ms, tex)
@@ -345,6 +367,7 @@ def main() -> int:
         "trace_study": trace,
         "shadow_study": shadow,
         "place_study": place,
+        "env_study": envs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -89,12 +89,22 @@ typedef struct sop_probe_maps {
   const void* texels;            /* device [P,res,res,4]                                  */
 } sop_probe_maps;
 
-/* Environment map L_dir (Eq. 8) as an equirectangular image: row 0 is around +z, column u
- * covers azimuth phi = 2*pi*u/W - pi. Layout [H][W][3] (RGB). */
+/* Environment map L_dir (Eq. 8), layout [H][W][3] (RGB):
+ *   SOP_ENV_EQUIRECT (0, the default of a zeroed struct): equirectangular, row 0 around +z,
+ *     column u covering azimuth phi = 2*pi*u/W - pi; bilinear, columns wrap, rows clamp.
+ *   SOP_ENV_OCTAHEDRAL (1): an octahedral map with H = W (the paper's representation of
+ *     the estimated lighting, Sec. 3.2), read exactly like a probe map: +z at the centre
+ *     of the square, bilinear with mirror wrap. */
+typedef enum sop_env_layout {
+  SOP_ENV_EQUIRECT = 0,
+  SOP_ENV_OCTAHEDRAL = 1
+} sop_env_layout;
+
 typedef struct sop_envmap {
   int32_t      height;           /* H >= 1                                                */
-  int32_t      width;            /* W >= 1                                                */
+  int32_t      width;            /* W >= 1 (== H for SOP_ENV_OCTAHEDRAL, 2..1024)         */
   const float* texels;           /* device [H,W,3]                                        */
+  int32_t      layout;           /* sop_env_layout                                        */
 } sop_envmap;
 
 /* Shading points (G-buffer texels, Sec. 3.1, multi-target rendering). The view direction

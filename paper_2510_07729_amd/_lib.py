@@ -28,6 +28,7 @@ SOP_OP_DUMP_INTEGRAND, SOP_OP_PROPOSAL_INFER, SOP_OP_PROPOSAL_TRAIN = 4, 5, 6
 SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL, SOP_SAMPLER_PROPOSAL_NET = 0, 1, 2
 SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
 SOP_SHADOW_HAMMERSLEY, SOP_SHADOW_ENV = 0, 1
+SOP_ENV_EQUIRECT, SOP_ENV_OCTAHEDRAL = 0, 1
 
 
 class sop_probe_set(C.Structure):
@@ -40,7 +41,7 @@ class sop_probe_maps(C.Structure):
 
 
 class sop_envmap(C.Structure):
-    _fields_ = [("height", c_i32), ("width", c_i32), ("texels", c_vp)]
+    _fields_ = [("height", c_i32), ("width", c_i32), ("texels", c_vp), ("layout", c_i32)]
 
 
 class sop_points(C.Structure):

@@ -283,6 +283,11 @@ sop_status validate_env(const sop_envmap* env) {
     return fail(SOP_ERR_INVALID_ARGUMENT, "env size out of range");
   if (!env->texels || !aligned(env->texels, 4))
     return fail(SOP_ERR_INVALID_ARGUMENT, "env->texels is NULL or misaligned");
+  if (env->layout != SOP_ENV_EQUIRECT && env->layout != SOP_ENV_OCTAHEDRAL)
+    return fail(SOP_ERR_INVALID_ARGUMENT, "unknown env layout");
+  if (env->layout == SOP_ENV_OCTAHEDRAL &&
+      (env->height != env->width || env->width < 2 || env->width > 1024))
+    return fail(SOP_ERR_INVALID_ARGUMENT, "an octahedral env needs height == width in [2, 1024]");
   return SOP_OK;
 }
 
@@ -506,6 +511,7 @@ void set_dirs(sopk::ShadeArgs& a, const sop_envmap* env, const sop_shade_opts* o
   a.scale = (float)(2.0 * M_PI / o->n_dirs);
   a.seed = o->seed;
   a.per_point = o->rotate_per_point ? 1 : 0;
+  a.env_oct = env->layout == SOP_ENV_OCTAHEDRAL ? 1 : 0;
 }
 
 // the call's direction table, first piece of the workspace
@@ -514,10 +520,11 @@ sop_status setup_dirs(sopk::ShadeArgs& a, Bump& b, const sop_shade_opts* o, hipS
   double2* col = b.take<double2>((size_t)a.W + 2);
   double2* row = b.take<double2>((size_t)a.H + 2);
   a.dir_tab = tab;
-  a.col_ref = col;
-  a.row_ref = row;
+  // the reference directions serve the equirectangular lookup only
+  a.col_ref = a.env_oct ? nullptr : col;
+  a.row_ref = a.env_oct ? nullptr : row;
   SOP_HIP(sopk::launch_dir_table(o->n_dirs, o->seed, o->rotate_per_point ? 1 : 0, a.H, a.W, tab,
-                                 col, row, s),
+                                 a.env_oct ? nullptr : col, a.env_oct ? nullptr : row, s),
           "direction table");
   return SOP_OK;
 }
@@ -549,6 +556,8 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
+  if (opts->sampler != SOP_SAMPLER_HAMMERSLEY && a.env_oct)
+    return fail(SOP_ERR_UNSUPPORTED, "the proposal samplers take an equirectangular env");
   if (opts->sampler == SOP_SAMPLER_PROPOSAL_NET) {
     a.mix_eps = opts->mix_eps;
     a.mlp_params = opts->net->params;
@@ -586,6 +595,8 @@ extern "C" sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_m
   if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
   if (pts->count == 0) return SOP_OK;
   const hipStream_t s = (hipStream_t)stream;
+  if (env->layout != SOP_ENV_EQUIRECT)
+    return fail(SOP_ERR_UNSUPPORTED, "sop_dump_integrand takes an equirectangular env");
   sopk::ShadeArgs a = base_args(plan, maps, pts);
   set_dirs(a, env, opts);
   a.npb = samples_per_bin;

@@ -120,11 +120,31 @@ struct Sample {
   float O;
 };
 
+// environment taps of direction w64: equirectangular (FP64-corrected per-call references) or,
+// with EO, octahedral (the probe maps' lookup at the map's side). The layout is a template
+// parameter so that the equirectangular kernels carry no code of the other lookup.
+template <bool EO>
+__device__ __forceinline__ EnvTaps env_taps_of(const ShadeArgs& a, const double w64[3]) {
+  if constexpr (EO) {
+    const Taps t = oct_taps64(w64, a.W);
+    EnvTaps e;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      e.off[i] = t.off[i];
+      e.w[i] = t.w[i];
+    }
+    return e;
+  }
+  else {
+    return env_taps64(w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
+  }
+}
+
 // environment and probe fetches of a sample whose direction (w64, w, ct) is set
-template <int KT, typename TexT>
+template <int KT, typename TexT, bool EO = false>
 __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps,
                                         const Neighbors<KT>& nb, int32_t k, Sample& s) {
-  s.et = env_taps64(s.w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
+  s.et = env_taps_of<EO>(a, s.w64);
   s.Le[0] = s.Le[1] = s.Le[2] = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -160,7 +180,7 @@ __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps
   }
 }
 
-template <int KT, typename TexT>
+template <int KT, typename TexT, bool EO = false>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState& ps,
                                             const Neighbors<KT>& nb, int32_t k, int j,
                                             Sample& s) {
@@ -170,7 +190,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
   world_dir64(ps.F, da, db, e.z, s.w64);
   s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
   s.ct = (float)e.z;
-  eval_at<KT, TexT>(a, ps, nb, k, s);
+  eval_at<KT, TexT, EO>(a, ps, nb, k, s);
 }
 
 // Sum over the L lanes of a lane group (L = 64: the whole wavefront, with DPP).
@@ -193,7 +213,7 @@ __device__ __forceinline__ int64_t group_slot(int lane) {
   return (die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) + lane / L;
 }
 
-template <int KT, typename TexT, int L>
+template <int KT, typename TexT, int L, bool EO = false>
 // three wavefronts per SIMD (at most 168 registers): the batched tap loads would otherwise
 // take the kernel to two
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd(ShadeArgs a, int32_t k) {
@@ -211,7 +231,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     nb.load(a, ps.p, k);
     for (int j = li; j < a.S; j += L) {
       Sample s;
-      eval_sample<KT, TexT>(a, ps, nb, k, j, s);
+      eval_sample<KT, TexT, EO>(a, ps, nb, k, j, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
       const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
 #pragma unroll
@@ -243,7 +263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Traced shading: the estimate of k_shade_fwd with L_in and O of every sample read from its
 // traced ray (a.traced, [n,S] in the caller's point order) instead of the probes.
-template <int L>
+template <int L, bool EO = false>
 __global__ __launch_bounds__(256) void k_shade_traced(ShadeArgs a) {
   const int lane = threadIdx.x & 63, li = lane % L;
   const int64_t slot = group_slot<L>(lane);
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(256) void k_shade_traced(ShadeArgs a) {
       double w64[3];
       world_dir64(ps.F, da, db, e.z, w64);
       const float ct = (float)e.z;
-      const EnvTaps et = env_taps64(w64, a.H, a.W, a.u_scale, a.v_scale, a.col_ref, a.row_ref);
+      const EnvTaps et = env_taps_of<EO>(a, w64);
       float Le[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -847,14 +867,14 @@ struct SampleAdj {
   float gl[3], go, ge[3];
 };
 
-template <int KT, typename TexT>
+template <int KT, typename TexT, bool EO = false>
 __device__ __forceinline__ void sample_adjoint(const ShadeArgs& a, const PointState& ps,
                                                const Neighbors<KT>& nb, int32_t k, int j,
                                                const float g[3], float ga[3], float& gr,
                                                float& gm, Sample& s, SampleAdj& r) {
   const Material& M = ps.M;
   const float al[3] = {M.a.x, M.a.y, M.a.z};
-  eval_sample<KT, TexT>(a, ps, nb, k, j, s);
+  eval_sample<KT, TexT, EO>(a, ps, nb, k, j, s);
   const BrdfTerms bt = brdf_terms(M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
   const float om5 = 1.0f - bt.x5;
   // dD/dalpha = 2 alpha (1 - NoH^2 - alpha^2 NoH^2) / (pi q^3)
@@ -897,7 +917,7 @@ __device__ __forceinline__ void scatter_env(const ShadeArgs& a, const Sample& s,
 
 // General adjoint: one wavefront per point, texture gradients scattered with atomics.
 // Used when the grouped kernel below does not apply (res > 32, more than 16384 probes).
-template <int KT, typename TexT>
+template <int KT, typename TexT, bool EO = false>
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
   const int64_t wv = die_block() * kWavesPerBlock + wave_id_uniform();
   if (wv >= a.n) return;
@@ -916,7 +936,7 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
     if (j < a.S) {
       Sample s;
       SampleAdj r;
-      sample_adjoint<KT, TexT>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
+      sample_adjoint<KT, TexT, EO>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
       if (a.g_tex) {
         for (int s2 = 0; s2 < kc; ++s2) {
           const int32_t id = nb.id(s2, a, ps.p, k);
@@ -1015,7 +1035,7 @@ __device__ __forceinline__ void env_runs_flush(float* g_env, EnvRun* run, int la
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int KT, typename TexT>
+template <int KT, typename TexT, bool EO = false>
 __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a, int32_t k) {
   extern __shared__ float lds[];
   const int MV = a.R * a.R * 4;                         // values per map
@@ -1102,7 +1122,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
           Sample s;
           SampleAdj r;
           if (j < a.S) {
-            sample_adjoint<KT, TexT>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
+            sample_adjoint<KT, TexT, EO>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
               float* dst = Hb + s.tt.off[t] * 4;
@@ -1271,13 +1291,21 @@ hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, 
   return dispatch_prop(1, a, k, format, s);
 }
 
-template <int KT, int L>
-static void launch_fwd_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+template <int KT, int L, bool EO>
+static void launch_fwd_le(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   const dim3 grid = grid_for(a.n, L);
   if (format == SOP_TEXEL_F16)
-    hipLaunchKernelGGL((k_shade_fwd<KT, uint2, L>), grid, dim3(256), 0, s, a, k);
+    hipLaunchKernelGGL((k_shade_fwd<KT, uint2, L, EO>), grid, dim3(256), 0, s, a, k);
   else
-    hipLaunchKernelGGL((k_shade_fwd<KT, float4, L>), grid, dim3(256), 0, s, a, k);
+    hipLaunchKernelGGL((k_shade_fwd<KT, float4, L, EO>), grid, dim3(256), 0, s, a, k);
+}
+
+template <int KT, int L>
+static void launch_fwd_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  if (a.env_oct)
+    launch_fwd_le<KT, L, true>(a, k, format, s);
+  else
+    launch_fwd_le<KT, L, false>(a, k, format, s);
 }
 
 template <int KT>
@@ -1289,6 +1317,11 @@ static void launch_kt(bool fwd, const ShadeArgs& a, int32_t k, int32_t format, d
       case 32: launch_fwd_l<KT, 32>(a, k, format, s); break;
       default: launch_fwd_l<KT, 64>(a, k, format, s); break;
     }
+  } else if (a.env_oct) {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_bwd<KT, uint2, true>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_bwd<KT, float4, true>), grid, dim3(256), 0, s, a, k);
   } else {
     if (format == SOP_TEXEL_F16)
       hipLaunchKernelGGL((k_shade_bwd<KT, uint2>), grid, dim3(256), 0, s, a, k);
@@ -1312,13 +1345,21 @@ static hipError_t dispatch(bool fwd, const ShadeArgs& a, int32_t k, int32_t form
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   return dispatch(true, a, k, format, s);
 }
+template <int L>
+static void launch_traced_l(const ShadeArgs& a, hipStream_t s) {
+  if (a.env_oct)
+    hipLaunchKernelGGL((k_shade_traced<L, true>), grid_for(a.n, L), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_shade_traced<L, false>), grid_for(a.n, L), dim3(256), 0, s, a);
+}
+
 hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   if (!a.traced) return hipErrorInvalidValue;
   switch (lanes_for(a.S)) {
-    case 16: hipLaunchKernelGGL(k_shade_traced<16>, grid_for(a.n, 16), dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_shade_traced<32>, grid_for(a.n, 32), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_shade_traced<64>, grid_for(a.n, 64), dim3(256), 0, s, a); break;
+    case 16: launch_traced_l<16>(a, s); break;
+    case 32: launch_traced_l<32>(a, s); break;
+    default: launch_traced_l<64>(a, s); break;
   }
   return hipGetLastError();
 }
@@ -1371,21 +1412,29 @@ size_t batched_lds_bytes(int32_t R) {
          (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kEnvRuns * sizeof(EnvRun);
 }
 
-template <int KT>
-static void launch_batched_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+template <int KT, bool EO>
+static void launch_batched_kte(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + kBatch - 1) / kBatch));
   const size_t lds = batched_lds_bytes(a.R);
   // dynamic LDS above 64 KB must be allowed per kernel (gfx950 has 160 KB per CU)
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, uint2>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, uint2, EO>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, float4>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, float4, EO>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (format == SOP_TEXEL_F16)
-    hipLaunchKernelGGL((k_shade_bwd_batched<KT, uint2>), grid, dim3(kBatchThreads), lds, s, a,
-                       k);
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, uint2, EO>), grid, dim3(kBatchThreads), lds, s,
+                       a, k);
   else
-    hipLaunchKernelGGL((k_shade_bwd_batched<KT, float4>), grid, dim3(kBatchThreads), lds, s, a,
-                       k);
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, float4, EO>), grid, dim3(kBatchThreads), lds, s,
+                       a, k);
+}
+
+template <int KT>
+static void launch_batched_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  if (a.env_oct)
+    launch_batched_kte<KT, true>(a, k, format, s);
+  else
+    launch_batched_kte<KT, false>(a, k, format, s);
 }
 
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {

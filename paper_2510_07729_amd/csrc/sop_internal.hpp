@@ -85,6 +85,7 @@ struct ShadeArgs {
   float* rgb;
   float* irr;
   const float4* traced;     // [n,S] (L_in rgb, O) per sample (traced shading)
+  int32_t env_oct;          // env is an octahedral map [W,W,3] (else equirectangular [H,W,3])
   // cast-shadow ratio: octahedral environment in env, its texel masses and their prefix
   const uint32_t* env_mass; // [Re*Re]
   const uint64_t* env_prefix;  // [Re*Re + 1], env_prefix[Re*Re] = total mass

@@ -107,12 +107,29 @@ def _maps(tex: torch.Tensor) -> L.sop_probe_maps:
     return m
 
 
-def _env(env: torch.Tensor) -> L.sop_envmap:
-    if env.dim() != 3 or env.shape[2] != 3:
+class OctEnv:
+    """An octahedral environment map [R,R,3] (+z at the centre, read like a probe map) for
+    the shading calls, which otherwise take an equirectangular [H,W,3] tensor."""
+
+    def __init__(self, texels: torch.Tensor):
+        if texels.dim() != 3 or texels.shape[2] != 3 or texels.shape[0] != texels.shape[1]:
+            raise ValueError("an octahedral env must be [R,R,3]")
+        self.texels = texels
+
+    @property
+    def shape(self):
+        return self.texels.shape
+
+
+def _env(env) -> L.sop_envmap:
+    oct_ = isinstance(env, OctEnv)
+    t = env.texels if oct_ else env
+    if t.dim() != 3 or t.shape[2] != 3:
         raise ValueError("env must be [H,W,3]")
     e = L.sop_envmap()
-    e.height, e.width = int(env.shape[0]), int(env.shape[1])
-    e.texels = _ptr(env, torch.float32, "env")
+    e.height, e.width = int(t.shape[0]), int(t.shape[1])
+    e.texels = _ptr(t, torch.float32, "env")
+    e.layout = L.SOP_ENV_OCTAHEDRAL if oct_ else L.SOP_ENV_EQUIRECT
     return e
 
 

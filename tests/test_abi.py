@@ -157,6 +157,12 @@ def test_traced_shading_validation():
         assert call(offset=bad) == L.SOP_ERR_INVALID_ARGUMENT
         assert "offset" in lib.sop_last_error().decode()
     assert call(samples=0x2004) == L.SOP_ERR_INVALID_ARGUMENT       # not 16-byte aligned
+    env.layout = 2                                                  # unknown layout
+    assert call() == L.SOP_ERR_INVALID_ARGUMENT
+    env.layout = L.SOP_ENV_OCTAHEDRAL                               # 4 x 8 is not square
+    assert call() == L.SOP_ERR_INVALID_ARGUMENT
+    assert "octahedral" in lib.sop_last_error().decode()
+    env.layout = L.SOP_ENV_EQUIRECT
     o.sampler = L.SOP_SAMPLER_PROPOSAL
     assert call() == L.SOP_ERR_UNSUPPORTED
     o.sampler = L.SOP_SAMPLER_HAMMERSLEY

@@ -40,6 +40,8 @@ def test_bake_kernel_keeps_three_wavefronts(tmp_path):
     assert st["vgpr"] <= 168 and st["occupancy"] >= 3 and st["scratch"] == 0, st
 
 
-def test_shade_forward_keeps_three_wavefronts(tmp_path):
-    st = kernel_stats("shade.hip", tmp_path, "_ZN4sopk11k_shade_fwdILi8E15HIP_vector_typeIfLj4EELi64EE")
+@pytest.mark.parametrize("layout", ["Lb0E", "Lb1E"])      # equirectangular, octahedral sky
+def test_shade_forward_keeps_three_wavefronts(tmp_path, layout):
+    st = kernel_stats("shade.hip", tmp_path,
+                      "_ZN4sopk11k_shade_fwdILi8E15HIP_vector_typeIfLj4EELi64E" + layout)
     assert st["vgpr"] <= 168 and st["occupancy"] >= 3 and st["scratch"] == 0, st
