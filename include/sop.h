@@ -229,7 +229,9 @@ typedef struct sop_shade_opts {
  * distributions are the network's (opts->net), computed in the same kernel exactly as
  * sop_proposal_infer computes them; the result equals that of SOP_SAMPLER_PROPOSAL with
  * sop_proposal_infer's output up to the order of the per-point sums. The proposal samplers
- * have no adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. */
+ * have no adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. The proposal
+ * samplers (and sop_dump_integrand) take an equirectangular env only
+ * (SOP_ERR_UNSUPPORTED for SOP_ENV_OCTAHEDRAL). */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
                      const sop_points* pts, const sop_neighbors* nb,
                      const sop_shade_opts* opts, float* rgb,

@@ -103,3 +103,28 @@ def test_octahedral_sky_traced_and_rejections(torch_gpu):
         sop.sop_dump_integrand(pplan, dev(sc.texels), sop.OctEnv(dev(sc.env)), gpu_points(sc),
                                1, k=sc.k)
     assert e.value.status == L.SOP_ERR_UNSUPPORTED
+
+
+def test_octahedral_sky_through_autograd(torch_gpu):
+    import torch
+    from paper_2510_07729_amd import sop
+    from paper_2510_07729_amd.autograd import Geometry, shade
+    log("octahedral sky: autograd.shade against the direct calls")
+    sc = with_oct_sky(scenes.tiny_shade(n_points=300), 16, seed=11)
+    plan = gpu_plan(sc)
+    geom = Geometry(dev(sc.pos), dev(sc.normal), view=dev(sc.view))
+    albedo = dev(sc.albedo).requires_grad_(True)
+    env = dev(sc.env).requires_grad_(True)
+    rough, metal, tex = dev(sc.rough), dev(sc.metal), dev(sc.texels)
+    rgb = shade(albedo, rough, metal, env, tex, plan, geom, sc.n_dirs, sc.k, seed=sc.seed,
+                env_oct=True)
+    grad = torch.randn_like(rgb)
+    rgb.backward(grad)
+    pts = gpu_points(sc)
+    direct = sop.sop_shade(plan, tex, sop.OctEnv(dev(sc.env)), pts, sc.n_dirs, k=sc.k,
+                           seed=sc.seed)
+    g = sop.sop_shade_backward(plan, tex, sop.OctEnv(dev(sc.env)), pts, grad, sc.n_dirs,
+                               k=sc.k, seed=sc.seed, want=("albedo", "env"))
+    assert torch.equal(rgb.detach(), direct)
+    assert torch.allclose(albedo.grad, g["albedo"], rtol=1e-6, atol=1e-7)
+    assert torch.allclose(env.grad, g["env"], rtol=1e-5, atol=1e-6)
