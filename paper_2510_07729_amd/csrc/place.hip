@@ -3,10 +3,10 @@
 // normal, L_sops = L1(L_in, L_tr) + L1(O, O_tr) (probe textures towards the traced ones)
 // and L_lam = L1(R, 1) + L1(M, 0) (material regulariser), each with its gradient.
 //
-// FPS runs as one short kernel per pick: every point keeps its squared distance to the
-// nearest pick so far, and the next pick is the maximum of 64-bit keys (distance bits,
-// inverted index) taken with a 64-bit atomic max into one of three rotating slots, so no
-// kernel ever waits on another workgroup. The losses are single coalesced passes with
+// FPS runs as one short kernel per pick: every point, stored as (x, y, z, d) in 16 bytes,
+// keeps its squared distance d to the nearest pick so far, and the next pick is the maximum
+// of 64-bit keys (distance bits, inverted index) taken with a 64-bit atomic max into one of
+// three rotating slots, so no kernel ever waits on another workgroup. The losses are single coalesced passes with
 // per-workgroup FP64 partial sums added in a fixed order (the same inputs give the same
 // loss bit for bit).
 #include "sop_internal.hpp"
@@ -16,9 +16,9 @@ namespace sopk {
 // squared distance in IEEE single precision, in the fixed order ((dx dx + dy dy) + dz dz)
 // and without fused multiply-adds (contraction is switched off here: the compiler would
 // otherwise fuse the products into the sums), so that every comparison is reproducible
-__device__ __forceinline__ float fps_d2(const float* a, float qx, float qy, float qz) {
+__device__ __forceinline__ float fps_d2(float4 a, float4 q) {
 #pragma clang fp contract(off)
-  const float dx = a[0] - qx, dy = a[1] - qy, dz = a[2] - qz;
+  const float dx = a.x - q.x, dy = a.y - q.y, dz = a.z - q.z;
   return (dx * dx + dy * dy) + dz * dz;
 }
 
@@ -33,25 +33,67 @@ __device__ __forceinline__ int64_t fps_index(uint64_t key) {
 
 __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
+// Points per thread and sweep of a step: a workgroup takes 256 * kFpsPpt consecutive
+// points per sweep; the grid is capped at kFpsMaxBlocks workgroups (larger clouds take
+// several sweeps), because the atomics of a pick, one per workgroup on a single slot, are
+// serialised and dominate beyond a few hundred.
+#ifndef SOP_FPS_PPT
+#define SOP_FPS_PPT 4
+#endif
+#ifndef SOP_FPS_MAXB
+#define SOP_FPS_MAXB 256
+#endif
+constexpr int kFpsPpt = SOP_FPS_PPT;
+constexpr int64_t kFpsChunk = 256 * kFpsPpt;
+constexpr int64_t kFpsMaxBlocks = SOP_FPS_MAXB;
+
+// pd[j] = (x_j, y_j, z_j, +inf): the points with their distance to the nearest pick so far
+__global__ __launch_bounds__(256) void k_fps_pack(const float* pts, int64_t M, float4* pd) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < M)
+    pd[j] = make_float4(pts[3 * j], pts[3 * j + 1], pts[3 * j + 2], __int_as_float(0x7F800000));
+}
+
 // Pick k (1 <= k < P): the pick of step k-1 (the start for k = 1, else the winner in slot
 // (k-1)%3) lowers every point's distance; the workgroup maxima of the keys go into slot k%3;
-// slot (k+1)%3, which no kernel of steps k-1 or k touches, is cleared for step k+1.
-__global__ __launch_bounds__(256) void k_fps_step(const float* pts, int64_t M, float* dist,
-                                                  uint64_t* slots, int32_t* chosen, int32_t k,
-                                                  int64_t start) {
+// slot (k+1)%3, which no kernel of steps k-1 or k touches, is cleared for step k+1. Each
+// thread loads its first points before the winner of the previous step, so the two loads
+// overlap.
+__device__ __forceinline__ void fps_load(const float4* pd, int64_t M, int64_t j0,
+                                         float4 (&p)[kFpsPpt]) {
+#pragma unroll
+  for (int u = 0; u < kFpsPpt; ++u) {
+    const int64_t j = j0 + u * 256;
+    p[u] = j < M ? pd[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fps_step(float4* pd, int64_t M, uint64_t* slots,
+                                                  int32_t* chosen, int32_t k, int64_t start) {
   __shared__ uint64_t wave_best[4];
+  int64_t base = (int64_t)blockIdx.x * kFpsChunk;       // the same for the whole workgroup
+  float4 p[kFpsPpt];
+  fps_load(pd, M, base + threadIdx.x, p);
   const int64_t q = k == 1 ? start : fps_index(slots[(k - 1) % 3]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     chosen[k - 1] = (int32_t)q;
     slots[(k + 1) % 3] = 0;
   }
-  const float qx = pts[3 * q], qy = pts[3 * q + 1], qz = pts[3 * q + 2];
+  const float4 c = pd[q];                     // only x, y, z are used (w may be changing)
   uint64_t best = 0;
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < M;
-       j += (int64_t)gridDim.x * 256) {
-    const float d = fminf(dist[j], fps_d2(pts + 3 * j, qx, qy, qz));
-    dist[j] = d;
-    best = max_u64(best, fps_key(d, j));
+  for (;;) {
+#pragma unroll
+    for (int u = 0; u < kFpsPpt; ++u) {
+      const int64_t j = base + threadIdx.x + u * 256;
+      if (j < M) {
+        const float d = fminf(p[u].w, fps_d2(p[u], c));
+        reinterpret_cast<float*>(pd + j)[3] = d;
+        best = max_u64(best, fps_key(d, j));
+      }
+    }
+    base += (int64_t)gridDim.x * kFpsChunk;
+    if (base >= M) break;
+    fps_load(pd, M, base + threadIdx.x, p);
   }
   for (int o = 32; o > 0; o >>= 1) {
     const uint32_t lo = __shfl_xor((uint32_t)best, o), hi = __shfl_xor((uint32_t)(best >> 32), o);
@@ -81,18 +123,21 @@ __global__ __launch_bounds__(256) void k_fps_finish(const float* pts, const floa
 }
 
 hipError_t launch_place_probes(const float* pts, const float* nrm, int64_t M, int32_t P,
-                               int64_t start, float offset, float* dist, uint64_t* slots,
+                               int64_t start, float offset, float* packed, uint64_t* slots,
                                int32_t* chosen, float* out, hipStream_t s) {
   if (P < 1) return hipSuccess;
-  if (M < 1 || start < 0 || start >= M || !pts || !nrm || !dist || !slots || !chosen || !out)
+  if (M < 1 || M > INT32_MAX || start < 0 || start >= M || !pts || !nrm || !packed || !slots ||
+      !chosen || !out)
     return hipErrorInvalidValue;
-  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(dist), 0x7F800000, (size_t)M, s);
-  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t*>(slots), 0, 6, s);
+  float4* pd4 = reinterpret_cast<float4*>(packed);
+  hipLaunchKernelGGL(k_fps_pack, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, pts, M,
+                     pd4);
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(slots), 0, 6, s);
   if (e != hipSuccess) return e;
-  const unsigned blocks = (unsigned)std::min<int64_t>((M + 255) / 256, 2048);
+  const unsigned blocks = (unsigned)std::min((M + kFpsChunk - 1) / kFpsChunk, kFpsMaxBlocks);
   for (int32_t k = 1; k < P; ++k)
-    hipLaunchKernelGGL(k_fps_step, dim3(blocks), dim3(256), 0, s, pts, M, dist, slots, chosen,
-                       k, start);
+    hipLaunchKernelGGL(k_fps_step, dim3(blocks), dim3(256), 0, s, pd4, M, slots, chosen, k,
+                       start);
   hipLaunchKernelGGL(k_fps_finish, dim3((unsigned)std::min<int64_t>((P + 255) / 256, 1024)),
                      dim3(256), 0, s, pts, nrm, slots, chosen, P, start, offset, out);
   return hipGetLastError();

@@ -205,7 +205,7 @@ hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int
 // farthest point sampling of P of M points from `start` (dist [M] and slots [3] scratch),
 // chosen [P], probes out [P,3] = fmaf(offset, n, x)
 hipError_t launch_place_probes(const float* pts, const float* nrm, int64_t M, int32_t P,
-                               int64_t start, float offset, float* dist, uint64_t* slots,
+                               int64_t start, float offset, float* packed, uint64_t* slots,
                                int32_t* chosen, float* out, hipStream_t s);
 // doubles of partial sums the loss launches need for n elements
 size_t loss_partials(int64_t n);

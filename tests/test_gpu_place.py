@@ -36,7 +36,10 @@ def check_place(pts, nrm, P, start, offset, label):
     assert np.array_equal(pos, oracle.place(pts, nrm, ref, offset))
 
 
-@pytest.mark.parametrize("M,P,start", [(1000, 100, 7), (4099, 333, 4098), (300, 300, 0)])
+# the last cloud takes several sweeps per workgroup (more points than 256 workgroups of
+# 1024), with a ragged tail
+@pytest.mark.parametrize("M,P,start", [(1000, 100, 7), (4099, 333, 4098), (300, 300, 0),
+                                       (600_001, 96, 600_000)])
 def test_fps_random_clouds(torch_gpu, M, P, start):
     g = np.random.default_rng(M)
     pts = g.uniform(-1, 1, (M, 3)).astype(F32)
