@@ -37,15 +37,9 @@ __device__ __forceinline__ uint64_t max_u64(uint64_t a, uint64_t b) { return a >
 // points per sweep; the grid is capped at kFpsMaxBlocks workgroups (larger clouds take
 // several sweeps), because the atomics of a pick, one per workgroup on a single slot, are
 // serialised and dominate beyond a few hundred.
-#ifndef SOP_FPS_PPT
-#define SOP_FPS_PPT 4
-#endif
-#ifndef SOP_FPS_MAXB
-#define SOP_FPS_MAXB 256
-#endif
-constexpr int kFpsPpt = SOP_FPS_PPT;
+constexpr int kFpsPpt = 4;
 constexpr int64_t kFpsChunk = 256 * kFpsPpt;
-constexpr int64_t kFpsMaxBlocks = SOP_FPS_MAXB;
+constexpr int64_t kFpsMaxBlocks = 256;
 
 // pd[j] = (x_j, y_j, z_j, +inf): the points with their distance to the nearest pick so far
 __global__ __launch_bounds__(256) void k_fps_pack(const float* pts, int64_t M, float4* pd) {
@@ -86,8 +80,10 @@ __global__ __launch_bounds__(256) void k_fps_step(float4* pd, int64_t M, uint64_
     for (int u = 0; u < kFpsPpt; ++u) {
       const int64_t j = base + threadIdx.x + u * 256;
       if (j < M) {
-        const float d = fminf(p[u].w, fps_d2(p[u], c));
-        reinterpret_cast<float*>(pd + j)[3] = d;
+        const float d2 = fps_d2(p[u], c);
+        const float d = fminf(p[u].w, d2);
+        // only a distance that shrinks is written back (after the first picks most do not)
+        if (d2 < p[u].w) reinterpret_cast<float*>(pd + j)[3] = d;
         best = max_u64(best, fps_key(d, j));
       }
     }
