@@ -297,7 +297,7 @@ typedef struct sop_bake_opts {
   float alpha_max;               /* default 0.99                                          */
   float T_min;                   /* default 1e-4                                          */
   float cell_scale;              /* grid cell side relative to the mean cut-off box of the
-                                    Gaussians; 0 selects the library default (0.35)       */
+                                    Gaussians; 0 selects the library default (0.25)       */
 } sop_bake_opts;
 
 typedef struct sop_bake_plan sop_bake_plan;   /* Gaussian grid (opaque)                   */

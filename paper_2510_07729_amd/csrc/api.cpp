@@ -951,7 +951,7 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
       lo[a] -= pad;
       hi[a] += pad;
     }
-    const double cs = o.cell_scale > 0.0f ? (double)o.cell_scale : 0.35;
+    const double cs = o.cell_scale > 0.0f ? (double)o.cell_scale : 0.25;
     double h = cs * (double)ext_sum / n_reg;
     if (!(h > 0)) h = 1.0;
     for (;;) {

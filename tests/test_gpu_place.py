@@ -93,6 +93,21 @@ def test_sops_loss_object_maps(torch_gpu):
     assert np.array_equal(loss.cpu().numpy(), loss2.cpu().numpy())     # fixed order
 
 
+def test_sops_loss_ragged_and_empty(torch_gpu):
+    from paper_2510_07729_amd import sop
+    log("L_sops: 1001 texels (a ragged workgroup), then none")
+    g = np.random.default_rng(5)
+    tex = g.standard_normal((1001, 4)).astype(F32)
+    tgt = g.standard_normal((1001, 4)).astype(F32)
+    tgt[::3] = tex[::3]
+    loss, grad = sop.sop_sops_loss(dev(tex), dev(tgt))
+    rl, rg = oracle.sops_loss(tex, tgt)
+    assert report("L_sops ragged loss", parity_err(loss.cpu().numpy(), rl)) <= TOL
+    assert report("L_sops ragged grad", parity_err(grad.cpu().numpy(), rg)) <= TOL
+    z, zg = sop.sop_sops_loss(dev(tex[:0]), dev(tgt[:0]))
+    assert np.all(z.cpu().numpy() == 0.0) and zg.numel() == 0
+
+
 def test_lam_loss(torch_gpu):
     from paper_2510_07729_amd import sop
     log("L_lam: 200,001 points, some at r = 1 and m = 0 exactly")
