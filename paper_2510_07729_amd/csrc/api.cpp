@@ -832,6 +832,7 @@ struct sop_bake_plan {
   sop_bake_opts opts{};
   float4* gdata = nullptr;
   float4* aabb = nullptr;
+  uint64_t* cellmask = nullptr;   // [G][kCellMaskWords] acceptance bits of the count pass
   int32_t* counts = nullptr;
   int32_t* cell_start = nullptr;
   int32_t* cursor = nullptr;
@@ -843,10 +844,11 @@ struct sop_bake_plan {
   size_t ncell = 0;
 
   void release() {
-    void* ptrs[] = {gdata, aabb, counts, cell_start, cursor, entries, scan_tmp, misc};
+    void* ptrs[] = {gdata, aabb, cellmask, counts, cell_start, cursor, entries, scan_tmp, misc};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     gdata = aabb = nullptr;
+    cellmask = nullptr;
     counts = cell_start = cursor = entries = scan_tmp = misc = nullptr;
   }
 };
@@ -885,7 +887,8 @@ sop_bake_opts resolve_bake_opts(const sop_bake_opts* o) {
 hipError_t register_gaussians(sop_bake_plan* pl, hipStream_t s) {
   hipError_t e = sopk::launch_fill_i32(pl->counts, 0, pl->ncell, s);
   if (e == hipSuccess) e = sopk::launch_fill_i32(pl->cursor, 0, pl->ncell, s);
-  if (e == hipSuccess) e = sopk::launch_gauss_count(pl->grid, pl->aabb, pl->counts, pl->misc + 7, s);
+  if (e == hipSuccess)
+    e = sopk::launch_gauss_count(pl->grid, pl->aabb, pl->counts, pl->cellmask, pl->misc + 7, s);
   if (e == hipSuccess)
     e = sopk::launch_exclusive_scan(pl->counts, pl->cell_start, pl->ncell, pl->scan_tmp, s);
   return e;
@@ -915,6 +918,7 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   };
   alloc((void**)&pl->gdata, G1 * 5 * sizeof(float4));
   alloc((void**)&pl->aabb, G1 * 2 * sizeof(float4));
+  alloc((void**)&pl->cellmask, G1 * sopk::kCellMaskWords * sizeof(uint64_t));
   alloc((void**)&pl->misc, 16 * sizeof(int32_t));
   auto bail = [&](sop_status code, const std::string& msg) {
     pl->release();
@@ -1003,8 +1007,8 @@ extern "C" sop_status sop_bake_plan_create(const sop_gaussians* g, const sop_bak
   if (e != hipSuccess) return bail(SOP_ERR_OUT_OF_MEMORY, "bake entries allocation");
   G.entries = pl->entries;
   G.capacity = pl->capacity;
-  e = sopk::launch_gauss_fill(G, pl->aabb, pl->cell_start, pl->cursor, pl->entries,
-                              pl->capacity, pl->misc + 7, s);
+  e = sopk::launch_gauss_fill(G, pl->aabb, pl->cellmask, pl->cell_start, pl->cursor,
+                              pl->entries, pl->capacity, pl->misc + 7, s);
   if (e != hipSuccess) return bail(SOP_ERR_DEVICE, std::string("bake fill: ") + hipGetErrorString(e));
   *out = pl;
   return SOP_OK;
@@ -1027,8 +1031,9 @@ extern "C" sop_status sop_bake_plan_update(sop_bake_plan* plan, const sop_gaussi
     return SOP_OK;
   }
   SOP_HIP(register_gaussians(plan, s), "sop_bake_plan_update");
-  SOP_HIP(sopk::launch_gauss_fill(plan->grid, plan->aabb, plan->cell_start, plan->cursor,
-                                  plan->entries, plan->capacity, plan->misc + 7, s),
+  SOP_HIP(sopk::launch_gauss_fill(plan->grid, plan->aabb, plan->cellmask, plan->cell_start,
+                                  plan->cursor, plan->entries, plan->capacity, plan->misc + 7,
+                                  s),
           "sop_bake_plan_update");
   return SOP_OK;
 }

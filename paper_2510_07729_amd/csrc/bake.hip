@@ -229,8 +229,12 @@ __device__ __forceinline__ void box_cell(const int c0[3], int nx, int ny, int t,
   z = c0[2] + t / (nx * ny);
 }
 
+// The count pass keeps the acceptance bits of the first 64 kCellMaskWords cells of every box
+// (one wavefront ballot per 64 cells), so the fill pass repeats the exact test only beyond
+// them.
 __global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* aabb,
-                                                     int32_t* counts, int32_t* overflow) {
+                                                     int32_t* counts, uint64_t* cellmask,
+                                                     int32_t* overflow) {
   const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= G.G) return;
@@ -240,15 +244,28 @@ __global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* a
   if (lane == 0 && !inside_grid(G, lo, hi)) atomicOr(overflow, 1);
   const float4* gd = G.gdata + (size_t)kGRows * i;
   const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
-  for (int t = lane; t < nx * ny * nz; t += 64) {
-    int x, y, z;
-    box_cell(c0, nx, ny, t, x, y, z);
-    if (cell_overlaps(G, gd, x, y, z) && cell_meets_ellipsoid(G, gd, x, y, z))
-      atomicAdd(&counts[(z * G.dims[1] + y) * G.dims[0] + x], 1);
+  const int n = nx * ny * nz;
+  for (int t0 = 0; t0 < n; t0 += 64) {       // the same trip count for every lane
+    const int t = t0 + lane;
+    bool acc = false;
+    int32_t c = 0;
+    if (t < n) {
+      int x, y, z;
+      box_cell(c0, nx, ny, t, x, y, z);
+      acc = cell_overlaps(G, gd, x, y, z) && cell_meets_ellipsoid(G, gd, x, y, z);
+      c = (z * G.dims[1] + y) * G.dims[0] + x;
+    }
+    const int w = t0 >> 6;
+    if (w < kCellMaskWords) {
+      const uint64_t m = __ballot(acc);
+      if (lane == 0) cellmask[(size_t)kCellMaskWords * i + w] = m;
+    }
+    if (acc) atomicAdd(&counts[c], 1);
   }
 }
 
 __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aabb,
+                                                    const uint64_t* cellmask,
                                                     const int32_t* cell_start, int32_t* cursor,
                                                     int32_t* entries, int32_t capacity,
                                                     int32_t* overflow) {
@@ -265,10 +282,17 @@ __global__ __launch_bounds__(256) void k_gauss_fill(BakeGrid G, const float4* aa
   if (!cell_range(G, lo, hi, c0, c1)) return;
   const float4* gd = G.gdata + (size_t)kGRows * i;
   const int nx = c1[0] - c0[0] + 1, ny = c1[1] - c0[1] + 1, nz = c1[2] - c0[2] + 1;
-  for (int t = lane; t < nx * ny * nz; t += 64) {
+  const int n = nx * ny * nz;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    const int t = t0 + lane;
+    if (t >= n) continue;
     int x, y, z;
     box_cell(c0, nx, ny, t, x, y, z);
-    if (!cell_overlaps(G, gd, x, y, z) || !cell_meets_ellipsoid(G, gd, x, y, z)) continue;
+    const int w = t0 >> 6;
+    const bool acc = w < kCellMaskWords
+                         ? ((cellmask[(size_t)kCellMaskWords * i + w] >> lane) & 1) != 0
+                         : cell_overlaps(G, gd, x, y, z) && cell_meets_ellipsoid(G, gd, x, y, z);
+    if (!acc) continue;
     const int32_t c = (z * G.dims[1] + y) * G.dims[0] + x;
     const int32_t slot = cell_start[c] + atomicAdd(&cursor[c], 1);
     entries[slot] = i;
@@ -676,21 +700,21 @@ hipError_t launch_gauss_prep(const sop_gaussians& g, float alpha_min, float4* gd
 }
 
 hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* counts,
-                              int32_t* overflow, hipStream_t s) {
+                              uint64_t* cellmask, int32_t* overflow, hipStream_t s) {
   if (G.G == 0) return hipSuccess;
-  if (!G.gdata || !aabb || !counts || !overflow) return hipErrorInvalidValue;
+  if (!G.gdata || !aabb || !counts || !cellmask || !overflow) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gauss_count, dim3((G.G + 3) / 4), dim3(256), 0, s, G, aabb, counts,
-                     overflow);
+                     cellmask, overflow);
   return hipGetLastError();
 }
 
-hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_t* cell_start,
-                             int32_t* cursor, int32_t* entries, int32_t capacity,
-                             int32_t* overflow, hipStream_t s) {
+hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const uint64_t* cellmask,
+                             const int32_t* cell_start, int32_t* cursor, int32_t* entries,
+                             int32_t capacity, int32_t* overflow, hipStream_t s) {
   if (G.G == 0) return hipSuccess;
-  if (!G.gdata || !aabb || !cell_start || !cursor || !entries || !overflow)
+  if (!G.gdata || !aabb || !cellmask || !cell_start || !cursor || !entries || !overflow)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 3) / 4), dim3(256), 0, s, G, aabb,
+  hipLaunchKernelGGL(k_gauss_fill, dim3((G.G + 3) / 4), dim3(256), 0, s, G, aabb, cellmask,
                      cell_start, cursor, entries, capacity, overflow);
   return hipGetLastError();
 }

@@ -179,11 +179,13 @@ struct BakeGrid {
 hipError_t launch_gauss_prep(const sop_gaussians& g, float alpha_min, float4* gdata,
                              float4* aabb, int32_t* bounds_ord, float* ext_sum, int32_t* n_reg,
                              hipStream_t s);
+// 64-bit words of cell acceptance bits the count pass keeps per Gaussian for the fill pass
+constexpr int kCellMaskWords = 4;
 hipError_t launch_gauss_count(const BakeGrid& G, const float4* aabb, int32_t* counts,
-                              int32_t* overflow, hipStream_t s);
-hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const int32_t* cell_start,
-                             int32_t* cursor, int32_t* entries, int32_t capacity,
-                             int32_t* overflow, hipStream_t s);
+                              uint64_t* cellmask, int32_t* overflow, hipStream_t s);
+hipError_t launch_gauss_fill(const BakeGrid& G, const float4* aabb, const uint64_t* cellmask,
+                             const int32_t* cell_start, int32_t* cursor, int32_t* entries,
+                             int32_t capacity, int32_t* overflow, hipStream_t s);
 // traced shading: one ray per (point, direction) sample
 struct TraceArgs {
   int64_t n;                // points
