@@ -180,3 +180,15 @@ def test_bake_morton_order_is_output_invariant(torch_gpu):
     t2, d2 = sop.sop_bake(plan, probes, 16, order_by=pplan)
     torch.cuda.synchronize()
     assert np.array_equal(t1, t2.cpu().numpy()) and np.array_equal(d1, d2.cpu().numpy())
+
+
+def test_bake_grid_cell_size_is_output_invariant(torch_gpu):
+    """The grid only decides which Gaussians a ray tests, never which it resolves: cells of
+    0.2, 0.5 and 1.0 of the mean cut-off box give the bytes of the default size."""
+    log("bake: 512 object probes at 16x16 with four grid cell sizes")
+    gs = scenes.object_gaussians()
+    probes_np = scenes.object_probes()[:512]
+    _, t0, d0 = gpu_bake(gs, probes_np, 16)
+    for cs in (0.2, 0.5, 1.0):
+        _, t1, d1 = gpu_bake(gs, probes_np, 16, cell_scale=cs)
+        assert np.array_equal(t0, t1) and np.array_equal(d0, d1), cs
