@@ -92,7 +92,7 @@ def _sig(lib):
     lib.orc_mlp_infer.argtypes = [dptr, C.c_long, dptr, dptr, dptr, dptr, dptr, dptr, C.c_int,
                                   dptr, dptr]
     lib.orc_mlp_loss_grad.argtypes = [dptr, C.c_long, dptr, dptr, dptr, dptr, dptr, dptr, dptr,
-                                      C.c_int, dptr, dptr]
+                                      C.c_int, dptr, dptr, dptr]
     lib.orc_adam.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_double, C.c_double,
                              C.c_double, C.c_double, C.c_int]
     lib.orc_hash24.restype = u32
@@ -627,18 +627,22 @@ def mlp_infer(params, pos, normal, view, rough, lo, hi, emulate_bf16=True):
     return logits, probs
 
 
-def mlp_loss_grad(params, pos, normal, view, rough, lo, hi, targets, emulate_bf16=True):
-    """(loss, grad [P]) of the mean cross entropy against row-normalised targets [B,256]."""
+def mlp_loss_grad(params, pos, normal, view, rough, lo, hi, targets, emulate_bf16=True,
+                  mass=False):
+    """(loss, grad [P]) of the mean cross entropy against row-normalised targets [B,256];
+    with mass=True (loss, grad, mass [P]), mass = the sum of |terms| of each entry."""
     P, pp = _d(params)
     keep, ptrs = _pts(pos, normal, view, rough)
     lo_, plo = _d(lo)
     hi_, phi = _d(hi)
     T, pt = _d(targets)
     grad = np.zeros(P.shape[0])
+    m = np.zeros(P.shape[0]) if mass else None
     loss = np.zeros(1)
     lib().orc_mlp_loss_grad(pp, keep[0].shape[0], *ptrs, plo, phi, pt, int(emulate_bf16),
-                            grad.ctypes.data_as(dptr), loss.ctypes.data_as(dptr))
-    return float(loss[0]), grad
+                            grad.ctypes.data_as(dptr), loss.ctypes.data_as(dptr),
+                            m.ctypes.data_as(dptr) if mass else None)
+    return (float(loss[0]), grad, m) if mass else (float(loss[0]), grad)
 
 
 def adam(params, m, v, grad, lr, beta1, beta2, eps, step):

@@ -163,12 +163,18 @@ void orc_mlp_infer(const double* P, long N, const double* pos, const double* nor
  * batch of -sum_b t_b log q_b. With emu = 1 the backward operands are rounded to bfloat16
  * where the GPU rounds them: the output-side gradients dz (before they meet a weight or an
  * activation) and the weights; bias gradients use the unrounded dz.
+ * mass (optional, [PR_PARAMS]) receives the sum of |terms| of every gradient entry: the
+ * same chain rule with every factor replaced by its absolute value and q_b - t_b by
+ * q_b + t_b, the scale that bounds the rounding of the sum whatever cancels inside it. A
+ * pre-activation within 1e-5 of its own sum of |terms| of zero may fall on either side of
+ * the ReLU's kink under another rounding order, so its path counts in the mass either way.
  * ----------------------------------------------------------------------------------*/
 void orc_mlp_loss_grad(const double* P, long B, const double* pos, const double* normal,
                        const double* view, const double* rough, const double lo[3],
                        const double hi[3], const double* T, int emu, double* grad,
-                       double* loss_out) {
+                       double* loss_out, double* mass) {
   memset(grad, 0, sizeof(double) * PR_PARAMS);
+  if (mass) memset(mass, 0, sizeof(double) * PR_PARAMS);
   double loss = 0.0;
   for (long i = 0; i < B; ++i) {
     double feat[PR_IN], a0[PR_IN], z1[PR_H], h1[PR_H], z2[PR_H], h2[PR_H], z3[PR_BINS],
@@ -185,40 +191,77 @@ void orc_mlp_loss_grad(const double* P, long B, const double* pos, const double*
     double lse = mx + log(se);
     for (int b = 0; b < PR_BINS; ++b) loss -= t[b] * (z3[b] - lse) / (double)B;
 
-    double dz3[PR_BINS], dz3r[PR_BINS];
+    double dz3[PR_BINS], dz3r[PR_BINS], m3[PR_BINS];
     for (int b = 0; b < PR_BINS; ++b) {
       dz3[b] = (q[b] - t[b]) / (double)B;
       dz3r[b] = rnd(dz3[b], emu);
+      m3[b] = (q[b] + t[b]) / (double)B;
     }
-    double dh2[PR_H] = {0};
+    double dh2[PR_H] = {0}, mh2[PR_H] = {0};
     for (int k = 0; k < PR_H; ++k)
       for (int o = 0; o < PR_BINS; ++o) {
+        const double wr = rnd(P[PR_OFF_W3 + k * PR_BINS + o], emu);
         grad[PR_OFF_W3 + k * PR_BINS + o] += h2[k] * dz3r[o];
-        dh2[k] += rnd(P[PR_OFF_W3 + k * PR_BINS + o], emu) * dz3r[o];
+        dh2[k] += wr * dz3r[o];
+        if (mass) {
+          mass[PR_OFF_W3 + k * PR_BINS + o] += fabs(h2[k]) * m3[o];
+          mh2[k] += fabs(wr) * m3[o];
+        }
       }
-    for (int o = 0; o < PR_BINS; ++o) grad[PR_OFF_B3 + o] += dz3[o];
+    for (int o = 0; o < PR_BINS; ++o) {
+      grad[PR_OFF_B3 + o] += dz3[o];
+      if (mass) mass[PR_OFF_B3 + o] += m3[o];
+    }
 
-    double dz2[PR_H], dz2r[PR_H];
+    double dz2[PR_H], dz2r[PR_H], m2[PR_H];
     for (int k = 0; k < PR_H; ++k) {
       dz2[k] = z2[k] > 0.0 ? dh2[k] : 0.0;
       dz2r[k] = rnd(dz2[k], emu);
+      m2[k] = 0.0;
+      if (mass) {
+        double zm = fabs(P[PR_OFF_B2 + k]);
+        for (int i2 = 0; i2 < PR_H; ++i2)
+          zm += fabs(h1[i2] * rnd(P[PR_OFF_W2 + i2 * PR_H + k], emu));
+        m2[k] = (z2[k] > 0.0 || fabs(z2[k]) <= 1e-5 * zm) ? mh2[k] : 0.0;
+      }
     }
-    double dh1[PR_H] = {0};
+    double dh1[PR_H] = {0}, mh1[PR_H] = {0};
     for (int k = 0; k < PR_H; ++k)
       for (int o = 0; o < PR_H; ++o) {
+        const double wr = rnd(P[PR_OFF_W2 + k * PR_H + o], emu);
         grad[PR_OFF_W2 + k * PR_H + o] += h1[k] * dz2r[o];
-        dh1[k] += rnd(P[PR_OFF_W2 + k * PR_H + o], emu) * dz2r[o];
+        dh1[k] += wr * dz2r[o];
+        if (mass) {
+          mass[PR_OFF_W2 + k * PR_H + o] += fabs(h1[k]) * m2[o];
+          mh1[k] += fabs(wr) * m2[o];
+        }
       }
-    for (int o = 0; o < PR_H; ++o) grad[PR_OFF_B2 + o] += dz2[o];
+    for (int o = 0; o < PR_H; ++o) {
+      grad[PR_OFF_B2 + o] += dz2[o];
+      if (mass) mass[PR_OFF_B2 + o] += m2[o];
+    }
 
-    double dz1[PR_H], dz1r[PR_H];
+    double dz1[PR_H], dz1r[PR_H], m1[PR_H];
     for (int k = 0; k < PR_H; ++k) {
       dz1[k] = z1[k] > 0.0 ? dh1[k] : 0.0;
       dz1r[k] = rnd(dz1[k], emu);
+      m1[k] = 0.0;
+      if (mass) {
+        double zm = fabs(P[PR_OFF_B1 + k]);
+        for (int i2 = 0; i2 < PR_IN; ++i2)
+          zm += fabs(a0[i2] * rnd(P[PR_OFF_W1 + i2 * PR_H + k], emu));
+        m1[k] = (z1[k] > 0.0 || fabs(z1[k]) <= 1e-5 * zm) ? mh1[k] : 0.0;
+      }
     }
     for (int k = 0; k < PR_IN; ++k)
-      for (int o = 0; o < PR_H; ++o) grad[PR_OFF_W1 + k * PR_H + o] += a0[k] * dz1r[o];
-    for (int o = 0; o < PR_H; ++o) grad[PR_OFF_B1 + o] += dz1[o];
+      for (int o = 0; o < PR_H; ++o) {
+        grad[PR_OFF_W1 + k * PR_H + o] += a0[k] * dz1r[o];
+        if (mass) mass[PR_OFF_W1 + k * PR_H + o] += fabs(a0[k]) * m1[o];
+      }
+    for (int o = 0; o < PR_H; ++o) {
+      grad[PR_OFF_B1 + o] += dz1[o];
+      if (mass) mass[PR_OFF_B1 + o] += m1[o];
+    }
   }
   *loss_out = loss;
 }

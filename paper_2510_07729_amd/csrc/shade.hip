@@ -1102,7 +1102,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
     misc[0] = n;
   }
   __syncthreads();
-  if (tid < ne && lead >= 0) W[erank[lead] * kBatch + tid / k] = ew[tid];
+  // added, not stored: a list that names one probe twice counts both entries, as the
+  // forward does
+  if (tid < ne && lead >= 0) atomicAdd(&W[erank[lead] * kBatch + tid / k], ew[tid]);
   __syncthreads();
 
   // --- splat: wavefront b takes point b, lanes take directions -----------------------------

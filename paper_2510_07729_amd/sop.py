@@ -32,6 +32,20 @@ def _ptr(t: Optional[torch.Tensor], dtype=None, what: str = "tensor") -> Optiona
     return t.data_ptr()
 
 
+def _shape(t: Optional[torch.Tensor], shape, what: str, dtype=None) -> None:
+    """Raises ValueError unless t (when given) has `shape` (None matches any size) and, when
+    asked, `dtype`. The C ABI receives bare pointers and cannot check sizes itself: a
+    mismatch here would otherwise become an out-of-bounds device access."""
+    if t is None:
+        return
+    if t.dim() != len(shape) or any(s is not None and int(t.shape[i]) != int(s)
+                                    for i, s in enumerate(shape)):
+        want = "[" + ",".join("*" if s is None else str(int(s)) for s in shape) + "]"
+        raise ValueError(f"{what} has shape {list(t.shape)}, expected {want}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} has dtype {t.dtype}, expected {dtype}")
+
+
 def workspace(nbytes: int, device) -> torch.Tensor:
     """A 256-byte-aligned byte buffer of at least nbytes (the tensor may be larger)."""
     buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
@@ -57,7 +71,24 @@ class Points:
     def n(self) -> int:
         return int(self.pos.shape[0])
 
+    def check(self) -> None:
+        """Every per-point array has N rows; camera mode needs F * points_per_frame == N."""
+        n = self.n
+        _shape(self.pos, (n, 3), "pos")
+        _shape(self.normal, (n, 3), "normal")
+        _shape(self.albedo, (n, 3), "albedo")
+        _shape(self.rough, (n,), "rough")
+        _shape(self.metal, (n,), "metal")
+        _shape(self.view, (n, 3), "view")
+        if self.view is None:
+            if self.cam_pos is None:
+                raise ValueError("points need view vectors or camera positions")
+            _shape(self.cam_pos, (None, 3), "cam_pos")
+            if int(self.cam_pos.shape[0]) * int(self.points_per_frame) != n:
+                raise ValueError("cam_pos rows * points_per_frame must equal the point count")
+
     def c(self) -> L.sop_points:
+        self.check()
         f = torch.float32
         s = L.sop_points()
         s.count = self.n
@@ -83,7 +114,15 @@ class Neighbors:
     def k(self) -> int:
         return int(self.idx.shape[1])
 
-    def c(self) -> L.sop_neighbors:
+    def check(self, n: Optional[int] = None) -> None:
+        k = self.k
+        rows = int(self.idx.shape[0]) if n is None else int(n)
+        _shape(self.idx, (rows, k), "nb.idx")
+        _shape(self.w, (rows, k), "nb.w")
+        _shape(self.order, (rows,), "nb.order")
+
+    def c(self, n: Optional[int] = None) -> L.sop_neighbors:
+        self.check(n)
         s = L.sop_neighbors()
         s.k = self.k
         s.order = _ptr(self.order, torch.int32, "order")
@@ -92,10 +131,17 @@ class Neighbors:
         return s
 
 
-def _maps(tex: torch.Tensor) -> L.sop_probe_maps:
-    m = L.sop_probe_maps()
+def _maps_shape(tex: torch.Tensor, plan=None) -> None:
     if tex.dim() != 4 or tex.shape[1] != tex.shape[2] or tex.shape[3] != 4:
         raise ValueError("probe textures must be [P,R,R,4]")
+    if plan is not None and int(tex.shape[0]) != int(plan.n_probes):
+        raise ValueError(f"probe textures hold {int(tex.shape[0])} maps, the plan "
+                         f"{int(plan.n_probes)} probes")
+
+
+def _maps(tex: torch.Tensor, plan=None) -> L.sop_probe_maps:
+    _maps_shape(tex, plan)
+    m = L.sop_probe_maps()
     m.res = int(tex.shape[1])
     if tex.dtype == torch.float32:
         m.format = L.SOP_TEXEL_F32
@@ -121,11 +167,16 @@ class OctEnv:
         return self.texels.shape
 
 
-def _env(env) -> L.sop_envmap:
-    oct_ = isinstance(env, OctEnv)
-    t = env.texels if oct_ else env
+def _env_shape(env) -> None:
+    t = env.texels if isinstance(env, OctEnv) else env
     if t.dim() != 3 or t.shape[2] != 3:
         raise ValueError("env must be [H,W,3]")
+
+
+def _env(env) -> L.sop_envmap:
+    _env_shape(env)
+    oct_ = isinstance(env, OctEnv)
+    t = env.texels if oct_ else env
     e = L.sop_envmap()
     e.height, e.width = int(t.shape[0]), int(t.shape[1])
     e.texels = _ptr(t, torch.float32, "env")
@@ -138,6 +189,7 @@ class Plan:
     """Probe grid for the neighbour search (sop_plan_create / sop_plan_destroy)."""
 
     def __init__(self, probe_pos: torch.Tensor, bounds_lo, bounds_hi):
+        _shape(probe_pos, (None, 3), "probe_pos")
         self._lib = L.load()
         ps = L.sop_probe_set()
         ps.count = int(probe_pos.shape[0])
@@ -151,6 +203,7 @@ class Plan:
         self.device = probe_pos.device
 
     def rebuild(self, probe_pos: torch.Tensor) -> None:
+        _shape(probe_pos, (self.n_probes, 3), "probe_pos")
         L.check(self._lib.sop_plan_rebuild(self.handle, _ptr(probe_pos, torch.float32, "pos"),
                                            _stream()), "sop_plan_rebuild")
 
@@ -182,11 +235,16 @@ class Plan:
 def sop_knn(plan: Plan, pts: Points, k: int, radius: float = math.inf) -> Neighbors:
     dev = pts.pos.device
     n = pts.n
+    _shape(pts.pos, (n, 3), "pos")
+    _shape(pts.normal, (n, 3), "normal")
     order = torch.empty(n, dtype=torch.int32, device=dev)
     idx = torch.empty((n, k), dtype=torch.int32, device=dev)
     w = torch.empty((n, k), dtype=torch.float32, device=dev)
     ws = workspace(plan.workspace_size(L.SOP_OP_KNN, n, k), dev)
-    cp = pts.c()
+    cp = L.sop_points()
+    cp.count = n
+    cp.pos = _ptr(pts.pos, torch.float32, "pos")
+    cp.normal = _ptr(pts.normal, torch.float32, "normal")
     L.check(plan._lib.sop_knn(plan.handle, C.byref(cp), k, radius, order.data_ptr(),
                               idx.data_ptr(), w.data_ptr(), ws.data_ptr(), ws.numel(),
                               _stream()), "sop_knn")
@@ -196,15 +254,20 @@ def sop_knn(plan: Plan, pts: Points, k: int, radius: float = math.inf) -> Neighb
 def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
               nb: Optional[Neighbors] = None, k: int = 4, radius: float = math.inf):
     """Eq. 9 at given world directions dirs [N,D,3]: returns (L_in [N,D,3], O [N,D])."""
-    n, D = int(dirs.shape[0]), int(dirs.shape[1])
+    n, D = pts.n, int(dirs.shape[1]) if dirs.dim() == 3 else -1
+    _shape(dirs, (n, None, 3), "dirs")
+    pts.check()
+    _maps_shape(texels, plan)
+    if nb is not None:
+        nb.check(n)
     dev = dirs.device
     Lin = torch.empty((n, D, 3), dtype=torch.float32, device=dev)
     O = torch.empty((n, D), dtype=torch.float32, device=dev)
     kk = nb.k if nb is not None else k
     ws = workspace(plan.workspace_size(L.SOP_OP_QUERY, n, kk, D, with_neighbors=nb is not None),
                    dev)
-    m, cp = _maps(texels), pts.c()
-    nbc = nb.c() if nb is not None else None
+    m, cp = _maps(texels, plan), pts.c()
+    nbc = nb.c(n) if nb is not None else None
     L.check(plan._lib.sop_query(plan.handle, C.byref(m), C.byref(cp),
                                 C.byref(nbc) if nbc is not None else None,
                                 _ptr(dirs, torch.float32, "dirs"), D, k, radius, Lin.data_ptr(),
@@ -243,6 +306,13 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
     with net (an Mlp) from the network's distributions, evaluated inside the call."""
     dev = pts.pos.device
     n = pts.n
+    pts.check()
+    _maps_shape(texels, plan)
+    _env_shape(env)
+    _shape(out, (n, 3), "out", torch.float32)
+    _shape(probs, (n, L.SOP_MLP_BINS), "probs", torch.float32)
+    if nb is not None:
+        nb.check(n)
     rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
     irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
     kk = nb.k if nb is not None else k
@@ -250,8 +320,8 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
         ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, env.shape[:2],
                                            nb is not None), dev)
     o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr, probs, mix_eps, net)
-    m, e, cp = _maps(texels), _env(env), pts.c()
-    nbc = nb.c() if nb is not None else None
+    m, e, cp = _maps(texels, plan), _env(env), pts.c()
+    nbc = nb.c(n) if nb is not None else None
     L.check(plan._lib.sop_shade(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
                                 C.byref(nbc) if nbc is not None else None, C.byref(o),
                                 _ptr(rgb, torch.float32, "rgb"), ws.data_ptr(), ws.numel(),
@@ -271,6 +341,15 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
     new ones otherwise); per-point gradients are fresh tensors."""
     dev = pts.pos.device
     n = pts.n
+    pts.check()
+    _maps_shape(texels, plan)
+    _env_shape(env)
+    _shape(grad_rgb, (n, 3), "grad_rgb", torch.float32)
+    # the library adds float32 gradients over exactly these sizes
+    _shape(g_env, tuple(env.shape), "g_env", torch.float32)
+    _shape(g_tex, tuple(texels.shape), "g_tex", torch.float32)
+    if nb is not None:
+        nb.check(n)
     out = {}
     if "albedo" in want:
         out["albedo"] = torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -289,8 +368,8 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
         ws = workspace(plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, n, kk, n_dirs, env.shape[:2],
                                            nb is not None), dev)
     o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point)
-    m, e, cp = _maps(texels), _env(env), pts.c()
-    nbc = nb.c() if nb is not None else None
+    m, e, cp = _maps(texels, plan), _env(env), pts.c()
+    nbc = nb.c(n) if nb is not None else None
     g = grad_rgb.contiguous()
     L.check(plan._lib.sop_shade_backward(
         plan.handle, C.byref(m), C.byref(e), C.byref(cp),
@@ -311,6 +390,12 @@ def sop_dump_integrand(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
     """Training targets [N,256]: per-bin integrals of the luminance of f L_i cos."""
     dev = pts.pos.device
     n = pts.n
+    pts.check()
+    _maps_shape(texels, plan)
+    _env_shape(env)
+    _shape(out, (n, L.SOP_MLP_BINS), "out", torch.float32)
+    if nb is not None:
+        nb.check(n)
     T = out if out is not None else torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32,
                                                 device=dev)
     kk = nb.k if nb is not None else k
@@ -318,8 +403,8 @@ def sop_dump_integrand(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
         ws = workspace(plan.workspace_size(L.SOP_OP_DUMP_INTEGRAND, n, kk, 1, env.shape[:2],
                                            nb is not None), dev)
     o = shade_opts(1, kk, seed, radius)
-    m, e, cp = _maps(texels), _env(env), pts.c()
-    nbc = nb.c() if nb is not None else None
+    m, e, cp = _maps(texels, plan), _env(env), pts.c()
+    nbc = nb.c(n) if nb is not None else None
     L.check(plan._lib.sop_dump_integrand(
         plan.handle, C.byref(m), C.byref(e), C.byref(cp),
         C.byref(nbc) if nbc is not None else None, C.byref(o), int(samples_per_bin),
@@ -360,6 +445,8 @@ def sop_proposal_infer(mlp: Mlp, pts: Points, logits: bool = False,
     """probs [N,256] (and logits [N,256] when asked)."""
     dev = pts.pos.device
     n = pts.n
+    pts.check()
+    _shape(out, (n, L.SOP_MLP_BINS), "out", torch.float32)
     probs = out if out is not None else torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32,
                                                     device=dev)
     lg = torch.empty((n, L.SOP_MLP_BINS), dtype=torch.float32, device=dev) if logits else None
@@ -384,6 +471,10 @@ def sop_proposal_train_step(mlp: Mlp, pts: Points, targets: torch.Tensor,
     """One step: returns the batch loss (device scalar tensor). With lr the parameters are
     updated by Adam (mlp.step advances); with grad the batch gradient is written there."""
     dev = pts.pos.device
+    pts.check()
+    _shape(targets, (pts.n, L.SOP_MLP_BINS), "targets")
+    _shape(grad, (L.SOP_MLP_PARAMS,), "grad", torch.float32)
+    _shape(loss, (1,), "loss", torch.float32)
     lo = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=dev)
     if ws is None:
         ws = proposal_workspace(L.SOP_OP_PROPOSAL_TRAIN, pts.n, dev)
@@ -402,6 +493,9 @@ def sop_proposal_train_step(mlp: Mlp, pts: Points, targets: torch.Tensor,
 
 def sop_adam_update(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
                     grad: torch.Tensor, lr: float, step: int, **adam_kw) -> None:
+    for t, what in ((m, "m"), (v, "v"), (grad, "grad")):
+        if t.numel() != params.numel():
+            raise ValueError(f"{what} has {t.numel()} entries, params {params.numel()}")
     opt = adam_opts(lr, step, **adam_kw)
     L.check(L.load().sop_adam_update(_ptr(params, torch.float32), _ptr(m, torch.float32),
                                      _ptr(v, torch.float32), _ptr(grad, torch.float32),
@@ -462,7 +556,12 @@ def sop_bake(plan: BakePlan, probe_pos: torch.Tensor, res: int, depth: bool = Tr
              order_by: Optional[Plan] = None):
     """Probe textures [P,res,res,4] (R,G,B,O) and depth [P,res,res] by ray tracing; with
     order_by (a probe Plan over the same probes) the probes are traced in its Morton order."""
+    _shape(probe_pos, (None, 3), "probe_pos")
     P = int(probe_pos.shape[0])
+    _shape(texels, (P, res, res, 4), "texels", torch.float32)
+    _shape(depth_out, (P, res, res), "depth_out", torch.float32)
+    if order_by is not None and int(order_by.n_probes) != P:
+        raise ValueError(f"order_by plan has {int(order_by.n_probes)} probes, not {P}")
     dev = probe_pos.device
     tex = texels if texels is not None else torch.empty((P, res, res, 4), dtype=torch.float32,
                                                         device=dev)
@@ -490,6 +589,10 @@ def sop_shade_traced(plan: BakePlan, env: torch.Tensor, pts: Points, n_dirs: int
     orders the points for ray coherence without changing the result."""
     dev = pts.pos.device
     n = pts.n
+    pts.check()
+    _env_shape(env)
+    _shape(out, (n, 3), "out", torch.float32)
+    _shape(samples_out, (n, int(n_dirs), 4), "samples_out", torch.float32)
     rgb = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
     irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
     smp = samples_out
@@ -520,6 +623,13 @@ def sop_shadow_ratio(plan: Plan, texels: torch.Tensor, env_oct: torch.Tensor, pt
     texels [P,R,R,4]; with irradiance=True also the unshadowed estimate [N,3]."""
     dev = pts.pos.device
     n = pts.n
+    _shape(pts.pos, (n, 3), "pos")
+    _shape(pts.normal, (n, 3), "normal")
+    _maps_shape(texels, plan)
+    _shape(env_oct, (None, None, 3), "env_oct")
+    _shape(out, (n, 3), "out", torch.float32)
+    if nb is not None:
+        nb.check(n)
     ratio = out if out is not None else torch.empty((n, 3), dtype=torch.float32, device=dev)
     irr = torch.empty((n, 3), dtype=torch.float32, device=dev) if irradiance else None
     kk = nb.k if nb is not None else k
@@ -535,8 +645,12 @@ def sop_shadow_ratio(plan: Plan, texels: torch.Tensor, env_oct: torch.Tensor, pt
     e = L.sop_env_oct()
     e.res = int(env_oct.shape[0])
     e.texels = _ptr(env_oct, torch.float32, "env_oct")
-    m, cp = _maps(texels), pts.c()
-    nbc = nb.c() if nb is not None else None
+    m = _maps(texels, plan)
+    cp = L.sop_points()
+    cp.count = n
+    cp.pos = _ptr(pts.pos, torch.float32, "pos")
+    cp.normal = _ptr(pts.normal, torch.float32, "normal")
+    nbc = nb.c(n) if nb is not None else None
     L.check(lib.sop_shadow_ratio(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
                                  C.byref(nbc) if nbc is not None else None, C.byref(o),
                                  _ptr(ratio, torch.float32, "ratio"), ws.data_ptr(), ws.numel(),
@@ -549,8 +663,10 @@ def sop_place_probes(pts: torch.Tensor, normals: torch.Tensor, n_probes: int, st
     """Farthest point sampling of n_probes of the surface points pts [M,3] (normals [M,3])
     from `start`, each pick raised by `offset` along its normal: (probe_pos [P,3],
     chosen [P] int32)."""
-    lib = L.load()
+    _shape(pts, (None, 3), "pts")
     M, dev = int(pts.shape[0]), pts.device
+    _shape(normals, (M, 3), "normals")
+    lib = L.load()
     out = torch.empty((int(n_probes), 3), dtype=torch.float32, device=dev)
     chosen = torch.empty(int(n_probes), dtype=torch.int32, device=dev)
     if ws is None:
@@ -568,6 +684,11 @@ def sop_sops_loss(tex: torch.Tensor, target: torch.Tensor, grad: bool = True,
                   grad_out: Optional[torch.Tensor] = None):
     """L_sops of probe textures [...,4] against the traced ones: (loss [2] =
     (L1(L_in, L_tr), L1(O, O_tr)), gradient of their sum w.r.t. tex or None)."""
+    if tex.dim() < 1 or tex.shape[-1] != 4:
+        raise ValueError("probe textures must end in 4 channels")
+    _shape(target, tuple(tex.shape), "target")
+    _shape(grad_out, tuple(tex.shape), "grad_out", torch.float32)
+    _shape(loss_out, (2,), "loss_out", torch.float32)
     lib = L.load()
     T, dev = int(tex.numel() // 4), tex.device
     loss = loss_out if loss_out is not None else torch.empty(2, dtype=torch.float32, device=dev)
@@ -584,6 +705,8 @@ def sop_sops_loss(tex: torch.Tensor, target: torch.Tensor, grad: bool = True,
 def sop_lam_loss(rough: torch.Tensor, metal: torch.Tensor, grad: bool = True,
                  ws: Optional[torch.Tensor] = None):
     """L_lam of the materials: (loss [2] = (L1(R, 1), L1(M, 0)), g_rough, g_metal)."""
+    _shape(rough, (None,), "rough")
+    _shape(metal, (int(rough.shape[0]),), "metal")
     lib = L.load()
     N, dev = int(rough.numel()), rough.device
     loss = torch.empty(2, dtype=torch.float32, device=dev)

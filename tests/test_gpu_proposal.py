@@ -39,15 +39,15 @@ def gpu_mlp(params, sc):
 def logit_mass(params, sc, rows):
     """sum_k |h2_k W3_kb| + |b3_b| per logit (oracle activations): the scale of a logit's
     rounding error."""
-    W3 = params[OFF["W3"]].astype(np.float64).reshape(64, 256)
-    b3 = params[OFF["b3"]].astype(np.float64)
+    W3 = params[OFF["W3"]].astype(np.float64)
+    W3r = np.abs(np.array([oracle.bf16(x) for x in W3])).reshape(64, 256)
+    b3 = np.abs(params[OFF["b3"]].astype(np.float64))
+    P64 = params.astype(np.float64)
     out = []
     for i in rows:
         f = oracle.pe_features(sc.pos[i], sc.normal[i], sc.view[i], sc.rough[i], sc.bounds_lo,
                                sc.bounds_hi)
-        h2 = oracle.mlp_forward(params.astype(np.float64), f)["h2"]
-        out.append(np.abs(h2) @ np.abs(np.array([[oracle.bf16(x) for x in row] for row in W3]))
-                   + np.abs(b3))
+        out.append(np.abs(oracle.mlp_forward(P64, f)["h2"]) @ W3r + b3)
     return np.array(out)
 
 
@@ -64,11 +64,11 @@ def test_infer_matches_bf16_oracle(torch_gpu, n):
     lg, pg = logits.cpu().numpy(), probs.cpu().numpy()
     lo, po = oracle.mlp_infer(params.astype(np.float64), sc.pos, sc.normal, sc.view, sc.rough,
                               sc.bounds_lo, sc.bounds_hi, emulate_bf16=True)
-    rows = np.arange(min(n, 64))
+    rows = np.arange(n)                      # every row
     mass = logit_mass(params, sc, rows)
     rel = np.abs(lg[rows] - lo[rows]) / mass
-    log(f"logits: max |d|/mass {rel.max():.3e}  p99.9 {np.percentile(rel, 99.9):.3e}; "
-        f"max |d| all rows {np.abs(lg - lo).max():.3e}")
+    log(f"logits ({n} rows): max |d|/mass {rel.max():.3e}  p99.9 "
+        f"{np.percentile(rel, 99.9):.3e}; max |d| {np.abs(lg - lo).max():.3e}")
     # one bfloat16 step (2^-8 relative) of an operand moves a logit by far less than its
     # mass; FP32 vs FP64 accumulation adds ~1e-7 of it
     assert np.percentile(rel, 99.9) <= 2.0 ** -8 and rel.max() <= 2.0 ** -6
@@ -111,15 +111,22 @@ def test_train_gradient_matches_oracle(torch_gpu, B):
     loss = sop().sop_proposal_train_step(mlp, gpu_points(sc), dev(T), grad=grad)
     torch.cuda.synchronize()
     g = grad.cpu().numpy().astype(np.float64)
-    lo, go = oracle.mlp_loss_grad(params.astype(np.float64), sc.pos, sc.normal, sc.view,
-                                  sc.rough, sc.bounds_lo, sc.bounds_hi, T, emulate_bf16=True)
+    lo, go, gm = oracle.mlp_loss_grad(params.astype(np.float64), sc.pos, sc.normal, sc.view,
+                                      sc.rough, sc.bounds_lo, sc.bounds_hi, T,
+                                      emulate_bf16=True, mass=True)
     lg = float(loss.item())
     log(f"loss gpu {lg:.7f} oracle {lo:.7f}")
     assert abs(lg - lo) <= 1e-4 * abs(lo)
+    # element by element against the entry's sum of |terms|: both sides round the same
+    # operands to bfloat16, so they differ by the accumulation order (~1e-7 of the mass)
+    # and by the rare operand whose FP32 and FP64 values round to neighbouring bfloat16
+    # numbers (a 2^-8 change of that one sample's terms)
     for name, sl in OFF.items():
-        e = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
-        log(f"grad {name}: relative L2 error {e:.3e}")
-        assert e <= 1e-2, name
+        e = sum_err(g[sl], go[sl], gm[sl])
+        l2 = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        log(f"grad {name}: max |d|/mass {e.max():.3e}  p99.9 {np.percentile(e, 99.9):.3e}  "
+            f"(relative L2 {l2:.3e})")
+        assert e.max() <= 2.0 ** -6, name
     # parameters untouched without an optimiser
     assert np.array_equal(mlp.params.cpu().numpy(), params)
 
@@ -330,3 +337,46 @@ def test_fused_network_sampler_matches_two_steps(torch_gpu, n, k, S):
     assert report("fused vs two-step rgb", parity_err(one.cpu().numpy(), two.cpu().numpy())) <= 1e-5
     assert report("fused vs two-step irradiance",
                   parity_err(one_e.cpu().numpy(), two_e.cpu().numpy())) <= 1e-5
+
+
+def exact_logit_network(n_active: int, seed: int):
+    """A network whose logits both sides compute exactly: random first and second layers,
+    W3 = 0 and b3 = 0 on n_active bins (a power of two) and -1000 elsewhere, so that the
+    softmax is exactly 1/n_active on the active bins and 0 elsewhere in FP32 and FP64 alike
+    (exp(0) = 1, exp(-1000) = 0). Every mass decision is then the same on both sides."""
+    params = scenes.mlp_init(seed=seed)
+    params[OFF["b1"]] = 0.1
+    params[OFF["W3"]] = 0.0
+    b3 = np.full(256, -1000.0, np.float32)
+    b3[np.random.default_rng(seed).choice(256, n_active, replace=False)] = 0.0
+    params[OFF["b3"]] = b3
+    return params
+
+
+@pytest.mark.parametrize("scene,n_active,S,k", [("tiny", 8, 32, 4), ("tiny", 256, 7, 4),
+                                                ("tiny", 1, 16, 4), ("object", 64, 32, 8)])
+def test_fused_network_sampler_matches_oracle(torch_gpu, scene, n_active, S, k):
+    """The fused kernel (network on the matrix cores, softmax, masses, draws, shading in one
+    launch) against the oracle's network followed by the oracle's proposal shading, element
+    by element, for networks whose bin probabilities both compute exactly."""
+    log(f"fused proposal shading vs oracle: {scene} scene, {n_active} active bins, S={S}, K={k}")
+    import torch
+    if scene == "tiny":
+        sc = scenes.tiny_shade(n_points=509, seed=4)
+    else:
+        full = scenes.object_scene()
+        sc = full.subset(np.arange(2000))
+    params = exact_logit_network(n_active, seed=n_active + S)
+    lo_, probs = oracle.mlp_infer(params.astype(np.float64), sc.pos, sc.normal, sc.view,
+                                  sc.rough, sc.bounds_lo, sc.bounds_hi, emulate_bf16=True)
+    assert np.all(np.isin(probs, (0.0, 1.0 / n_active)))
+    idx, w = oracle_knn(sc, k)
+    ref, ref_e = oracle.prop_shade(sc, idx, w, probs.astype(np.float32), 0.1, S, 19,
+                                   irradiance=True)
+    mlp = sop().Mlp(dev(params), sc.bounds_lo, sc.bounds_hi)
+    plan = gpu_plan(sc)
+    rgb, irr = sop().sop_shade(plan, dev(sc.texels), dev(sc.env), gpu_points(sc), S, k=k,
+                               seed=19, irradiance=True, net=mlp, mix_eps=0.1)
+    torch.cuda.synchronize()
+    assert report("fused vs oracle rgb", parity_err(rgb.cpu().numpy(), ref)) <= TOL
+    assert report("fused vs oracle irradiance", parity_err(irr.cpu().numpy(), ref_e)) <= TOL

@@ -286,3 +286,28 @@ def test_training_targets_sum_to_the_shading_luminance(small_scene):
     zero = oracle.dump_integrand(sc, idx, w, 2, 11, env=np.zeros_like(sc.env),
                                  texels=np.zeros(sc.texels.shape))
     assert np.all(zero == 0.0)
+
+
+def test_gradient_mass_bounds_the_gradient():
+    """The sum of |terms| of each gradient entry: never below |gradient| (triangle
+    inequality, so a sign slip in the chain fails), and for the output biases it sums to
+    exactly 2 over the bins (sum over points of sum_b (q_b + t_b) / B, both rows normalised)."""
+    P = scenes.mlp_init(seed=1).astype(np.float64)
+    P[OFF["b1"]] = 0.05
+    pos, n, v, r, T = random_batch(B=48)
+    T[5] = 0.0                                   # an empty row counts as uniform
+    args = (pos, n, v, r, -np.ones(3), np.ones(3), T)
+    for emu in (False, True):
+        loss, g, m = oracle.mlp_loss_grad(P, *args, emulate_bf16=emu, mass=True)
+        _, g2 = oracle.mlp_loss_grad(P, *args, emulate_bf16=emu)
+        assert np.array_equal(g, g2)
+        if not emu:
+            assert np.all(m >= np.abs(g) * (1 - 1e-12))
+        assert m[OFF["b3"]].sum() == pytest.approx(2.0, rel=1e-12)
+        assert np.all(m >= 0)
+    # first-layer units all off: no mass reaches the first layer or the weights after it
+    P0 = P.copy()
+    P0[OFF["b1"]] = -100.0
+    _, g0, m0 = oracle.mlp_loss_grad(P0, *args, emulate_bf16=False, mass=True)
+    for name in ("W1", "b1", "W2"):
+        assert np.all(m0[OFF[name]] == 0) and np.all(g0[OFF[name]] == 0)
