@@ -202,9 +202,9 @@ def test_backward_list_naming_a_probe_twice(torch_gpu):
     grad = np.random.default_rng(24).standard_normal((sc.n, 3)).astype(np.float32)
     plan = gpu_plan(sc)
     pts = gpu_points(sc)
-    rgb = sop.sop_shade(plan, dev(sc.texels), dev(sc.env), pts, sc.n_dirs, nb=nb)
+    rgb = sop.sop_shade(plan, dev(sc.texels), dev(sc.env), pts, sc.n_dirs, nb=nb, seed=sc.seed)
     g = sop.sop_shade_backward(plan, dev(sc.texels), dev(sc.env), pts, dev(grad), sc.n_dirs,
-                               nb=nb)
+                               nb=nb, seed=sc.seed)
     torch.cuda.synchronize()
     wf = w.astype(np.float32).astype(np.float64)
     ro = oracle.shade(sc, idx, wf)
