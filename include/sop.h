@@ -556,6 +556,25 @@ sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_maps* maps,
                               void* ws, size_t ws_bytes, sop_stream stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Shading for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sop_shade with its workspace taken from a fixed
+ * device array inside the library, SOP_NOALLOC_SCRATCH_BYTES per device, held by every
+ * device that runs the library until the process ends. The caller still passes inputs and
+ * outputs. Same arguments, results and errors as sop_shade; a call whose workspace
+ * (sop_workspace_size with op SOP_OP_SHADE) exceeds the array returns
+ * SOP_ERR_WORKSPACE_TOO_SMALL before any device work (pass nb, or fewer points). The stream
+ * must belong to the current device. The first call on a device looks up that device's
+ * copy of the array once; no call allocates. Calls that overlap on one device (two streams,
+ * or two threads) share the array and race: serialise them.
+ * --------------------------------------------------------------------------------------*/
+#define SOP_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+sop_status sop_shade_noalloc(const sop_plan* plan, const sop_probe_maps* maps,
+                             const sop_envmap* env, const sop_points* pts,
+                             const sop_neighbors* nb, const sop_shade_opts* opts, float* rgb,
+                             sop_stream stream);
+
+/* ----------------------------------------------------------------------------------------
  * Misc
  * --------------------------------------------------------------------------------------*/
 const char* sop_status_string(sop_status s);

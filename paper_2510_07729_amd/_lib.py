@@ -29,6 +29,7 @@ SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL, SOP_SAMPLER_PROPOSAL_NET = 0, 1, 2
 SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
 SOP_SHADOW_HAMMERSLEY, SOP_SHADOW_ENV = 0, 1
 SOP_ENV_EQUIRECT, SOP_ENV_OCTAHEDRAL = 0, 1
+SOP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class sop_probe_set(C.Structure):
@@ -102,6 +103,8 @@ SIGNATURES = {
                           c_i32, c_i32, c_f32, c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
     "sop_shade": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
                           P(sop_neighbors), P(sop_shade_opts), c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_shade_noalloc": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
+                                  P(sop_neighbors), P(sop_shade_opts), c_vp, c_vp]),
     "sop_shade_backward": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
                                    P(sop_neighbors), P(sop_shade_opts), c_vp, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, C.c_size_t, c_vp]),

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -1385,6 +1386,64 @@ extern "C" sop_status sop_lam_loss(const float* rough, const float* metal, int64
                                 (hipStream_t)stream),
           "sop_lam_loss");
   return SOP_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// shading without allocation: the workspace is a fixed device array of this library
+// ------------------------------------------------------------------------------------------
+namespace {
+
+// Every device that runs the library holds its own copy until the process ends. In host
+// code the name below only stands in for the array: its device address (per device) comes
+// from hipGetSymbolAddress and is the only form passed to kernels.
+__device__ __align__(256) unsigned char scratch[SOP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch`, looked up once per device
+sop_status current_scratch(void** out) {
+  int dev = -1;
+  SOP_HIP(hipGetDevice(&dev), "sop_shade_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SOP_ERR_UNSUPPORTED, "sop_shade_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    SOP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)),
+            "sop_shade_noalloc: scratch address");
+    if (!p) return fail(SOP_ERR_DEVICE, "sop_shade_noalloc: scratch address is NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" sop_status sop_shade_noalloc(const sop_plan* plan, const sop_probe_maps* maps,
+                                        const sop_envmap* env, const sop_points* pts,
+                                        const sop_neighbors* nb, const sop_shade_opts* opts,
+                                        float* rgb, sop_stream stream) {
+  sop_status st = validate_shade(plan, maps, env, pts, nb, opts, true);
+  if (st != SOP_OK) return st;
+  const int32_t k = nb ? nb->k : opts->k;
+  const size_t need = ws_needed(plan, SOP_OP_SHADE, pts->count, k, nb != nullptr, opts->n_dirs,
+                                env->height, env->width);
+  if (need > (size_t)SOP_NOALLOC_SCRATCH_BYTES)
+    return fail(SOP_ERR_WORKSPACE_TOO_SMALL,
+                "sop_shade_noalloc: this call needs " + std::to_string(need) +
+                    " bytes of scratch, the fixed array holds " +
+                    std::to_string((size_t)SOP_NOALLOC_SCRATCH_BYTES) +
+                    " (pass neighbour lists or fewer points)");
+  void* ws = nullptr;
+  if ((st = current_scratch(&ws)) != SOP_OK) return st;
+  // sop_shade writes every scratch word it reads later in the same call (direction tables,
+  // neighbour-search counters are cleared by its own kernels), so the previous call's
+  // contents do not matter
+  return sop_shade(plan, maps, env, pts, nb, opts, rgb, ws, (size_t)SOP_NOALLOC_SCRATCH_BYTES,
+                   stream);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -329,6 +329,32 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
     return (rgb, irr) if irradiance else rgb
 
 
+def sop_shade_noalloc(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points,
+                      n_dirs: int, out: torch.Tensor, k: int = 4,
+                      nb: Optional[Neighbors] = None, seed: int = 0, radius: float = math.inf,
+                      rotate_per_point: bool = False,
+                      irradiance: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sop_shade into the caller's out [N,3] (and irradiance [N,3] when given) with the
+    library's fixed device scratch instead of a workspace: the call allocates nothing."""
+    n = pts.n
+    pts.check()
+    _maps_shape(texels, plan)
+    _env_shape(env)
+    _shape(out, (n, 3), "out", torch.float32)
+    _shape(irradiance, (n, 3), "irradiance", torch.float32)
+    if nb is not None:
+        nb.check(n)
+    kk = nb.k if nb is not None else k
+    o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irradiance)
+    m, e, cp = _maps(texels, plan), _env(env), pts.c()
+    nbc = nb.c(n) if nb is not None else None
+    L.check(plan._lib.sop_shade_noalloc(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+                                        C.byref(nbc) if nbc is not None else None, C.byref(o),
+                                        _ptr(out, torch.float32, "out"), _stream()),
+            "sop_shade_noalloc")
+    return out
+
+
 def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points,
                        grad_rgb: torch.Tensor, n_dirs: int, k: int = 4,
                        nb: Optional[Neighbors] = None, seed: int = 0,
