@@ -234,7 +234,10 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     return b.used;
   }
   if (op == SOP_OP_SHADE || op == SOP_OP_SHADE_BACKWARD || op == SOP_OP_DUMP_INTEGRAND) {
-    if (op == SOP_OP_SHADE) (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+    if (op == SOP_OP_SHADE) {
+      (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+      (void)b.take<double4>((size_t)n_dirs);   // directions along the hemisphere's Z curve
+    }
     (void)b.take<double4>((size_t)n_dirs);
     (void)b.take<double2>((size_t)env_w + 2);
     (void)b.take<double2>((size_t)env_h + 2);
@@ -553,6 +556,7 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   int32_t kk;
   Bump b{(char*)ws, 0, ws_bytes};
   uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
+  double4* sorted = b.take<double4>((size_t)opts->n_dirs);
   if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
@@ -574,6 +578,10 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
     a.mix_eps = opts->mix_eps;
     SOP_HIP(sopk::launch_shade_prop(a, kk, maps->format, s), "sop_shade");
   } else {
+    SOP_HIP(sopk::launch_dir_sort(opts->n_dirs, opts->seed, opts->rotate_per_point ? 1 : 0,
+                                  sorted, s),
+            "sop_shade");
+    a.dir_sorted = sorted;
     SOP_HIP(sopk::launch_shade_fwd(a, kk, maps->format, s), "sop_shade");
   }
   return SOP_OK;

@@ -3,11 +3,13 @@
 // incident light (1 - O) L_env + L_in (Eq. 8), O and L_in interpolated from the K nearest
 // probes (Eq. 9-11), and the adjoint of that estimate.
 //
-// Layout: one wavefront per shading point, lane l takes directions l, l+64, ...; the point's
-// data and its neighbour list are wave-uniform (scalar loads), the octahedral taps of a
-// direction are formed once and reused for all K probes, and the per-point sums are reduced
-// across the wavefront with DPP. The backward pass recomputes every sample instead of
-// storing per-sample fetches.
+// Layouts: the forward gives each point 8 lanes of a wavefront that take its directions in
+// the order of a Z curve over the hemisphere (k_shade_fwd_cl); the adjoint and the other
+// estimates give one wavefront to a point, lane l taking directions l, l+64, ..., with the
+// point's data and its neighbour list wave-uniform (scalar loads). The octahedral taps of a
+// direction are formed once and reused for all K probes, and per-point sums are reduced
+// across lanes. The backward pass recomputes every sample instead of storing per-sample
+// fetches.
 #include "mlp_device.hpp"
 #include "sop_device.hpp"
 #include "sop_internal.hpp"
@@ -140,6 +142,20 @@ __device__ __forceinline__ EnvTaps env_taps_of(const ShadeArgs& a, const double 
   }
 }
 
+// environment fetch of a sample whose direction (w64, w, ct) is set
+template <bool EO>
+__device__ __forceinline__ void eval_env(const ShadeArgs& a, Sample& s) {
+  s.et = env_taps_of<EO>(a, s.w64);
+  s.Le[0] = s.Le[1] = s.Le[2] = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float* e = a.env + 3 * (size_t)s.et.off[t];
+    s.Le[0] += s.et.w[t] * e[0];
+    s.Le[1] += s.et.w[t] * e[1];
+    s.Le[2] += s.et.w[t] * e[2];
+  }
+}
+
 // environment and probe fetches of a sample whose direction (w64, w, ct) is set
 template <int KT, typename TexT, bool EO = false>
 __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps,
@@ -213,27 +229,64 @@ __device__ __forceinline__ int64_t group_slot(int lane) {
   return (die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) + lane / L;
 }
 
-template <int KT, typename TexT, int L, bool EO = false>
-// three wavefronts per SIMD (at most 168 registers): the batched tap loads would otherwise
-// take the kernel to two
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd(ShadeArgs a, int32_t k) {
-  const int lane = threadIdx.x & 63, li = lane % L;
-  const int64_t slot = group_slot<L>(lane);
-  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+// Neighbour entries of a lane's point in ascending probe index (dropped entries, -1, last),
+// so that lanes of nearby points, whose lists mostly hold the same probes, read the same
+// probe at the same step. Eq. 9 is a sum over the entries: their order is free.
+template <int KT>
+__device__ __forceinline__ void order_by_probe(Neighbors<KT>& nb) {
+  if constexpr (KT > 0) {
+#pragma unroll
+    for (int pass = 0; pass < KT; ++pass)
+#pragma unroll
+      for (int i = pass & 1; i + 1 < KT; i += 2) {
+        const bool sw = (uint32_t)nb.idx[i] > (uint32_t)nb.idx[i + 1];
+        const int32_t i0 = nb.idx[i], i1 = nb.idx[i + 1];
+        const float w0 = nb.w[i], w1 = nb.w[i + 1];
+        nb.idx[i] = sw ? i1 : i0;
+        nb.idx[i + 1] = sw ? i0 : i1;
+        nb.w[i] = sw ? w1 : w0;
+        nb.w[i + 1] = sw ? w0 : w1;
+      }
+  }
+}
+
+// Shading forward in the cluster layout: a wavefront takes 8 consecutive points of the
+// processing order, 8 lanes per point, and lane q of a point takes directions q, q + 8, ...
+// of the call's direction table sorted along a Z curve over the hemisphere (dir_sorted),
+// so that at every step the 8 directions of a point are close together, and the 8 points,
+// whose normals are close (the processing order groups them by probe-grid cell) and whose
+// neighbour lists mostly coincide (ordered by probe index), look the same way. The 64 lanes'
+// taps then fall on a few texels of a few probe maps, and a gather instruction touches a
+// few cache lines instead of one per lane, which is what bounded the layouts that spread
+// one point's directions (or 64 points' same direction) over the lanes: their texture
+// units were 75-90% busy on 46-60 line lookups per gather. The sum over a point's
+// directions is order-free (Eq. 7); the 8 lanes' partial sums meet by shuffles.
+constexpr int kFwdLanes = 8;          // lanes per point (points per wavefront: 64 / kFwdLanes)
+template <int KT, typename TexT, bool EO = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd_cl(ShadeArgs a, int32_t k) {
+  constexpr int PPW = 64 / kFwdLanes;
+  const int lane = threadIdx.x & 63, q = lane % kFwdLanes;
+  const int64_t wv = die_block() * kWavesPerBlock + wave_id_uniform();
+  if (wv * PPW >= a.n) return;                          // uniform over the wavefront
+  const int64_t slot = wv * PPW + lane / kFwdLanes;
   PointState ps;
-  // lanes of a group past the end (or with an invalid order entry) skip the work but take
-  // part in the group sums
-  const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
-  if (L == 64 && !valid) return;
-  Neighbors<KT> nb;
+  const bool valid = slot < a.n && load_point<false>(a, slot, ps);
   float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
   if (valid) {
+    Neighbors<KT> nb;
     nb.load(a, ps.p, k);
-    for (int j = li; j < a.S; j += L) {
+    order_by_probe<KT>(nb);
+    const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+    for (int i = q; i < a.S; i += kFwdLanes) {
+      const double4 e = a.dir_sorted[i];
       Sample s;
-      eval_sample<KT, TexT, EO>(a, ps, nb, k, j, s);
+      const double da = e.x * ps.cr - e.y * ps.sr;
+      const double db = e.x * ps.sr + e.y * ps.cr;
+      world_dir64(ps.F, da, db, e.z, s.w64);
+      s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+      s.ct = (float)e.z;
+      eval_at<KT, TexT, EO>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
-      const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
@@ -242,26 +295,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
   }
-  float r[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc[c]) * a.scale;
-  if (valid && li == 0) {
-    a.rgb[3 * ps.p] = r[0];
-    a.rgb[3 * ps.p + 1] = r[1];
-    a.rgb[3 * ps.p + 2] = r[2];
-  }
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int o = 1; o < kFwdLanes; o <<= 1) {
+      acc[c] += __shfl_xor(acc[c], o);
+      acc_e[c] += __shfl_xor(acc_e[c], o);
+    }
+  if (!valid || q != 0) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a.rgb[3 * ps.p + c] = acc[c] * a.scale;
   if (a.irr) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[c] = group_sum<L>(acc_e[c]) * a.scale;
-    if (valid && li == 0) {
-      a.irr[3 * ps.p] = r[0];
-      a.irr[3 * ps.p + 1] = r[1];
-      a.irr[3 * ps.p + 2] = r[2];
-    }
+    for (int c = 0; c < 3; ++c) a.irr[3 * ps.p + c] = acc_e[c] * a.scale;
   }
 }
 
-// Traced shading: the estimate of k_shade_fwd with L_in and O of every sample read from its
+// Traced shading: the estimate of the shading forward with L_in and O of every sample read from its
 // traced ray (a.traced, [n,S] in the caller's point order) instead of the probes.
 template <int L, bool EO = false>
 __global__ __launch_bounds__(256) void k_shade_traced(ShadeArgs a) {
@@ -1293,32 +1343,24 @@ hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, 
   return dispatch_prop(1, a, k, format, s);
 }
 
-template <int KT, int L, bool EO>
-static void launch_fwd_le(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
-  const dim3 grid = grid_for(a.n, L);
+template <int KT, bool EO>
+static void launch_fwd_e(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  constexpr int per_block = kWavesPerBlock * (64 / kFwdLanes);
+  const dim3 grid((unsigned)((a.n + per_block - 1) / per_block));
   if (format == SOP_TEXEL_F16)
-    hipLaunchKernelGGL((k_shade_fwd<KT, uint2, L, EO>), grid, dim3(256), 0, s, a, k);
+    hipLaunchKernelGGL((k_shade_fwd_cl<KT, uint2, EO>), grid, dim3(256), 0, s, a, k);
   else
-    hipLaunchKernelGGL((k_shade_fwd<KT, float4, L, EO>), grid, dim3(256), 0, s, a, k);
-}
-
-template <int KT, int L>
-static void launch_fwd_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
-  if (a.env_oct)
-    launch_fwd_le<KT, L, true>(a, k, format, s);
-  else
-    launch_fwd_le<KT, L, false>(a, k, format, s);
+    hipLaunchKernelGGL((k_shade_fwd_cl<KT, float4, EO>), grid, dim3(256), 0, s, a, k);
 }
 
 template <int KT>
 static void launch_kt(bool fwd, const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
                       hipStream_t s) {
   if (fwd) {
-    switch (lanes_for(a.S)) {
-      case 16: launch_fwd_l<KT, 16>(a, k, format, s); break;
-      case 32: launch_fwd_l<KT, 32>(a, k, format, s); break;
-      default: launch_fwd_l<KT, 64>(a, k, format, s); break;
-    }
+    if (a.env_oct)
+      launch_fwd_e<KT, true>(a, k, format, s);
+    else
+      launch_fwd_e<KT, false>(a, k, format, s);
   } else if (a.env_oct) {
     if (format == SOP_TEXEL_F16)
       hipLaunchKernelGGL((k_shade_bwd<KT, uint2, true>), grid, dim3(256), 0, s, a, k);
@@ -1468,6 +1510,62 @@ __global__ __launch_bounds__(256) void k_dir_table(int32_t S, uint32_t rho, doub
     sincospi(((double)(j - 1) + 0.5) / (double)H, &sn, &cs);
     row_ref[j] = make_double2(cs, sn);
   }
+}
+
+// 20-bit Morton code of two 10-bit coordinates
+__device__ __forceinline__ uint32_t morton2(uint32_t x, uint32_t y) {
+  auto spread = [](uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1);
+}
+
+// The S directions of the call (dir_entry) ordered by the Z curve of their position on the
+// hemispherical octahedral square (u, v) = (x + y, x - y) / (|x| + |y| + z) at 10 bits per
+// axis, ties by index: a bitonic sort of (code << 12 | j) in one workgroup (S <= 4096).
+__global__ __launch_bounds__(1024) void k_dir_sort(int32_t S, uint32_t rho, double4* sorted) {
+  __shared__ uint32_t key[SOP_MAX_DIRS];
+  int n = 1;
+  while (n < S) n <<= 1;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    uint32_t kv = 0xFFFFFFFFu;
+    if (i < S) {
+      const double4 e = dir_entry(i, S, rho);
+      const double l1 = fabs(e.x) + fabs(e.y) + e.z;
+      const double u = (e.x + e.y) / l1, v = (e.x - e.y) / l1;
+      const uint32_t qu = (uint32_t)fmin(fmax((u + 1.0) * 512.0, 0.0), 1023.0);
+      const uint32_t qv = (uint32_t)fmin(fmax((v + 1.0) * 512.0, 0.0), 1023.0);
+      kv = (morton2(qu, qv) << 12) | (uint32_t)i;
+    }
+    key[i] = kv;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < n / 2; t += 1024) {
+        const int i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+        const uint32_t x = key[i], y = key[j];
+        if ((x > y) == ((i & size) == 0)) {
+          key[i] = y;
+          key[j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < S; i += 1024) sorted[i] = dir_entry((int)(key[i] & 0xFFFu), S, rho);
+}
+
+hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4* sorted,
+                           hipStream_t s) {
+  if (S < 1 || S > SOP_MAX_DIRS || !sorted) return hipErrorInvalidValue;
+  const uint32_t rho = per_point ? 0u : rotation24(seed, false, 0u);
+  hipLaunchKernelGGL(k_dir_sort, dim3(1), dim3(1024), 0, s, S, rho, sorted);
+  return hipGetLastError();
 }
 
 hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,

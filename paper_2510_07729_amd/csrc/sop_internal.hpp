@@ -76,6 +76,7 @@ struct ShadeArgs {
   float u_scale, v_scale;
   int32_t S;
   const double4* dir_tab;   // [S] local directions of the call (see dir_entry)
+  const double4* dir_sorted;  // [S] the same directions along a Z curve over the hemisphere
   const double2* col_ref;   // [W+2] environment column reference directions
   const double2* row_ref;   // [H+2] environment row reference directions
   float inv2S;
@@ -143,6 +144,9 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* g, int64_t n, 
 // per-call direction table: dir_entry(j, S, rho) with rho of the call (0 when per point)
 hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t H, int32_t W,
                             double4* tab, double2* col_ref, double2* row_ref, hipStream_t s);
+// the call's directions in the order of a Z curve over the hemisphere (shading forward)
+hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4* sorted,
+                           hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
@@ -194,6 +198,7 @@ struct TraceArgs {
   const float* nrm;         // [n,3]
   const int32_t* order;     // [n] processing order (a permutation) or NULL
   const double4* dir_tab;   // [S] local directions of the call (see dir_entry)
+  const double4* dir_sorted;  // [S] the same directions along a Z curve over the hemisphere
   uint32_t seed;            // direction rotation seed
   int32_t per_point;        // 1: one rotation per point
   float offset;             // ray origin fmaf(offset, n, x)

@@ -1,7 +1,8 @@
 """Register budgets of the latency-bound kernels (CPU: hipcc cross-compiles for gfx950).
 
 The bake and the shading forward run three wavefronts per SIMD; one register over the
-budget drops them to two and costs ~40% (bake) or more. These checks compile the sources
+budget drops them to two and costs ~40% (bake) or more (the forward at two wavefronts with
+its probe-union variant: 1.90 against 1.66 ms). These checks compile the sources
 to gfx950 assembly and read the register counts the compiler reports."""
 import os
 import re
@@ -43,5 +44,5 @@ def test_bake_kernel_keeps_three_wavefronts(tmp_path):
 @pytest.mark.parametrize("layout", ["Lb0E", "Lb1E"])      # equirectangular, octahedral sky
 def test_shade_forward_keeps_three_wavefronts(tmp_path, layout):
     st = kernel_stats("shade.hip", tmp_path,
-                      "_ZN4sopk11k_shade_fwdILi8E15HIP_vector_typeIfLj4EELi64E" + layout)
+                      "_ZN4sopk14k_shade_fwd_clILi8E15HIP_vector_typeIfLj4EE" + layout)
     assert st["vgpr"] <= 168 and st["occupancy"] >= 3 and st["scratch"] == 0, st
