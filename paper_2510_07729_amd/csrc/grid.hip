@@ -187,6 +187,52 @@ __global__ __launch_bounds__(256) void k_point_scatter(const int32_t* point_cell
   order[slot] = (int32_t)i;
 }
 
+// Orders the points of each grid cell by the Morton code of their lattice position inside
+// the cell (10 bits per axis), ties by point index: consecutive points of the order then
+// lie close together at the scale of a few points, not only of a cell, so a batch of them
+// shares more neighbouring probes (the adjoint adds each batch's texture gradient once per
+// distinct probe). One workgroup per cell, bitonic sort in LDS; a cell of more than
+// kRefineMax points keeps the counting sort's order. Also makes the order deterministic.
+constexpr int kRefineMax = 4096;
+__global__ __launch_bounds__(256) void k_point_refine(ProbeGrid g, const float* pts,
+                                                      const int32_t* ends, int32_t* order) {
+  __shared__ uint64_t key[kRefineMax];
+  const int32_t c = blockIdx.x;
+  const int32_t s0 = c == 0 ? 0 : ends[c - 1], s1 = ends[c];
+  const int n = s1 - s0;
+  if (n <= 1 || n > kRefineMax) return;
+  int m = 1;
+  while (m < n) m <<= 1;
+  const int fine = g.shift < 10 ? g.shift : 10;           // bits per axis inside the cell
+  const uint32_t mask = (1u << g.shift) - 1u;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    uint64_t kv = ~0ull;
+    if (i < n) {
+      const int32_t p = order[s0 + i];
+      const uint32_t qx = (uint32_t)quantize1(pts[3 * (int64_t)p], g.lo[0], g.sc) & mask;
+      const uint32_t qy = (uint32_t)quantize1(pts[3 * (int64_t)p + 1], g.lo[1], g.sc) & mask;
+      const uint32_t qz = (uint32_t)quantize1(pts[3 * (int64_t)p + 2], g.lo[2], g.sc) & mask;
+      const int sh = g.shift - fine;
+      kv = ((uint64_t)morton3(qx >> sh, qy >> sh, qz >> sh) << 32) | (uint32_t)p;
+    }
+    key[i] = kv;
+  }
+  __syncthreads();
+  for (int size = 2; size <= m; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < m / 2; t += 256) {
+        const int i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+        const uint64_t x = key[i], y = key[j];
+        if ((x > y) == ((i & size) == 0)) {
+          key[i] = y;
+          key[j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < n; i += 256) order[s0 + i] = (int32_t)(key[i] & 0xFFFFFFFFu);
+}
+
 hipError_t launch_point_order(const ProbeGrid& g, const float* pts, int64_t N,
                               int32_t* point_cell, int32_t* counts, int32_t* offsets,
                               int32_t* scan_tmp, int32_t* order, hipStream_t s) {
@@ -201,6 +247,9 @@ hipError_t launch_point_order(const ProbeGrid& g, const float* pts, int64_t N,
   if ((e = launch_exclusive_scan(counts, offsets, C, scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_point_scatter, dim3(blocks), dim3(256), 0, s, point_cell, N, offsets,
                      order);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // after the scatter offsets[c] holds the end of cell c
+  hipLaunchKernelGGL(k_point_refine, dim3((unsigned)C), dim3(256), 0, s, g, pts, offsets, order);
   return hipGetLastError();
 }
 

@@ -1085,6 +1085,97 @@ __device__ __forceinline__ void env_runs_flush(float* g_env, EnvRun* run, int la
   __builtin_amdgcn_wave_barrier();
 }
 
+// Per-wavefront LDS scratch of the batched adjoint, in 32-bit words: the staged environment
+// runs (kEnvRuns EnvRun records) and, after them, the sort of the texture splat (256 keys,
+// 64 factors, 4 x 64 tap weights) share it.
+constexpr int kScratchWords = 768;
+static_assert(kEnvRuns * (int)sizeof(EnvRun) <= kScratchWords * 4, "env runs fit the scratch");
+
+// Adds the texture adjoint of the wavefront's current samples (one per lane; valid = false
+// lanes have none) to the point's LDS map H without atomics: the 256 (tap texel, entry)
+// pairs are sorted by texel with a stable radix sort on wavefront ballots, and the first
+// entry of every run of equal texels adds the run's values (tap weight x factor, in entry
+// order) to H[texel] with a plain read-modify-write; runs hold distinct texels, so no two
+// lanes write the same word. (LDS float atomics retire at ~0.3 lanes per clock per CU on
+// this chip, an order of magnitude below plain LDS traffic.)
+__device__ __forceinline__ void splat_sorted(float* H, uint32_t* scr, int lane, bool valid,
+                                             const Sample& s, const SampleAdj& r,
+                                             uint32_t nkey, int nbits) {
+  uint32_t* buf = scr;                                            // [256] keys
+  float4* fac = reinterpret_cast<float4*>(scr + 256);             // [64] factors
+  float* wt = reinterpret_cast<float*>(scr + 512);                // [4][64] tap weights
+  fac[lane] = make_float4(r.gl[0], r.gl[1], r.gl[2], r.go);
+  uint32_t v[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    wt[t * 64 + lane] = s.tt.w[t];
+    const uint32_t key = valid ? (uint32_t)s.tt.off[t] : nkey;     // nkey sorts last
+    v[t] = (key << 8) | ((uint32_t)t << 6) | (uint32_t)lane;
+  }
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int bit = 8; bit < 8 + nbits; ++bit) {
+    uint64_t bal[4];
+    int zeros = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bal[i] = __ballot((v[i] >> bit) & 1u);
+      zeros += 64 - __popcll(bal[i]);
+    }
+    int zb = 0, ob = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool one = (v[i] >> bit) & 1u;
+      const int pos = one ? zeros + ob + __popcll(bal[i] & below) : zb + __popcll(~bal[i] & below);
+      buf[pos] = v[i];
+      const int ones = __popcll(bal[i]);
+      ob += ones;
+      zb += 64 - ones;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (bit + 1 < 8 + nbits) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = buf[i * 64 + lane];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // lane takes sorted positions 4 lane .. 4 lane + 3
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int p = 4 * lane + i;
+    uint32_t w = buf[p];
+    const uint32_t key = w >> 8;
+    if (key >= nkey) continue;
+    if (p > 0 && (buf[p - 1] >> 8) == key) continue;     // not the first of its run
+    float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int q = p;;) {
+      const uint32_t e = w & 0xFFu;
+      const float tw = wt[(e >> 6) * 64 + (e & 63u)];
+      const float4 f = fac[e & 63u];
+      acc.x += tw * f.x;
+      acc.y += tw * f.y;
+      acc.z += tw * f.z;
+      acc.w += tw * f.w;
+      if (++q >= 256) break;
+      w = buf[q];
+      if ((w >> 8) != key) break;
+    }
+    float4* h = reinterpret_cast<float4*>(H) + key;
+    float4 hv = *h;
+    hv.x += acc.x;
+    hv.y += acc.y;
+    hv.z += acc.z;
+    hv.w += acc.w;
+    *h = hv;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int KT, typename TexT, bool EO = false>
 __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a, int32_t k) {
   extern __shared__ float lds[];
@@ -1097,10 +1188,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
   int32_t* erank = uni + kMaxEntries;                   // [kMaxEntries] slot of a leader
   float* W = reinterpret_cast<float*>(erank + kMaxEntries);     // [kMaxEntries][kBatch]
   int32_t* misc = reinterpret_cast<int32_t*>(W + kMaxEntries * kBatch);  // [1]
-  // [kBatch][kEnvRuns], 16-byte aligned; indexed off the LDS array itself so that the
+  // [kBatch][kScratchWords], 16-byte aligned; indexed off the LDS array itself so that the
   // accesses stay LDS instructions (not generic ones that also wait on global memory)
-  const int run_off = (kBatch * MV + 5 * kMaxEntries + kMaxEntries * kBatch + 1 + 3) & ~3;
-  EnvRun* runs = reinterpret_cast<EnvRun*>(lds + run_off);
+  const int scr_off = (kBatch * MV + 5 * kMaxEntries + kMaxEntries * kBatch + 1 + 3) & ~3;
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -1168,26 +1258,20 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
         const float g[3] = {a.grad[3 * ps.p], a.grad[3 * ps.p + 1], a.grad[3 * ps.p + 2]};
         float ga[3] = {0.0f, 0.0f, 0.0f}, gr = 0.0f, gm = 0.0f;
         float* Hb = H + b * MV;
-        EnvRun* rb = runs + b * kEnvRuns;
+        uint32_t* scr = reinterpret_cast<uint32_t*>(lds + scr_off + b * kScratchWords);
+        EnvRun* rb = reinterpret_cast<EnvRun*>(lds + scr_off + b * kScratchWords);
+        const uint32_t nkey = (uint32_t)(a.R * a.R);           // texels per map, <= 1024
+        const int nbits = 32 - __clz((int)nkey);               // bits of keys 0 .. nkey
         for (int j0 = 0; j0 < a.S; j0 += 64) {     // uniform over the wavefront
           const int j = j0 + lane;
           Sample s;
           SampleAdj r;
-          if (j < a.S) {
-            sample_adjoint<KT, TexT, EO>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              float* dst = Hb + s.tt.off[t] * 4;
-              atomicAdd(dst + 0, s.tt.w[t] * r.gl[0]);
-              atomicAdd(dst + 1, s.tt.w[t] * r.gl[1]);
-              atomicAdd(dst + 2, s.tt.w[t] * r.gl[2]);
-              atomicAdd(dst + 3, s.tt.w[t] * r.go);
-            }
-          }
+          if (j < a.S) sample_adjoint<KT, TexT, EO>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
           if (a.g_env) {
             env_runs_flush(a.g_env, rb, lane, 0, j < a.S, s, r);
             env_runs_flush(a.g_env, rb, lane, 1, j < a.S, s, r);
           }
+          if (a.g_tex) splat_sorted(Hb, scr, lane, j < a.S, s, r, nkey, nbits);
         }
         const float v0 = wave_sum(ga[0]) * a.scale, v1 = wave_sum(ga[1]) * a.scale,
                     v2 = wave_sum(ga[2]) * a.scale;
@@ -1453,7 +1537,7 @@ hipError_t launch_shadow_ratio(const ShadeArgs& a, int32_t k, int32_t format, hi
 
 size_t batched_lds_bytes(int32_t R) {
   return (size_t)kBatch * R * R * 4 * sizeof(float) + 5 * kMaxEntries * 4 +
-         (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kEnvRuns * sizeof(EnvRun);
+         (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kScratchWords * 4;
 }
 
 template <int KT, bool EO>
