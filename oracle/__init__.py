@@ -123,6 +123,9 @@ def _sig(lib):
     lib.orc_shadow_ratio.argtypes = [C.c_long, dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr,
                                      C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr,
                                      C.POINTER(C.c_uint32)]
+    lib.orc_shade_envis.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
+                                    dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr, C.c_int,
+                                    C.c_int, u32, C.POINTER(C.c_uint32), dptr, dptr, iptr]
     lib.orc_fps.argtypes = [fptr, C.c_long, C.c_int, C.c_long, iptr]
     lib.orc_place.argtypes = [fptr, fptr, iptr, C.c_int, C.c_float, fptr]
     lib.orc_sops_loss.argtypes = [fptr, fptr, C.c_long, dptr, dptr]
@@ -515,6 +518,46 @@ def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sample
                            np.ascontiguousarray(ids, np.uint32).ctypes.data_as(
                                C.POINTER(C.c_uint32)))
     return {"ratio": ratio, "irr": irr, "texels": tx}
+
+
+def shade_envis(sc, idx, w, n_dirs=None, seed=None, ids=None, irradiance=False, texels_out=False,
+                texels=None, env=None):
+    """Relighting of a ShadeScene with environment importance sampling (Eq. 18 draws and
+    density on the octahedral environment sc.env [Re,Re,3]) instead of the Hammersley set.
+    Returns rgb [N,3] (and irradiance [N,3], and the texel of every draw [N,S])."""
+    keep = []
+
+    def d(a):
+        a2, p = _d(a)
+        keep.append(a2)
+        return p
+
+    N = sc.pos.shape[0]
+    S = sc.n_dirs if n_dirs is None else n_dirs
+    sd = sc.seed if seed is None else seed
+    envf, pe = _f(sc.env if env is None else env)
+    tex = sc.texels.astype(np.float64) if texels is None else np.asarray(texels, np.float64)
+    idx, pi = _i(idx)
+    w, pw = _d(w)
+    if sc.view is not None:
+        pv, pc, ppf = d(sc.view), None, 1
+    else:
+        pv, pc, ppf = None, d(sc.cam_pos), sc.points_per_frame
+    rgb = np.zeros((N, 3))
+    irr = np.zeros((N, 3))
+    tx = np.zeros((N, S), np.int32)
+    idp = None
+    if ids is not None:
+        ida = np.ascontiguousarray(ids, np.uint32)
+        keep.append(ida)
+        idp = ida.ctypes.data_as(C.POINTER(C.c_uint32))
+    lib().orc_shade_envis(N, d(sc.pos), d(sc.normal), pv, pc, ppf, d(sc.albedo), d(sc.rough),
+                          d(sc.metal), d(tex), tex.shape[1], pi, pw, idx.shape[1], pe,
+                          envf.shape[0], S, sd & 0xFFFFFFFF, idp, rgb.ctypes.data_as(dptr),
+                          irr.ctypes.data_as(dptr), tx.ctypes.data_as(iptr))
+    del keep
+    out = (rgb,) + ((irr,) if irradiance else ()) + ((tx,) if texels_out else ())
+    return out[0] if len(out) == 1 else out
 
 
 # ------------------------------------------------------------------------------------------

@@ -19,6 +19,11 @@
  *     normalisation read as I_t / sum(I): pdf = (m_t / C) * R^2 / (4 pi), every texel being
  *     given the mean solid angle 4 pi / R^2 (the paper's "roughly uniform texel areas").
  * Samples below the horizon add nothing to either sum. A channel with L_o = 0 has S = 1.
+ *
+ * The same draws estimate the object's relighting (Sec. 3.3: object relighting and shadow
+ * computation are both accelerated by importance sampling with the density of Eq. 18):
+ * orc_shade_envis is the shading estimate of Eq. 6-9 (the BRDF, L_i = (1 - O) L_env + L_in
+ * from the probes) with these draws and this density in place of the Hammersley set.
  */
 #include <math.h>
 #include <stdint.h>
@@ -28,6 +33,8 @@
 #define SH_MASS_BITS 14
 
 uint32_t orc_hash24(uint32_t seed, uint32_t i, uint32_t j, uint32_t k);
+void orc_brdf(const double n[3], const double v[3], const double l[3], const double a[3],
+              double r, double m, double f[3]);
 uint32_t orc_rotation24(uint32_t seed, int per_point, uint32_t point_index);
 double orc_direction(int j, int S, uint32_t rho24, const double n[3], double w[3]);
 void orc_oct_decode(double u, double v, int R, double w[3]);
@@ -136,6 +143,68 @@ void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
     for (int c = 0; c < 3; ++c) {
       ratio[3 * i + c] = den[c] != 0.0 ? num[c] / den[c] : 1.0;
       if (irr) irr[3 * i + c] = den[c] / S;
+    }
+  }
+  free(prefix);
+  free(mass);
+  free(env64);
+}
+
+/* Object relighting with environment importance sampling (Sec. 3.3, Eq. 18): for point i
+ * rgb_i = (1/S) sum_j f(w_j) L_i(w_j) (n . w_j)+ / pdf_j, with the draws w_j and densities
+ * pdf_j of orc_env_draw on the octahedral environment env [Re][Re][3] (float32: its
+ * intensities decide the masses), L_i = (1 - O) L_env + L_in (Eq. 8) with O and L_in from
+ * the probe maps tex [P][R][R][4] and the neighbours idx/wts [N][K] (Eq. 9-11), L_env the
+ * bilinear octahedral lookup, f the BRDF of the shading step (orc_brdf) for the view v
+ * (view [N][3], or cam [F][3] with ppf points per frame when view is NULL). Draws below the
+ * horizon add nothing. irr (may be NULL) = (1/S) sum_j L_i (n . w_j)+ / pdf_j; texels (may
+ * be NULL) [N][S] receives the texel of every draw; ids (may be NULL: 0..N-1) key the
+ * draws, so that a subset of a larger point set keeps its draws. */
+void orc_shade_envis(long N, const double* pos, const double* normal, const double* view,
+                     const double* cam, long ppf, const double* albedo, const double* rough,
+                     const double* metal, const double* tex, int R, const int32_t* idx,
+                     const double* wts, int K, const float* env, int Re, int S, uint32_t seed,
+                     const uint32_t* ids, double* rgb, double* irr, int32_t* texels) {
+  const int T = Re * Re;
+  double* env64 = (double*)malloc(sizeof(double) * 3 * (size_t)T);
+  for (long q = 0; q < 3L * T; ++q) env64[q] = (double)env[q];
+  uint32_t* mass = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)T);
+  uint64_t* prefix = (uint64_t*)malloc(sizeof(uint64_t) * ((size_t)T + 1));
+  orc_env_masses(env, Re, mass, prefix);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < N; ++i) {
+    const double n[3] = {normal[3 * i], normal[3 * i + 1], normal[3 * i + 2]};
+    const double a[3] = {albedo[3 * i], albedo[3 * i + 1], albedo[3 * i + 2]};
+    double v[3];
+    if (view) {
+      for (int c = 0; c < 3; ++c) v[c] = view[3 * i + c];
+    } else {
+      const long f = i / ppf;
+      for (int c = 0; c < 3; ++c) v[c] = cam[3 * f + c] - pos[3 * i + c];
+      const double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      for (int c = 0; c < 3; ++c) v[c] /= l;
+    }
+    const uint32_t id = ids ? ids[i] : (uint32_t)i;
+    double acc[3] = {0, 0, 0}, acc_e[3] = {0, 0, 0};
+    for (int j = 0; j < S; ++j) {
+      double w[3], pdf;
+      const int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, w, &pdf);
+      if (texels) texels[i * S + j] = t;
+      const double ct = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+      if (!(ct > 0.0)) continue;
+      double E[3], Lin[3], O, f[3];
+      orc_oct_fetch(env64, Re, 3, w, E);
+      orc_interp(tex, R, idx + i * K, wts + i * K, K, w, Lin, &O);
+      orc_brdf(n, v, w, a, rough[i], metal[i], f);
+      for (int c = 0; c < 3; ++c) {
+        const double Li = (1.0 - O) * E[c] + Lin[c];
+        acc[c] += f[c] * Li * ct / pdf;
+        acc_e[c] += Li * ct / pdf;
+      }
+    }
+    for (int c = 0; c < 3; ++c) {
+      rgb[3 * i + c] = acc[c] / S;
+      if (irr) irr[3 * i + c] = acc_e[c] / S;
     }
   }
   free(prefix);
