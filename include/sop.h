@@ -200,8 +200,11 @@ sop_status sop_query(const sop_plan* plan, const sop_probe_maps* maps, const sop
 typedef enum sop_sampler {
   SOP_SAMPLER_HAMMERSLEY = 0,     /* uniform hemisphere Hammersley set (Eq. 7)              */
   SOP_SAMPLER_PROPOSAL = 1,       /* per-point bin distributions given in opts.probs        */
-  SOP_SAMPLER_PROPOSAL_NET = 2    /* bin distributions of the network opts.net, evaluated
+  SOP_SAMPLER_PROPOSAL_NET = 2,   /* bin distributions of the network opts.net, evaluated
                                      inside the shading call (they never reach memory)     */
+  SOP_SAMPLER_ENV = 3             /* environment importance sampling (Eq. 18) on an
+                                     octahedral env: the draws and density of
+                                     SOP_SHADOW_ENV (see sop_shadow_ratio)                  */
 } sop_sampler;
 
 typedef struct sop_mlp sop_mlp;
@@ -231,7 +234,12 @@ typedef struct sop_shade_opts {
  * sop_proposal_infer's output up to the order of the per-point sums. The proposal samplers
  * have no adjoint: sop_shade_backward accepts only SOP_SAMPLER_HAMMERSLEY. The proposal
  * samplers (and sop_dump_integrand) take an equirectangular env only
- * (SOP_ERR_UNSUPPORTED for SOP_ENV_OCTAHEDRAL). */
+ * (SOP_ERR_UNSUPPORTED for SOP_ENV_OCTAHEDRAL). With SOP_SAMPLER_ENV (object relighting by
+ * importance sampling, Sec. 3.3) the env must be SOP_ENV_OCTAHEDRAL (else
+ * SOP_ERR_UNSUPPORTED); draw j of point i (its index in pts) is the draw of the
+ * SOP_SHADOW_ENV sampler with density pdf_j = (m_t / C) R_e^2 / (4 pi), and
+ * rgb_i = (1/S) sum_j f L_i (n . w_j)+ / pdf_j, out_irradiance (1/S) sum_j L_i (n . w_j)+ /
+ * pdf_j; draws below the horizon add nothing. It has no adjoint either. */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
                      const sop_points* pts, const sop_neighbors* nb,
                      const sop_shade_opts* opts, float* rgb,

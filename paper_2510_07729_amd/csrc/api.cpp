@@ -224,6 +224,24 @@ NbScratch carve_nb(Bump& b, int64_t N, int32_t k) {
   return s;
 }
 
+// texel masses, their prefix sums and scan scratch of an environment of T texels (the
+// environment importance sampler)
+struct EnvCdf {
+  uint32_t* mass;
+  uint64_t* prefix;
+  uint64_t* tiles;
+  float* imax;
+};
+
+EnvCdf carve_env_cdf(Bump& b, size_t T) {
+  EnvCdf c;
+  c.mass = b.take<uint32_t>(T);
+  c.prefix = b.take<uint64_t>(T + 1);
+  c.tiles = b.take<uint64_t>((T + 1023) / 1024 + 1);
+  c.imax = b.take<float>(1);
+  return c;
+}
+
 // Workspace layout: [direction table (shade ops)] [order, idx, w] [search scratch]
 size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool with_nb,
                  int32_t n_dirs, int32_t env_h = 0, int32_t env_w = 0) {
@@ -237,6 +255,7 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     if (op == SOP_OP_SHADE) {
       (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
       (void)b.take<double4>((size_t)n_dirs);   // directions along the hemisphere's Z curve
+      carve_env_cdf(b, (size_t)env_h * (size_t)env_w);   // environment sampler
     }
     (void)b.take<double4>((size_t)n_dirs);
     (void)b.take<double2>((size_t)env_w + 2);
@@ -477,6 +496,9 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
   }
   if (o->n_dirs < 1 || o->n_dirs > SOP_MAX_DIRS)
     return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
+  if ((o->sampler == SOP_SAMPLER_PROPOSAL || o->sampler == SOP_SAMPLER_PROPOSAL_NET) &&
+      env->layout == SOP_ENV_OCTAHEDRAL && allow_proposal)
+    return fail(SOP_ERR_UNSUPPORTED, "the proposal samplers take an equirectangular env");
   if (o->sampler == SOP_SAMPLER_PROPOSAL) {
     if (!allow_proposal)
       return fail(SOP_ERR_UNSUPPORTED, "the proposal sampler has no adjoint");
@@ -496,6 +518,11 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
         return fail(SOP_ERR_INVALID_ARGUMENT, "net bounds must be finite with hi > lo");
     if (!(o->mix_eps >= 0.0f && o->mix_eps <= 1.0f))
       return fail(SOP_ERR_INVALID_ARGUMENT, "mix_eps out of [0, 1]");
+  } else if (o->sampler == SOP_SAMPLER_ENV) {
+    if (!allow_proposal)
+      return fail(SOP_ERR_UNSUPPORTED, "the environment sampler has no adjoint");
+    if (env->layout != SOP_ENV_OCTAHEDRAL)
+      return fail(SOP_ERR_UNSUPPORTED, "the environment sampler takes an octahedral env");
   } else if (o->sampler != SOP_SAMPLER_HAMMERSLEY) {
     return fail(SOP_ERR_UNSUPPORTED, "unknown sampler");
   }
@@ -557,12 +584,11 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
   Bump b{(char*)ws, 0, ws_bytes};
   uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
   double4* sorted = b.take<double4>((size_t)opts->n_dirs);
+  const EnvCdf cdf = carve_env_cdf(b, (size_t)env->height * (size_t)env->width);
   if ((st = setup_dirs(a, b, opts, s)) != SOP_OK) return st;
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
-  if (opts->sampler != SOP_SAMPLER_HAMMERSLEY && a.env_oct)
-    return fail(SOP_ERR_UNSUPPORTED, "the proposal samplers take an equirectangular env");
   if (opts->sampler == SOP_SAMPLER_PROPOSAL_NET) {
     a.mix_eps = opts->mix_eps;
     a.mlp_params = opts->net->params;
@@ -577,6 +603,14 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
     a.probs = opts->probs;
     a.mix_eps = opts->mix_eps;
     SOP_HIP(sopk::launch_shade_prop(a, kk, maps->format, s), "sop_shade");
+  } else if (opts->sampler == SOP_SAMPLER_ENV) {
+    a.env_res = env->width;
+    a.env_mass = cdf.mass;
+    a.env_prefix = cdf.prefix;
+    SOP_HIP(sopk::launch_env_cdf(env->texels, env->width * env->height, cdf.mass, cdf.prefix,
+                                 cdf.tiles, cdf.imax, s),
+            "sop_shade");
+    SOP_HIP(sopk::launch_shade_envis(a, kk, maps->format, s), "sop_shade");
   } else {
     SOP_HIP(sopk::launch_dir_sort(opts->n_dirs, opts->seed, opts->rotate_per_point ? 1 : 0,
                                   sorted, s),

@@ -563,6 +563,79 @@ __global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Object relighting with environment importance sampling (Sec. 3.3: relighting and shadows
+// are both estimated with the density of Eq. 18): the shading estimate of Eq. 6-9 with the
+// draws of the cast-shadow ratio's Eq. 18 sampler on an octahedral environment,
+// rgb = (1/S) sum_j f L_i cos+ / pdf_j with pdf_j = (m_t / C) R_e^2 / (4 pi); draws below
+// the horizon add nothing. L lanes per point (64/L points per wavefront), lane l of a point
+// taking draws l, l + L, ...
+// ------------------------------------------------------------------------------------------
+template <int KT, typename TexT, int L>
+__global__ __launch_bounds__(256) void k_shade_envis(ShadeArgs a, int32_t k) {
+  const int lane = threadIdx.x & 63, li = lane % L;
+  if ((die_block() * kWavesPerBlock + wave_id_uniform()) * (64 / L) >= a.n) return;
+  const int64_t slot = group_slot<L>(lane);
+  PointState ps;
+  const bool valid = slot < a.n && load_point<L == 64>(a, slot, ps);
+  if (L == 64 && !valid) return;
+  float acc[3] = {0.0f, 0.0f, 0.0f}, acc_e[3] = {0.0f, 0.0f, 0.0f};
+  if (valid) {
+    Neighbors<KT> nb;
+    nb.load(a, ps.p, k);
+    const int32_t Re = a.env_res, T = Re * Re;
+    const uint64_t C = a.env_prefix[T];
+    const uint32_t sh = pcg_hash(a.seed), pi = (uint32_t)ps.p;
+    const float al[3] = {ps.M.a.x, ps.M.a.y, ps.M.a.z};
+    for (int j = li; j < a.S; j += L) {
+      // the j-th of S slices of the mass line, then the texel whose stretch holds x
+      const uint64_t r = hash24(sh, pi, (uint32_t)j, 0);
+      const uint64_t x = ((uint64_t)j * C + ((r * C) >> 24)) / (uint64_t)a.S;
+      int lo = 0, hi = T;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.env_prefix[mid] <= x) lo = mid; else hi = mid;
+      }
+      const double xu = ((double)hash24(sh, pi, (uint32_t)j, 1) + 0.5) * 0x1p-24;
+      const double xv = ((double)hash24(sh, pi, (uint32_t)j, 2) + 0.5) * 0x1p-24;
+      Sample s;
+      oct_decode64((double)(lo % Re) + xu, (double)(lo / Re) + xv, Re, s.w64);
+      const double cd = s.w64[0] * ps.n64[0] + s.w64[1] * ps.n64[1] + s.w64[2] * ps.n64[2];
+      if (!(cd > 0.0)) continue;
+      s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
+      s.ct = (float)cd;
+      eval_at<KT, TexT, true>(a, ps, nb, k, s);
+      // 1 / pdf = 4 pi C / (m_t T)
+      const float wt = (float)(12.566370614359172 * (double)C / ((double)a.env_mass[lo] * (double)T));
+      const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
+        acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li * wt;
+        acc_e[c] += Li * s.ct * wt;
+      }
+    }
+  }
+  const float scale = 1.0f / (float)a.S;
+  float r3[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r3[c] = group_sum<L>(acc[c]) * scale;
+  if (valid && li == 0) {
+    a.rgb[3 * ps.p] = r3[0];
+    a.rgb[3 * ps.p + 1] = r3[1];
+    a.rgb[3 * ps.p + 2] = r3[2];
+  }
+  if (a.irr) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r3[c] = group_sum<L>(acc_e[c]) * scale;
+    if (valid && li == 0) {
+      a.irr[3 * ps.p] = r3[0];
+      a.irr[3 * ps.p + 1] = r3[1];
+      a.irr[3 * ps.p + 2] = r3[2];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Learned direction proposal: importance-sampled estimate of Eq. 7. Directions are drawn
 // from 16x16 bins over the hemispherical octahedral square of the local frame,
 // (u,v) = (x+y, x-y)/(|x|+|y|+z), with integer bin masses (decided in IEEE single
@@ -1502,6 +1575,35 @@ hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t*
                      tile_tmp);
   hipLaunchKernelGGL(k_env_tile_scan, dim3(1), dim3(1024), 0, s, ntiles, tile_tmp, prefix, T);
   hipLaunchKernelGGL(k_env_add, dim3(ntiles), dim3(1024), 0, s, T, tile_tmp, prefix);
+  return hipGetLastError();
+}
+
+template <int KT, int L>
+static void launch_envis_l(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  const dim3 grid = grid_for(a.n, L);
+  if (format == SOP_TEXEL_F16)
+    hipLaunchKernelGGL((k_shade_envis<KT, uint2, L>), grid, dim3(256), 0, s, a, k);
+  else
+    hipLaunchKernelGGL((k_shade_envis<KT, float4, L>), grid, dim3(256), 0, s, a, k);
+}
+
+template <int KT>
+static void launch_envis_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  switch (lanes_for(a.S)) {
+    case 16: launch_envis_l<KT, 16>(a, k, format, s); break;
+    case 32: launch_envis_l<KT, 32>(a, k, format, s); break;
+    default: launch_envis_l<KT, 64>(a, k, format, s); break;
+  }
+}
+
+hipError_t launch_shade_envis(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  if (!a.env_mass || !a.env_prefix || !a.env_oct) return hipErrorInvalidValue;
+  switch (k) {
+    case 4: launch_envis_kt<4>(a, k, format, s); break;
+    case 8: launch_envis_kt<8>(a, k, format, s); break;
+    default: launch_envis_kt<0>(a, k, format, s); break;
+  }
   return hipGetLastError();
 }
 

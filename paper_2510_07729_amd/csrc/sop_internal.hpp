@@ -155,6 +155,8 @@ hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, 
 // texels]; tile_tmp holds ceil(T/1024) values, imax one
 hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t* prefix,
                           uint64_t* tile_tmp, float* imax, hipStream_t s);
+// relighting with environment importance sampling (a.env octahedral, a.env_mass/prefix)
+hipError_t launch_shade_envis(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // ratio [n,3] in a.rgb (optional unshadowed estimate in a.irr)
 hipError_t launch_shadow_ratio(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // traced shading: the estimate of launch_shade_fwd with a.traced for L_in and O
