@@ -3,12 +3,15 @@
 One step = one pass of the whole path over the object workload: rebuild the probe grid,
 re-register the 100k Gaussians in the bake grid and bake 4096 probes at 32x32 (4.19M rays,
 probes traced in the probe grid's Morton order), order the 200k shading points and find
-their 8 nearest probes, shade them with 128 directions (forward) and run the adjoint (backward) into the probe and environment
-gradients; then run the proposal network on the 200k points, shade them again with 32
-directions drawn from its bin distributions, and take one proposal training step (fresh
-bin targets for 4096 points + Adam). value = shaded point-direction samples (N*S, S = 128) per second of the
-whole step. After the timed region, the learned proposal's speedup at matched error is
-measured on the tiny scene's geometry (see proposal_study).
+their 8 nearest probes, shade them with 128 directions (forward) and run the adjoint
+(backward) into the probe and environment gradients; then run the proposal network on the
+200k points, shade them again with 32 directions drawn from its bin distributions, and take
+one proposal training step (fresh bin targets for 4096 points + Adam). value = the metric's
+shaded point-direction samples per second forward + backward, N*S / (t_fwd + t_bwd) with
+S = 128 and the two kernels' times measured inside the step; the whole step's rate is
+reported next to it. After the timed region: the G-buffer frames workload (16.6M points),
+the learned proposal's speedup at matched error (as the workload states it and the online
+variant), and the studies of the rows after the hot path.
 
 Prints ONE JSON line. Per-kernel durations are measured with HIP events on the stream the
 kernels run on; algorithmic flop counts per sample are documented below.
@@ -73,6 +76,12 @@ def main() -> int:
     ap.add_argument("--no-shadow-study", action="store_true")
     ap.add_argument("--no-place-study", action="store_true")
     ap.add_argument("--no-env-study", action="store_true")
+    ap.add_argument("--no-frames-study", action="store_true")
+    ap.add_argument("--no-envis-study", action="store_true")
+    ap.add_argument("--frames-only", action="store_true",
+                    help="only the G-buffer frames forward (16.6M points, f16 maps, S=64, "
+                         "K=8; 1 warm-up + 3 timed calls; for kernel traces of that path)")
+
     ap.add_argument("--place-only", action="store_true",
                     help="only probe placement and the losses of the object workload (for "
                          "kernel traces of that path)")
@@ -104,6 +113,10 @@ def main() -> int:
         return trace_only(torch, dev, sop, scenes)
     if args.shadow_only:
         return shadow_only(torch, dev, sop, scenes)
+    if args.frames_only:
+        print(json.dumps(frames_study(torch, dev, sop, scenes, reps=3)), flush=True)
+        return 0
+
     if args.place_only:
         import numpy as np
         tex = torch.from_numpy(scenes.probe_textures(scenes.rng(scenes.CFG_OBJECT, 1, 0), 4096,
@@ -236,8 +249,9 @@ def main() -> int:
           file=sys.stderr, flush=True)
 
     samples = N * S
-    value = samples / (ms_per_step * 1e-3)
-    fb_rate = samples / ((phase["shade_fwd"] + phase["shade_bwd"]) * 1e-3)
+    # the metric: samples per second of the shading forward + backward
+    value = samples / ((phase["shade_fwd"] + phase["shade_bwd"]) * 1e-3)
+    step_rate = samples / (ms_per_step * 1e-3)
 
     # roofline of the dominant kernel (each phase is one kernel launch except bake_grid)
     dom = max(("shade_fwd", "shade_bwd", "bake"), key=lambda n: phase[n])
@@ -260,16 +274,17 @@ def main() -> int:
             roof["valu_issue_frac"] = issue
     else:
         f = flops_fwd(K) if dom == "shade_fwd" else flops_bwd(K)
+        kern = "k_shade_fwd_cl" if dom == "shade_fwd" else "k_shade_bwd_batched"
         achieved = samples * f / (phase[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": "k_" + dom, "achieved": round(achieved, 3),
+        roof = {"bound": "alu", "kernel": kern, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic("k_" + dom),
+                "traffic": measured_traffic(kern),
                 "flops_per_unit": f, "units_per_launch": samples,
                 "unit_def": "shaded point-direction sample", "launch_ms": round(phase[dom], 4)}
     # the shading kernels' own figures (the metric's fwd+bwd rate)
     shade_roof = {}
-    for n, f, kern in (("shade_fwd", flops_fwd(K), "k_shade_fwd"),
+    for n, f, kern in (("shade_fwd", flops_fwd(K), "k_shade_fwd_cl"),
                        ("shade_bwd", flops_bwd(K), "k_shade_bwd_batched")):
         a = samples * f / (phase[n] * 1e-3) / 1e12
         shade_roof[n] = {"achieved_tflops": round(a, 3), "frac": round(a / PEAK_FP32_TFLOPS, 4),
@@ -338,10 +353,24 @@ def main() -> int:
         place = place_study(torch, sop, scenes, time_ms, tex)
         print(f"# place study: {json.dumps(place)}", file=sys.stderr, flush=True)
 
-    study = None
+    frames = None
+    if not args.no_frames_study:
+        frames = frames_study(torch, dev, sop, scenes)
+        print(f"# frames study: {json.dumps(frames)}", file=sys.stderr, flush=True)
+
+    envis = None
+    if not args.no_envis_study:
+        envis = envis_study(torch, sop, scenes, time_ms, plan, tex, pts, nb_p, S, K,
+                            phase["shade_fwd"])
+        print(f"# envis study: {json.dumps(envis)}", file=sys.stderr, flush=True)
+
+    study = study_written = None
     if not args.no_proposal_study:
+        study_written = proposal_study_written(torch, dev)
+        print(f"# proposal study (as the workload states it): {json.dumps(study_written)}",
+              file=sys.stderr, flush=True)
         study = proposal_study(torch, dev, args.proposal_steps)
-        print(f"# proposal study: {json.dumps(study)}", file=sys.stderr, flush=True)
+        print(f"# proposal study (online): {json.dumps(study)}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -358,12 +387,16 @@ def main() -> int:
                                "points, proposal shade x 32 directions, one proposal "
                                "training step (4096 points)",
                    "points": N, "dirs": S, "k": K, "probes": P, "res": R, "gaussians": G},
-        "fwd_bwd_samples_per_s": round(fb_rate, 1),
+        "value_def": "N*S / (t_shade_fwd + t_shade_bwd), both kernels timed inside the step",
+        "step_samples_per_s": round(step_rate, 1),
         "phase_ms": {k: round(v, 4) for k, v in phase.items()},
         "roofline": roof,
         "shade_roofline": shade_roof,
         "proposal_paths": proposal_paths,
+        "frames_study": frames,
+        "proposal_study_as_written": study_written,
         "proposal_study": study,
+        "envis_study": envis,
         "trace_study": trace,
         "shadow_study": shadow,
         "place_study": place,
@@ -374,47 +407,14 @@ def main() -> int:
     return 0
 
 
-def proposal_study(torch, dev, steps: int) -> dict:
-    """Speedup at matched error of the learned proposal on the tiny scene's geometry (64
-    probes with 16x16 maps, 32x64 environment, K=4): online training on a pool of 262,144
-    points, then 200k held-out points shaded with the fixed Hammersley set (the paper's
-    estimator) and with proposal samples, each against a 4096-direction Hammersley reference.
-    RMSE is taken over the points with roughness >= 0.25, whose lobes the reference itself
-    resolves (narrower lobes are not converged by 4096 uniform directions either). S* is the
-    smallest proposal count whose RMSE reaches the Hammersley RMSE at 128 directions;
-    speedup = t(Hammersley 128) / min(t(network) + t(proposal S*), t(fused S*)), where the
-    fused call runs the network inside the shading kernel (same draws); both are reported."""
-    import numpy as np
-
-    from paper_2510_07729_amd import _lib as L
-    from paper_2510_07729_amd import proposal, scenes, sop
-    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
-
-    def pts_of(sc):
-        return sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
-                          view=d(sc.view))
-
-    pool_sc = scenes.proposal_eval(262_144, seed=5)
-    ev_sc = scenes.proposal_eval(200_000, seed=0)
-    plan = sop.Plan(d(pool_sc.probe_pos), pool_sc.bounds_lo, pool_sc.bounds_hi)
-    tex, env = d(pool_sc.texels), d(pool_sc.env)
-    pool, ev = pts_of(pool_sc), pts_of(ev_sc)
-    mlp = proposal.default_mlp(dev, pool_sc.bounds_lo, pool_sc.bounds_hi, seed=0)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    losses = proposal.train(mlp, plan, tex, env, pool, steps, batch=TRAIN_BATCH, lr=2e-3,
-                            log_every=max(1, steps // 4))
-    e1.record()
-    torch.cuda.synchronize()
-    train_ms = e0.elapsed_time(e1)
-
-    nb = sop.sop_knn(plan, ev, 4)
-    ref = sop.sop_shade(plan, tex, env, ev, 4096, nb=nb, seed=123)
-    mask = ev.rough >= 0.25
-
+def _proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, mask) -> dict:
+    """Hammersley and proposal estimates of the points `ev` against the reference `ref`:
+    RMSE (over `mask`, or all points when None) and time per call at each direction count,
+    S* = the fewest proposal directions whose RMSE reaches the Hammersley RMSE at 128, and
+    the speedup t(Hammersley 128) / min(t(network) + t(proposal S*), t(fused S*))."""
     def rmse(x):
-        return float(torch.sqrt(torch.mean(((x - ref)[mask]) ** 2)))
+        d = (x - ref) if mask is None else (x - ref)[mask]
+        return float(torch.sqrt(torch.mean(d ** 2)))
 
     def timed(fn, reps=10):
         out = fn()
@@ -446,17 +446,212 @@ def proposal_study(torch, dev, steps: int) -> dict:
     t_two = (t_mlp + prop[s_star]["ms"]) if s_star else None
     best = min(t_two, t_fused) if s_star else None
     speedup = (ham[128]["ms"] / best) if s_star else None
-    return {"workload": "tiny scene geometry, 200k held-out points, K=4, RMSE over "
-                        "roughness >= 0.25 against 4096 Hammersley directions",
-            "train_steps": steps, "train_batch": TRAIN_BATCH,
-            "train_integrand_samples": proposal.integrand_samples(steps, TRAIN_BATCH),
-            "train_ms": round(train_ms, 1), "loss_trace": [round(x, 4) for x in losses],
-            "mix_eps": MIX_EPS, "hammersley": ham, "proposal": prop,
-            "network_ms": round(t_mlp, 4), "S_star": s_star,
+    return {"hammersley": ham, "proposal": prop, "network_ms": round(t_mlp, 4),
+            "S_star": s_star,
             "speedup_vs_hammersley_128": round(speedup, 3) if speedup else None,
             "speedup_path": ("fused" if t_fused < t_two else "two_call") if s_star else None,
             "two_call_ms_at_S_star": round(t_two, 4) if s_star else None,
             "fused_ms_at_S_star": round(t_fused, 4)}
+
+
+def _reference_spot_check(torch, ev_sc, ref, n_dirs=4096, n_check=1000, seed=123) -> dict:
+    """The GPU reference estimate (Hammersley, n_dirs directions) against the oracle on
+    n_check sampled points: max and 99.9th percentile of the relative error (floored at
+    1e-3 of the mean, as the parity tests measure)."""
+    import numpy as np
+
+    import oracle
+    rows = np.sort(np.random.default_rng(41).choice(ev_sc.n, n_check, replace=False))
+    sub = ev_sc.subset(rows)
+    idx, w = oracle.knn(sub.probe_pos, sub.bounds_lo, sub.bounds_hi, sub.pos, sub.normal,
+                        sub.k)
+    ro = oracle.shade(sub, idx, w, n_dirs=n_dirs, seed=seed)
+    g = ref.cpu().numpy()[rows].astype(np.float64)
+    tau = 1e-3 * float(np.mean(np.abs(ro)))
+    err = np.abs(g - ro) / np.maximum(np.abs(ro), tau)
+    return {"points": n_check, "dirs": n_dirs, "max_rel_err": float(f"{err.max():.3e}"),
+            "p99_9_rel_err": float(f"{np.percentile(err, 99.9):.3e}")}
+
+
+def proposal_study_written(torch, dev, train_steps: int = 3000) -> dict:
+    """The learned-proposal workload as stated: the network is trained on 2,097,152
+    integrand samples of the tiny scene (4096 points x 512 directions, two per bin, dumped
+    once), then 200k held-out points are shaded with the Hammersley set and with proposal
+    samples; RMSE over all points and RGB against the 4096-direction Hammersley estimate,
+    which is itself spot-checked against the oracle on 1000 points."""
+    import numpy as np
+
+    from paper_2510_07729_amd import proposal, scenes, sop
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+
+    def pts_of(sc):
+        return sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                          view=d(sc.view))
+
+    train_sc = scenes.proposal_eval(TRAIN_BATCH, seed=5)
+    ev_sc = scenes.proposal_eval(200_000, seed=0)
+    plan = sop.Plan(d(train_sc.probe_pos), train_sc.bounds_lo, train_sc.bounds_hi)
+    tex, env = d(train_sc.texels), d(train_sc.env)
+    tr, ev = pts_of(train_sc), pts_of(ev_sc)
+    mlp = proposal.default_mlp(dev, train_sc.bounds_lo, train_sc.bounds_hi, seed=0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    losses = proposal.train_fixed(mlp, plan, tex, env, tr, train_steps, samples_per_bin=2,
+                                  lr=2e-3, log_every=max(1, train_steps // 4))
+    e1.record()
+    torch.cuda.synchronize()
+    nb = sop.sop_knn(plan, ev, 4)
+    ref = sop.sop_shade(plan, tex, env, ev, 4096, nb=nb, seed=123)
+    masked = _proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, ev.rough >= 0.25)
+    out = {"workload": "tiny scene geometry; trained on 4096 points x 512 directions "
+                       "(2,097,152 integrand samples, dumped once); 200k held-out points, "
+                       "K=4, RMSE over all points and RGB against 4096 Hammersley directions",
+           "train_integrand_samples": TRAIN_BATCH * 512, "train_steps": train_steps,
+           "train_ms": round(e0.elapsed_time(e1), 1),
+           "loss_trace": [round(x, 4) for x in losses], "mix_eps": MIX_EPS}
+    out.update(_proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, None))
+    # the same network judged over the points whose lobes the reference resolves
+    out["roughness_ge_0.25"] = {k: masked[k] for k in ("hammersley", "proposal", "S_star",
+                                                        "speedup_vs_hammersley_128")}
+    out["reference_vs_oracle"] = _reference_spot_check(torch, ev_sc, ref)
+    return out
+
+
+def proposal_study(torch, dev, steps: int) -> dict:
+    """Speedup at matched error of the learned proposal on the tiny scene's geometry (64
+    probes with 16x16 maps, 32x64 environment, K=4), online variant: training on a pool of
+    262,144 points with fresh targets every step, then 200k held-out points shaded with the
+    fixed Hammersley set and with proposal samples, each against a 4096-direction Hammersley
+    reference. RMSE is taken over the points with roughness >= 0.25, whose lobes the
+    reference itself resolves (narrower lobes are not converged by 4096 uniform directions
+    either)."""
+    import numpy as np
+
+    from paper_2510_07729_amd import proposal, scenes, sop
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+
+    def pts_of(sc):
+        return sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                          view=d(sc.view))
+
+    pool_sc = scenes.proposal_eval(262_144, seed=5)
+    ev_sc = scenes.proposal_eval(200_000, seed=0)
+    plan = sop.Plan(d(pool_sc.probe_pos), pool_sc.bounds_lo, pool_sc.bounds_hi)
+    tex, env = d(pool_sc.texels), d(pool_sc.env)
+    pool, ev = pts_of(pool_sc), pts_of(ev_sc)
+    mlp = proposal.default_mlp(dev, pool_sc.bounds_lo, pool_sc.bounds_hi, seed=0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    losses = proposal.train(mlp, plan, tex, env, pool, steps, batch=TRAIN_BATCH, lr=2e-3,
+                            log_every=max(1, steps // 4))
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+
+    nb = sop.sop_knn(plan, ev, 4)
+    ref = sop.sop_shade(plan, tex, env, ev, 4096, nb=nb, seed=123)
+    out = {"workload": "tiny scene geometry, 200k held-out points, K=4, RMSE over "
+                       "roughness >= 0.25 against 4096 Hammersley directions",
+           "train_steps": steps, "train_batch": TRAIN_BATCH,
+           "train_integrand_samples": proposal.integrand_samples(steps, TRAIN_BATCH),
+           "train_ms": round(train_ms, 1), "loss_trace": [round(x, 4) for x in losses],
+           "mix_eps": MIX_EPS}
+    out.update(_proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, ev.rough >= 0.25))
+    return out
+
+
+def frames_study(torch, dev, sop, scenes, reps=10) -> dict:
+    """The G-buffer frames workload: 8 frames of 1920x1080 (16,588,800 points, views from
+    the frames' cameras), 16,384 probes with 32x32 f16 maps, S = 64, K = 8, 256x512
+    environment: one forward call over all frames with the neighbour lists given, timed with
+    events, its samples per second and its share of the FP32 roof."""
+    import numpy as np
+    from paper_2510_07729_amd import _lib as L
+    t0 = time.time()
+    sc = scenes.gbuffer_frames()
+    build_s = time.time() - t0
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    N, S, K = sc.n, sc.n_dirs, sc.k
+    pts = sop.Points(d(sc.pos), d(sc.normal), d(sc.albedo), d(sc.rough), d(sc.metal),
+                     cam_pos=d(sc.cam_pos), points_per_frame=sc.points_per_frame)
+    plan = sop.Plan(d(sc.probe_pos), sc.bounds_lo, sc.bounds_hi)
+    tex, env = d(sc.texels), d(sc.env)
+    del sc
+    t_knn = time_ms_plain(lambda: sop.sop_knn(plan, pts, K), reps=3)
+    nb = sop.sop_knn(plan, pts, K)
+    out = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    ws = sop.workspace(plan.workspace_size(L.SOP_OP_SHADE, N, K, S, env.shape[:2], True), dev)
+    t = time_ms_plain(lambda: sop.sop_shade(plan, tex, env, pts, S, nb=nb, ws=ws, out=out),
+                      reps=reps)
+    assert bool(torch.isfinite(out).all()), "non-finite frames output"
+    samples = N * S
+    ach = samples * flops_fwd(K) / (t * 1e-3) / 1e12
+    res = {"workload": "8 frames x 1920x1080 G-buffers (16,588,800 points, camera views), "
+                       "16,384 probes with 32x32 f16 maps, S=64, K=8, env 256x512",
+           "points": N, "dirs": S, "k": K, "build_s": round(build_s, 1),
+           "knn_ms": round(t_knn, 3), "shade_fwd_ms": round(t, 3),
+           "samples_per_s": round(samples / (t * 1e-3), 1),
+           "frames_per_s": round(8 / (t * 1e-3), 2),
+           "roofline": {"bound": "alu", "kernel": "k_shade_fwd_cl", "achieved": round(ach, 3),
+                        "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                        "flops_per_unit": flops_fwd(K), "units_per_launch": samples}}
+    hb = measured_traffic("k_shade_fwd_cl", "frames")
+    if hb is not None:
+        bw = hb / (t * 1e-3) / 1e9
+        res["roofline"]["traffic"] = round(hb)
+        res["hbm_GBps"] = round(bw, 1)
+        res["hbm_frac"] = round(bw / PEAK_HBM_GBS, 4)
+    return res
+
+
+def envis_study(torch, sop, scenes, time_ms, plan, tex, pts, nb, S, K, t_fwd_equirect,
+                subset=4096, S_ref=4096) -> dict:
+    """Object relighting with environment importance sampling (Eq. 18) against the
+    Hammersley set on the object workload, under a 256x256 octahedral outdoor sky whose sun
+    holds ~70% of the energy: the time of each at the step's S on all points, and their
+    relative RMSE of the irradiance output (the cosine-weighted incident light; rgb errors
+    of uniform sampling are dominated by rare hits of narrow GGX lobes on the sun) against a
+    Hammersley estimate at S_ref directions on `subset` points; S* = the fewest importance
+    samples whose error is at most the Hammersley error at S. The importance estimate weights each draw with the paper's mean-solid-angle
+    density, so it converges to 4 pi times the mean of the integrand over the octahedral
+    square, not to the integral: its error levels off at that bias."""
+    import numpy as np
+    dev = pts.pos.device
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
+    sky = sop.OctEnv(d(scenes.octahedral_sky(np.random.default_rng(9), 256)))
+    sub = sop.Points(pts.pos[:subset], pts.normal[:subset], pts.albedo[:subset],
+                     pts.rough[:subset], pts.metal[:subset], view=pts.view[:subset])
+    nbs = sop.sop_knn(plan, sub, K)
+    _, ref = sop.sop_shade(plan, tex, sky, sub, S_ref, nb=nbs, seed=77, irradiance=True)
+    norm = float(torch.sqrt(torch.mean(ref ** 2)))
+
+    def err(out):
+        x = out[1]
+        return round(float(torch.sqrt(torch.mean((x - ref) ** 2))) / norm, 5)
+
+    counts = (4, 8, 16, 32, 64, 128, 256)
+    e_ham = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True))
+             for n in counts}
+    e_env = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True,
+                                  env_sampling=True)) for n in counts}
+    t_ham = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5))
+    t_env = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5,
+                                          env_sampling=True))
+    target = e_ham[S]
+    s_star = next((n for n in counts if e_env[n] <= target), None)
+    t_star = (time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, s_star, nb=nb, seed=5,
+                                            env_sampling=True)) if s_star else None)
+    return {"workload": "object: 200k points, K=8, 256x256 octahedral sky with a sun "
+                        "(~70% of the energy); errors on 4096 points against 4096 "
+                        "Hammersley directions",
+            "error_on": "irradiance",
+            "dirs": S, "hammersley_ms": round(t_ham, 4), "env_ms": round(t_env, 4),
+            "rel_rmse": {"hammersley": e_ham, "env": e_env}, "S_star_env": s_star,
+            "env_ms_at_S_star": round(t_star, 4) if t_star else None,
+            "speedup_matched": round(t_ham / t_star, 3) if t_star else None}
 
 
 def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb, S, phase,
@@ -760,12 +955,12 @@ def counter_summary(fname: str, key: str):
     return float(vals[key]) if h == digest else None
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str = "object"):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
     summary is missing or was taken on a different source of the kernel."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_object_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -782,22 +977,25 @@ def measured_traffic(kernel: str):
 
 
 def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
-    """The oracle on a bounded sample of the same workload, scaled to a whole step:
-    shade fwd+bwd (with its brute-force kNN) on a subset of points and the brute-force bake
-    on a subset of rays, each timed, then extrapolated to 200k points and 4.19M rays."""
+    """The oracle on a bounded sample of the same workload. value: shading forward +
+    backward samples per second (the metric; the neighbour lists are found beforehand and
+    not timed, as on the GPU, where the search is its own phase) with all host threads, on
+    a subset of points sized to about a third of the budget; the same at one thread; and the
+    whole step's rate with the brute-force bake of a subset of rays added, extrapolated to
+    200k points and 4.19M rays."""
     import numpy as np
 
     import oracle
     threads = oracle.max_threads()
     rng = np.random.default_rng(7)
-    # calibrate the shading sample on a small subset, then size it to about half the budget
+
     def shade_time(m):
         rows = rng.choice(sc.n, m, replace=False)
         sub = sc.subset(rows)
         grad = rng.standard_normal((m, 3))
-        t = time.time()
         idx, w = oracle.knn(sub.probe_pos, sub.bounds_lo, sub.bounds_hi, sub.pos, sub.normal,
                             sub.k)
+        t = time.time()
         oracle.shade(sub, idx, w)
         oracle.shade_backward(sub, idx, w, grad)
         return time.time() - t
@@ -811,8 +1009,14 @@ def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
             t = fn(m)
         return m, t
 
-    m, t_shade = grow(shade_time, 256, sc.n, 0.5 * seconds)
+    m, t_shade = grow(shade_time, 256, sc.n, seconds / 3.0)
     per_point = t_shade / m
+    oracle.set_threads(1)
+    try:
+        m1, t_shade1 = grow(shade_time, 16, sc.n, seconds / 3.0)
+    finally:
+        oracle.set_threads(threads)
+    per_point1 = t_shade1 / m1
 
     P = probes_np.shape[0]
     def bake_time(n):
@@ -822,16 +1026,19 @@ def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
         oracle.bake_rays(gs, probes_np.astype(np.float64), R, rp, rt)
         return time.time() - t
 
-    nr, t_bake = grow(bake_time, 64, P * R * R, 0.5 * seconds)
+    nr, t_bake = grow(bake_time, 64, P * R * R, seconds / 3.0)
     per_ray = t_bake / nr
 
     t_step = per_point * sc.n + per_ray * P * R * R
-    return {"value": round(sc.n * sc.n_dirs / t_step, 3), "unit": "samples/s",
+    return {"value": round(sc.n_dirs / per_point, 1), "unit": "samples/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"shade fwd+bwd with kNN on {m} of {sc.n} points ({t_shade:.1f}s) and "
-                      f"brute-force bake of {nr} of {P * R * R} rays ({t_bake:.1f}s), "
-                      f"extrapolated to one step; host CPU: {cpu_model()}",
-            "fwd_bwd_samples_per_s": round(sc.n_dirs / per_point, 1)}
+            "sample": f"shade fwd+bwd on {m} of {sc.n} points with {threads} threads "
+                      f"({t_shade:.1f}s) and on {m1} points with 1 thread ({t_shade1:.1f}s), "
+                      f"neighbour lists found beforehand; brute-force bake of {nr} of "
+                      f"{P * R * R} rays ({t_bake:.1f}s) for the whole step; host CPU: "
+                      f"{cpu_model()}",
+            "value_1_thread": round(sc.n_dirs / per_point1, 1),
+            "step_samples_per_s": round(sc.n * sc.n_dirs / t_step, 3)}
 
 
 if __name__ == "__main__":

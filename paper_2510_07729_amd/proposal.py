@@ -53,6 +53,29 @@ def train(mlp: sop.Mlp, plan: sop.Plan, texels: torch.Tensor, env: torch.Tensor,
     return out
 
 
+def train_fixed(mlp: sop.Mlp, plan: sop.Plan, texels: torch.Tensor, env: torch.Tensor,
+                pts: sop.Points, steps: int, samples_per_bin: int = 2, lr: float = 2e-3,
+                k: int = 4, seed: int = 0, log_every: int = 0) -> List[float]:
+    """Training on one fixed set of integrand samples: the bin targets of `pts` are dumped
+    once (pts.n * 256 * samples_per_bin evaluations of the integrand), then `steps` Adam
+    steps are taken on that batch with a cosine decay of the learning rate from lr to 0.
+    Returns the losses read back every `log_every` steps."""
+    if pts.view is None:
+        raise ValueError("the training points need per-point view directions")
+    dev = pts.pos.device
+    T = sop.sop_dump_integrand(plan, texels, env, pts, samples_per_bin, k=k,
+                               seed=seed & 0xFFFFFFFF)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    ws_t = sop.proposal_workspace(L.SOP_OP_PROPOSAL_TRAIN, pts.n, dev)
+    out: List[float] = []
+    for it in range(steps):
+        cur = lr * 0.5 * (1.0 + math.cos(math.pi * it / steps))
+        sop.sop_proposal_train_step(mlp, pts, T, lr=cur, loss=loss, ws=ws_t)
+        if log_every and (it % log_every == 0 or it == steps - 1):
+            out.append(float(loss.item()))
+    return out
+
+
 def integrand_samples(steps: int, batch: int, samples_per_bin: int = 1) -> int:
     """Number of integrand evaluations a training run of `steps` steps consumes."""
     return steps * batch * L.SOP_MLP_BINS * samples_per_bin

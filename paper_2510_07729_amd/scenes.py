@@ -159,16 +159,17 @@ def tiny_shade(n_points: int = 4096, n_probes: int = 64, res: int = 16, H: int =
 
 
 def proposal_eval(n_points: int = 200_000, seed: int = 0) -> ShadeScene:
-    """The tiny scene (same probes, textures and environment) with new shading points from
-    the proposal workload's own streams: the held-out set of the learned proposal."""
-    sc = tiny_shade(n_points=1, seed=seed)
+    """The tiny scene (its probes, textures and environment, whatever the seed) with new
+    shading points from the proposal workload's own streams (keyed by the seed): training
+    pools and held-out sets of the learned proposal share one scene."""
+    sc = tiny_shade(n_points=1, seed=0)
     cfg = CFG_PROPOSAL
     pts = unit_vectors(rng(cfg, 2, seed), n_points)
     view = hemisphere_vectors(rng(cfg, 3, seed), pts).astype(F32)
     albedo, rough, metal = materials(rng(cfg, 4, seed), n_points)
     return dataclasses.replace(sc, name="proposal_eval", pos=pts.astype(F32),
                                normal=pts.astype(F32), view=view, albedo=albedo, rough=rough,
-                               metal=metal)
+                               metal=metal, seed=seed)
 
 
 # learned direction proposal: parameter blob W1 [320,64], b1, W2 [64,64], b2, W3 [64,256], b3

@@ -222,3 +222,14 @@ def test_shade_with_precomputed_neighbors(torch_gpu):
     a = s.sop_shade(plan, dev(sc.texels), dev(sc.env), pts, 64, nb=nb).cpu().numpy()
     b = s.sop_shade(plan, dev(sc.texels), dev(sc.env), pts, 64, k=4).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_shade_reference_direction_count(torch_gpu):
+    """The 4096-direction Hammersley estimate that judges the proposal's error, on the
+    proposal workload's geometry: 1000 points against the oracle."""
+    log("shade at S=4096 (the reference estimate) on 1000 points")
+    sc = scenes.proposal_eval(n_points=1000, seed=0)
+    rgb = run_shade(sc, n_dirs=4096, seed=123)
+    idx, w = oracle_knn(sc)
+    ro = oracle.shade(sc, idx, w, n_dirs=4096, seed=123)
+    assert report("shade S=4096", parity_err(rgb, ro)) <= TOL
