@@ -443,8 +443,12 @@ size_t sop_shadow_workspace_size(const sop_plan* plan, int64_t n_points, int32_t
 
 /* pts, normals: device [M,3], 1 <= M <= 2^31 - 1; 1 <= n_probes <= M; 0 <= start < M;
  * offset finite. Writes probe_pos [n_probes,3] and, when not NULL, chosen [n_probes] (the
- * picks' indices). Enqueues one short kernel per pick. Workspace:
- * sop_place_workspace_size(M). */
+ * picks' indices). Enqueues a fill, all the picks as one launch of at most 64 workgroups
+ * that exchange every pick through device memory, and the probe positions. Every
+ * device-side wait between those workgroups is bounded (about a second): should one give
+ * up, which needs some of them to be kept from running while the others wait (e.g. a
+ * device filled by other work), probe_pos is all NaN. Workspace:
+ * sop_place_workspace_size(M, n_probes). */
 sop_status sop_place_probes(const float* pts, const float* normals, int64_t n_points,
                             int32_t n_probes, int64_t start, float offset, int32_t* chosen,
                             float* probe_pos, void* ws, size_t ws_bytes, sop_stream stream);

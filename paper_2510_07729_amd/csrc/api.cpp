@@ -1348,12 +1348,13 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
 // ------------------------------------------------------------------------------------------
 namespace {
 
-// Workspace layout: [points with their distance to the nearest pick, 4 floats each] [three
-// 64-bit slots] [picks, used when the caller passes no array for them]
+// Workspace layout: [points with their distance to the nearest pick, 4 floats each] [the
+// words the picks are exchanged through and a fault flag] [picks, used when the caller
+// passes no array for them]
 size_t place_ws(int64_t M, int32_t P) {
   Bump b{nullptr, 0, 0};
   (void)b.take<float>(4 * (size_t)M);
-  (void)b.take<uint64_t>(3);
+  (void)b.take<uint64_t>(sopk::kFpsSyncWords);
   (void)b.take<int32_t>((size_t)P);
   return b.used;
 }
@@ -1383,9 +1384,9 @@ extern "C" sop_status sop_place_probes(const float* pts, const float* normals,
   if (st != SOP_OK) return st;
   Bump b{(char*)ws, 0, ws_bytes};
   float* packed = b.take<float>(4 * (size_t)n_points);
-  uint64_t* slots = b.take<uint64_t>(3);
+  uint64_t* sync = b.take<uint64_t>(sopk::kFpsSyncWords);
   int32_t* picks = b.take<int32_t>((size_t)n_probes);
-  SOP_HIP(sopk::launch_place_probes(pts, normals, n_points, n_probes, start, offset, packed, slots,
+  SOP_HIP(sopk::launch_place_probes(pts, normals, n_points, n_probes, start, offset, packed, sync,
                                     chosen ? chosen : picks, probe_pos, (hipStream_t)stream),
           "sop_place_probes");
   return SOP_OK;

@@ -211,10 +211,14 @@ hipError_t launch_bake(const BakeGrid& G, const float* probe_pos, int32_t P, int
                        float* texels, float* depth, const int4* order, hipStream_t s);
 
 // place.hip --------------------------------------------------------------------------------
-// farthest point sampling of P of M points from `start` (dist [M] and slots [3] scratch),
-// chosen [P], probes out [P,3] = fmaf(offset, n, x)
+// farthest point sampling of P of M points from `start`, chosen [P], probes out [P,3] =
+// fmaf(offset, n, x); scratch: packed [4M] floats (points with their distances, for clouds
+// too large for registers) and sync [kFpsSyncWords] (the rows the picks are exchanged
+// through, at most 64 workgroups, then a fault flag)
+constexpr int kFpsSyncRows = 3;
+constexpr size_t kFpsSyncWords = kFpsSyncRows * 64 + 1;
 hipError_t launch_place_probes(const float* pts, const float* nrm, int64_t M, int32_t P,
-                               int64_t start, float offset, float* packed, uint64_t* slots,
+                               int64_t start, float offset, float* packed, uint64_t* sync,
                                int32_t* chosen, float* out, hipStream_t s);
 // doubles of partial sums the loss launches need for n elements
 size_t loss_partials(int64_t n);

@@ -192,3 +192,29 @@ def test_bake_grid_cell_size_is_output_invariant(torch_gpu):
     for cs in (0.2, 0.5, 1.0):
         _, t1, d1 = gpu_bake(gs, probes_np, 16, cell_scale=cs)
         assert np.array_equal(t0, t1) and np.array_equal(d0, d1), cs
+
+
+def test_bake_overflow_rounds_in_one_cell(torch_gpu):
+    """A cloud of 2000 faint Gaussians and a grid of one cell (cell_scale far above the
+    scene): every Gaussian a ray resolves lies in that cell, so a ray that resolves more than
+    the two lanes' 2 x 24 buffered keys must take the cell again above its largest complete
+    key, round after round. The oracle counts the resolved Gaussians per ray (well above 48
+    on most rays here); parity on every unambiguous ray, and the bytes equal those of the
+    default grid."""
+    log("bake: one grid cell, hundreds of resolved Gaussians per ray (buffer overflow rounds)")
+    rng = np.random.default_rng(21)
+    gs = scenes.random_gaussians(rng, 2000, spread=0.3, log_scale=(-2.0, 0.3))
+    gs.opacity[:] = rng.uniform(0.01, 0.04, gs.count).astype(np.float32)
+    probes = rng.uniform(-0.15, 0.15, (4, 3)).astype(np.float32)
+    # cell side = 1000 x the mean cut-off box (~0.5 here) against a scene ~3 across: the
+    # grid has one cell per axis
+    _, tex, dep = gpu_bake(gs, probes, 8, cell_scale=1000.0)
+    rp = np.repeat(np.arange(4), 64).astype(np.int32)
+    rt = np.tile(np.arange(64), 4).astype(np.int32)
+    _, _, used = oracle.bake_rays(gs, probes.astype(np.float64), 8, rp, rt, used=True)
+    log(f"resolved Gaussians per ray: median {int(np.median(used))}, max {used.max()}, "
+        f"{int(np.sum(used > 48))} of {used.size} rays above 48")
+    assert np.mean(used > 48) > 0.5 and used.max() > 4 * 48
+    assert compare(gs, probes, 8, tex, dep, rp, rt, "one cell") <= TOL
+    _, t0, d0 = gpu_bake(gs, probes, 8)
+    assert np.array_equal(t0, tex) and np.array_equal(d0, dep)

@@ -36,15 +36,34 @@ def check_place(pts, nrm, P, start, offset, label):
     assert np.array_equal(pos, oracle.place(pts, nrm, ref, offset))
 
 
-# the last cloud takes several sweeps per workgroup (more points than 256 workgroups of
-# 1024), with a ragged tail
-@pytest.mark.parametrize("M,P,start", [(1000, 100, 7), (4099, 333, 4098), (300, 300, 0),
-                                       (600_001, 96, 600_000)])
+# workgroups of 256 threads with up to 8 points each until there are 64 of them, then more
+# points per thread: 2, 4 (one workgroup), 6, 8, 16 and 25 per thread in registers (ragged
+# tails), and beyond 32 the points streamed from device memory
+@pytest.mark.parametrize("M,P,start", [(300, 300, 0), (1000, 100, 7), (4099, 333, 4098),
+                                       (100_003, 200, 5), (250_001, 128, 250_000),
+                                       (400_003, 64, 17), (600_001, 96, 600_000),
+                                       (1_100_003, 24, 77)])
 def test_fps_random_clouds(torch_gpu, M, P, start):
     g = np.random.default_rng(M)
     pts = g.uniform(-1, 1, (M, 3)).astype(F32)
     nrm = scenes.unit_vectors(g, M).astype(F32)
     check_place(pts, nrm, P, start, 0.03, f"cloud M={M}")
+
+
+def test_fps_calls_in_a_row_reuse_the_workspace(torch_gpu):
+    """The exchange words of one call are cleared by the next: three placements in a row
+    through one workspace, the second on a smaller cloud, all exact."""
+    from paper_2510_07729_amd import sop
+    g = np.random.default_rng(9)
+    ws = sop.workspace(sop.L.load().sop_place_workspace_size(70_000, 500), torch_gpu.device("cuda", 0))
+    for M, P in [(70_000, 500), (3000, 257), (70_000, 499)]:
+        pts = g.uniform(-1, 1, (M, 3)).astype(F32)
+        nrm = scenes.unit_vectors(g, M).astype(F32)
+        pos, chosen = sop.sop_place_probes(dev(pts), dev(nrm), P, 1, 0.02, ws=ws)
+        ref = oracle.fps(pts, P, 1)
+        log(f"placement through one workspace: M={M}, P={P}")
+        assert np.array_equal(chosen.cpu().numpy(), ref)
+        assert np.array_equal(pos.cpu().numpy(), oracle.place(pts, nrm, ref, 0.02))
 
 
 def test_fps_exact_ties_on_a_grid(torch_gpu):
