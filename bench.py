@@ -830,9 +830,12 @@ def place_study(torch, sop, scenes, time_ms, tex) -> dict:
         "workload": "object: 4096 probes from 65,536 surface samples; L_sops on the 4096 "
                     "baked 32x32 maps; L_lam on 200k points",
         "fps_ms": round(t_fps, 3), "fps_picks": 4096, "fps_points": 65536,
+        "fps_hbm_bytes": measured_traffic("k_fps"),
         "sops_loss_ms": round(t_sops, 4), "sops_bytes": b_sops,
         "sops_GBps": round(b_sops / (t_sops * 1e-3) / 1e9, 1),
         "sops_hbm_frac": round(b_sops / (t_sops * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "sops_hbm_bytes": measured_traffic("k_sops_loss"),
+        "lam_hbm_bytes": measured_traffic("k_lam_loss"),
         "lam_loss_ms": round(t_lam, 4), "lam_bytes": b_lam,
         "lam_GBps": round(b_lam / (t_lam * 1e-3) / 1e9, 1),
     }
@@ -1085,5 +1088,20 @@ def cpu_baseline(sc, gs, probes_np, R, seconds, samples_gpu_step):
             "step_samples_per_s": round(sc.n * sc.n_dirs / t_step, 3)}
 
 
+def _report_children() -> None:
+    """Names any child process still alive at exit on stderr (the benchmark starts none; the
+    oracle's gcc build, when its library is stale, is waited for)."""
+    try:
+        import psutil
+        kids = psutil.Process().children(recursive=True)
+    except Exception:
+        return
+    if kids:
+        names = [f"{k.pid}:{k.name()}" for k in kids]
+        print(f"# child processes at exit: {names}", file=sys.stderr, flush=True)
+
+
 if __name__ == "__main__":
-    sys.exit(main())
+    rc = main()
+    _report_children()
+    sys.exit(rc)
