@@ -118,14 +118,16 @@ def _sig(lib):
     u64p = C.POINTER(C.c_uint64)
     lib.orc_env_masses.argtypes = [fptr, C.c_int, u32p, u64p]
     lib.orc_env_masses.restype = C.c_uint64
-    lib.orc_env_draw.argtypes = [u32p, u64p, C.c_int, C.c_int, C.c_int, u32, u32, dptr, dptr]
+    lib.orc_env_draw.argtypes = [u32p, u64p, C.c_int, C.c_int, C.c_int, u32, u32, C.c_int,
+                                 dptr, dptr]
     lib.orc_env_draw.restype = C.c_int
     lib.orc_shadow_ratio.argtypes = [C.c_long, dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr,
                                      C.c_int, C.c_int, u32, C.c_int, C.c_int, dptr, dptr, iptr,
                                      C.POINTER(C.c_uint32)]
     lib.orc_shade_envis.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
                                     dptr, dptr, C.c_int, iptr, dptr, C.c_int, fptr, C.c_int,
-                                    C.c_int, u32, C.POINTER(C.c_uint32), dptr, dptr, iptr]
+                                    C.c_int, u32, C.POINTER(C.c_uint32), C.c_int, dptr, dptr,
+                                    iptr]
     lib.orc_fps.argtypes = [fptr, C.c_long, C.c_int, C.c_long, iptr]
     lib.orc_place.argtypes = [fptr, fptr, iptr, C.c_int, C.c_float, fptr]
     lib.orc_sops_loss.argtypes = [fptr, fptr, C.c_long, dptr, dptr]
@@ -481,16 +483,17 @@ def env_masses(env):
     return mass, prefix
 
 
-def env_draw(mass, prefix, R, S, j, seed, i):
-    """Draw j of S for point i: (texel, direction [3], pdf)."""
+def env_draw(mass, prefix, R, S, j, seed, i, exact=False):
+    """Draw j of S for point i: (texel, direction [3], pdf); pdf of Eq. 18, or with exact
+    the draw's own density on the octahedral map."""
     mass = np.ascontiguousarray(mass, np.uint32)
     prefix = np.ascontiguousarray(prefix, np.uint64)
     w = np.zeros(3)
     pdf = C.c_double()
     t = lib().orc_env_draw(mass.ctypes.data_as(C.POINTER(C.c_uint32)),
                            prefix.ctypes.data_as(C.POINTER(C.c_uint64)), R, S, j,
-                           seed & 0xFFFFFFFF, i & 0xFFFFFFFF, w.ctypes.data_as(dptr),
-                           C.byref(pdf))
+                           seed & 0xFFFFFFFF, i & 0xFFFFFFFF, int(bool(exact)),
+                           w.ctypes.data_as(dptr), C.byref(pdf))
     return t, w, pdf.value
 
 
@@ -498,7 +501,8 @@ def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sample
                  ids=None):
     """Cast-shadow ratio of the points with normals [N,3]: probe maps [P,R,R,4] (channel 3 =
     the object's occlusion O'), neighbours (idx, w) [N,K], octahedral environment [Re,Re,3].
-    sampler 0 = Hammersley, 1 = environment importance sampling. Returns a dict with ratio
+    sampler 0 = Hammersley, 1 = environment importance sampling with the density of Eq. 18,
+    2 = the same draws weighted by their exact density. Returns a dict with ratio
     [N,3], irr [N,3] (the unshadowed estimate) and texels [N,S] (importance draws). ids:
     the points' indices in the full set they come from (keys of draws and rotations)."""
     normal, pn = _d(normal)
@@ -521,10 +525,11 @@ def shadow_ratio(normal, texels, idx, w, env, S, seed=0, per_point=False, sample
 
 
 def shade_envis(sc, idx, w, n_dirs=None, seed=None, ids=None, irradiance=False, texels_out=False,
-                texels=None, env=None):
+                texels=None, env=None, exact=False):
     """Relighting of a ShadeScene with environment importance sampling (Eq. 18 draws and
-    density on the octahedral environment sc.env [Re,Re,3]) instead of the Hammersley set.
-    Returns rgb [N,3] (and irradiance [N,3], and the texel of every draw [N,S])."""
+    density on the octahedral environment sc.env [Re,Re,3]; with exact, the draws' exact
+    density) instead of the Hammersley set. Returns rgb [N,3] (and irradiance [N,3], and the
+    texel of every draw [N,S])."""
     keep = []
 
     def d(a):
@@ -553,7 +558,8 @@ def shade_envis(sc, idx, w, n_dirs=None, seed=None, ids=None, irradiance=False, 
         idp = ida.ctypes.data_as(C.POINTER(C.c_uint32))
     lib().orc_shade_envis(N, d(sc.pos), d(sc.normal), pv, pc, ppf, d(sc.albedo), d(sc.rough),
                           d(sc.metal), d(tex), tex.shape[1], pi, pw, idx.shape[1], pe,
-                          envf.shape[0], S, sd & 0xFFFFFFFF, idp, rgb.ctypes.data_as(dptr),
+                          envf.shape[0], S, sd & 0xFFFFFFFF, idp, int(bool(exact)),
+                          rgb.ctypes.data_as(dptr),
                           irr.ctypes.data_as(dptr), tx.ctypes.data_as(iptr))
     del keep
     out = (rgb,) + ((irr,) if irradiance else ()) + ((tx,) if texels_out else ())

@@ -17,7 +17,12 @@
  *     masses from the texel intensities, orc_env_masses), the direction uniform in the
  *     texel's square of the octahedral map, and the density as Eq. 18 states it with its
  *     normalisation read as I_t / sum(I): pdf = (m_t / C) * R^2 / (4 pi), every texel being
- *     given the mean solid angle 4 pi / R^2 (the paper's "roughly uniform texel areas").
+ *     given the mean solid angle 4 pi / R^2 (the paper's "roughly uniform texel areas");
+ *   - the same draws with their exact density instead: the octahedral square's area element
+ *     is dA = dw / s^3 in the square's [-1,1]^2 coordinates (s = |x| + |y| + |z| of the unit
+ *     direction: the central projection onto the octahedron face, then the projection of
+ *     the face onto the square), so a draw uniform in its texel has
+ *     pdf = (m_t / C) * (R^2 / 4) / s^3, and the estimate is unbiased.
  * Samples below the horizon add nothing to either sum. A channel with L_o = 0 has S = 1.
  *
  * The same draws estimate the object's relighting (Sec. 3.3: object relighting and shadow
@@ -76,9 +81,10 @@ uint64_t orc_env_masses(const float* env, int R, uint32_t* mass, uint64_t* prefi
  * integers with r = hash24(seed, i, j, 0); the texel t with prefix[t] <= x < prefix[t+1];
  * the position (col + xu, row + xv) in texel units with xu, xv = (hash24(seed, i, j, 1|2)
  * + 1/2) / 2^24; the direction is the octahedral decode of that position. Returns t and
- * the density of Eq. 18, *pdf = (m_t / C) R^2 / (4 pi). */
+ * the density: of Eq. 18, *pdf = (m_t / C) R^2 / (4 pi), or with exact != 0 the draw's own
+ * density (m_t / C) (R^2 / 4) / s^3, s = |w_x| + |w_y| + |w_z|. */
 int orc_env_draw(const uint32_t* mass, const uint64_t* prefix, int R, int S, int j,
-                 uint32_t seed, uint32_t i, double w[3], double* pdf) {
+                 uint32_t seed, uint32_t i, int exact, double w[3], double* pdf) {
   const int T = R * R;
   const uint64_t C = prefix[T];
   const uint64_t r = orc_hash24(seed, i, (uint32_t)j, 0);
@@ -91,13 +97,19 @@ int orc_env_draw(const uint32_t* mass, const uint64_t* prefix, int R, int S, int
   const double xu = ((double)orc_hash24(seed, i, (uint32_t)j, 1) + 0.5) / 16777216.0;
   const double xv = ((double)orc_hash24(seed, i, (uint32_t)j, 2) + 0.5) / 16777216.0;
   orc_oct_decode((double)(lo % R) + xu, (double)(lo / R) + xv, R, w);
-  *pdf = (double)mass[lo] / (double)C * (double)T / (4.0 * SH_PI);
+  if (exact) {
+    const double sl = fabs(w[0]) + fabs(w[1]) + fabs(w[2]);
+    *pdf = (double)mass[lo] / (double)C * ((double)T / 4.0) / (sl * sl * sl);
+  } else {
+    *pdf = (double)mass[lo] / (double)C * (double)T / (4.0 * SH_PI);
+  }
   return lo;
 }
 
 /* Shadow ratio of N points. normal [N][3]; tex [P][Rp][Rp][4] probe maps (channel 3 = O');
  * idx/nbw [N][K] neighbours (Eq. 9-11); env [Re][Re][3] float32 (its intensities decide
- * the masses). sampler 0 = Hammersley, 1 = environment importance sampling.
+ * the masses). sampler 0 = Hammersley, 1 = environment importance sampling with the
+ * density of Eq. 18, 2 = the same draws with their exact density.
  * ratio [N][3]; irr [N][3] (may be NULL) = (1/S) sum E cos+ / pdf (L_o / f_d); texels
  * [N][S] (may be NULL) = the texel of each importance draw (-1 for Hammersley). ids [N]
  * (may be NULL: 0..N-1) are the point indices that key the draws and rotations, so that a
@@ -126,7 +138,7 @@ void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
         if (texels) texels[i * S + j] = -1;
       } else {
         double pdf;
-        int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, w, &pdf);
+        int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, sampler == 2, w, &pdf);
         if (texels) texels[i * S + j] = t;
         ct = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
         wt = 1.0 / pdf;
@@ -159,12 +171,14 @@ void orc_shadow_ratio(long N, const double* normal, const double* tex, int Rp,
  * (view [N][3], or cam [F][3] with ppf points per frame when view is NULL). Draws below the
  * horizon add nothing. irr (may be NULL) = (1/S) sum_j L_i (n . w_j)+ / pdf_j; texels (may
  * be NULL) [N][S] receives the texel of every draw; ids (may be NULL: 0..N-1) key the
- * draws, so that a subset of a larger point set keeps its draws. */
+ * draws, so that a subset of a larger point set keeps its draws. exact != 0 weights every
+ * draw by its exact density instead of that of Eq. 18 (orc_env_draw). */
 void orc_shade_envis(long N, const double* pos, const double* normal, const double* view,
                      const double* cam, long ppf, const double* albedo, const double* rough,
                      const double* metal, const double* tex, int R, const int32_t* idx,
                      const double* wts, int K, const float* env, int Re, int S, uint32_t seed,
-                     const uint32_t* ids, double* rgb, double* irr, int32_t* texels) {
+                     const uint32_t* ids, int exact, double* rgb, double* irr,
+                     int32_t* texels) {
   const int T = Re * Re;
   double* env64 = (double*)malloc(sizeof(double) * 3 * (size_t)T);
   for (long q = 0; q < 3L * T; ++q) env64[q] = (double)env[q];
@@ -188,7 +202,7 @@ void orc_shade_envis(long N, const double* pos, const double* normal, const doub
     double acc[3] = {0, 0, 0}, acc_e[3] = {0, 0, 0};
     for (int j = 0; j < S; ++j) {
       double w[3], pdf;
-      const int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, w, &pdf);
+      const int t = orc_env_draw(mass, prefix, Re, S, j, seed, id, exact, w, &pdf);
       if (texels) texels[i * S + j] = t;
       const double ct = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
       if (!(ct > 0.0)) continue;

@@ -122,3 +122,80 @@ def test_bright_texel_takes_its_share_of_the_draws_and_the_weights_undo_it():
     L = np.array([oracle.oct_fetch(env.astype(np.float64), x)[0] for x in d])
     ref = 4.0 * np.pi * np.mean(L * np.maximum(d @ sc.normal[0].astype(np.float64), 0.0))
     assert irr[0, 0] == pytest.approx(ref, rel=2e-2)
+
+
+# ------------------------------------------------------------------------------------------
+# the same draws weighted by their exact density (m_t / C) (R^2 / 4) / s^3
+# ------------------------------------------------------------------------------------------
+def encode(w, R):
+    """Texel coordinates (u, v) in [0, R]^2 of a unit direction (inverse of decode)."""
+    w = np.asarray(w, np.float64)
+    p = w / np.sum(np.abs(w))
+    px, py = p[0], p[1]
+    if p[2] < 0.0:
+        px, py = (1.0 - abs(p[1])) * (1.0 if p[0] >= 0 else -1.0), \
+                 (1.0 - abs(p[0])) * (1.0 if p[1] >= 0 else -1.0)
+    return (px + 1.0) * R / 2.0, (py + 1.0) * R / 2.0
+
+
+def test_exact_density_is_the_mass_over_the_numerical_area_element():
+    """pdf of a draw = (m_t / C) / |dw/du x dw/dv| with the Jacobian of this file's own
+    decode taken by central differences (texel units: a texel has area 1), independent of
+    the s^3 formula."""
+    Re = 8
+    env = np.random.default_rng(7).lognormal(0.0, 1.0, (Re, Re, 3)).astype(F32)
+    mass, prefix = oracle.env_masses(env)
+    C = float(prefix[-1])
+    h = 1e-5
+    for j in range(0, 256, 7):
+        t, w, pdf = oracle.env_draw(mass, prefix, Re, 256, j, 5, 3, exact=True)
+        u, v = encode(w, Re)
+        assert np.allclose(decode(u, v, Re), w, atol=1e-12)
+        du = (decode(u + h, v, Re) - decode(u - h, v, Re)) / (2 * h)
+        dv = (decode(u, v + h, Re) - decode(u, v - h, Re)) / (2 * h)
+        area = np.linalg.norm(np.cross(du, dv))
+        assert pdf == pytest.approx(mass[t] / C / area, rel=1e-6)
+        _, w2, pdf_paper = oracle.env_draw(mass, prefix, Re, 256, j, 5, 3)
+        assert np.array_equal(w, w2)               # the same draw, only the density differs
+        assert pdf_paper == pytest.approx(mass[t] / C * Re * Re / (4 * np.pi), rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [(0, 0, 1), (0, 0, -1), (0.3, -0.5, 0.81), (1, 0, 0)])
+def test_exact_density_constant_sky_irradiance_is_pi_L(n):
+    """With the exact density the estimate is unbiased: a constant sky L gives pi L for
+    every normal (the biased density of Eq. 18 gives 4 pi L times the square mean of cos+
+    instead, pinned above)."""
+    Re, L = 8, 1.7
+    sc, idx, w = one_point(n, seed=1)
+    sc = dataclasses.replace(sc, texels=np.zeros_like(sc.texels),
+                             env=np.full((Re, Re, 3), L, F32), env_oct=True)
+    # 4096 draws per texel: the in-texel spread of 4 s^3 cos+ leaves a Monte Carlo error of
+    # ~1e-3 (relative standard deviation, from a quadrature of its per-texel variance)
+    _, irr = oracle.shade_envis(sc, idx, w, n_dirs=Re * Re * 4096, seed=3, irradiance=True,
+                                exact=True)
+    assert irr[0] == pytest.approx(np.full(3, np.pi * L), rel=5e-3)
+
+
+def test_exact_density_bright_texel_converges_to_the_solid_angle_integral():
+    """A sky with one texel 1000x brighter, normal +z: the exact-density irradiance against
+    the integral of L cos over the hemisphere by a midpoint rule in spherical coordinates
+    (L from the oracle's pinned octahedral lookup)."""
+    Re = 8
+    sc, idx, w = one_point((0, 0, 1), seed=3)
+    env = np.full((Re, Re, 3), 1.0, F32)
+    env.reshape(-1, 3)[3 * Re + 4] = 1000.0
+    sc = dataclasses.replace(sc, texels=np.zeros_like(sc.texels), env=env, env_oct=True)
+    # 2^19 draws: the texels next to the bright one take its bilinear spill-over with few
+    # draws (their masses are small), which leaves ~4% of scatter at 2^15 draws
+    _, irr = oracle.shade_envis(sc, idx, w, n_dirs=1 << 19, seed=6, irradiance=True,
+                                exact=True)
+    nt, nph = 192, 384
+    th = (np.arange(nt) + 0.5) * (np.pi / 2) / nt
+    ph = (np.arange(nph) + 0.5) * 2 * np.pi / nph
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    d = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1).reshape(-1, 3)
+    env64 = env.astype(np.float64)
+    Lr = np.array([oracle.oct_fetch(env64, x)[0] for x in d])
+    wq = (np.cos(T) * np.sin(T)).ravel() * (np.pi / 2 / nt) * (2 * np.pi / nph)
+    ref = float(np.sum(Lr * wq))
+    assert irr[0, 0] == pytest.approx(ref, rel=2e-2)
