@@ -645,9 +645,10 @@ def envis_study(torch, sop, scenes, time_ms, plan, tex, pts, nb, S, K, t_fwd_equ
     relative RMSE of the irradiance output (the cosine-weighted incident light; rgb errors
     of uniform sampling are dominated by rare hits of narrow GGX lobes on the sun) against a
     Hammersley estimate at S_ref directions on `subset` points; S* = the fewest importance
-    samples whose error is at most the Hammersley error at S. The importance estimate weights each draw with the paper's mean-solid-angle
-    density, so it converges to 4 pi times the mean of the integrand over the octahedral
-    square, not to the integral: its error levels off at that bias."""
+    samples whose error is at most the Hammersley error at S. Two weightings of the same
+    draws: "env" with the paper's mean-solid-angle density, which converges to 4 pi times
+    the mean of the integrand over the octahedral square, not to the integral, so its error
+    levels off at that bias; "env_exact" with the draws' exact density (unbiased)."""
     import numpy as np
     dev = pts.pos.device
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)   # noqa: E731
@@ -663,39 +664,41 @@ def envis_study(torch, sop, scenes, time_ms, plan, tex, pts, nb, S, K, t_fwd_equ
         return round(float(torch.sqrt(torch.mean((x - ref) ** 2))) / norm, 5)
 
     counts = (4, 8, 16, 32, 64, 128, 256)
+    modes = {"env": True, "env_exact": "exact"}
     e_ham = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True))
              for n in counts}
-    e_env = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True,
-                                  env_sampling=True)) for n in counts}
     t_ham = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5))
-    t_env = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5,
-                                          env_sampling=True))
-    target = e_ham[S]
-    s_star = next((n for n in counts if e_env[n] <= target), None)
-    t_star = (time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, s_star, nb=nb, seed=5,
-                                            env_sampling=True)) if s_star else None)
-    # the matched count and speedup for smaller Hammersley budgets too (the importance
-    # estimate's bias sets a floor below which it cannot match)
-    matched = {}
-    for nh in (16, 32, 64):
-        ne = next((n for n in counts if e_env[n] <= e_ham[nh]), None)
-        if ne is None:
-            matched[nh] = None
-            continue
-        th = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, nh, nb=nb, seed=5))
-        te = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, ne, nb=nb, seed=5,
-                                           env_sampling=True))
-        matched[nh] = {"env_dirs": ne, "hammersley_ms": round(th, 4), "env_ms": round(te, 4),
-                       "speedup": round(th / te, 3)}
-    return {"workload": "object: 200k points, K=8, 256x256 octahedral sky with a sun "
-                        "(~70% of the energy); errors on 4096 points against 4096 "
-                        "Hammersley directions",
-            "error_on": "irradiance",
-            "dirs": S, "hammersley_ms": round(t_ham, 4), "env_ms": round(t_env, 4),
-            "rel_rmse": {"hammersley": e_ham, "env": e_env}, "S_star_env": s_star,
-            "env_ms_at_S_star": round(t_star, 4) if t_star else None,
-            "speedup_matched": round(t_ham / t_star, 3) if t_star else None,
-            "matched_at_smaller_budgets": matched}
+    out = {"workload": "object: 200k points, K=8, 256x256 octahedral sky with a sun "
+                       "(~70% of the energy); errors on 4096 points against 4096 "
+                       "Hammersley directions",
+           "error_on": "irradiance", "dirs": S, "hammersley_ms": round(t_ham, 4),
+           "rel_rmse": {"hammersley": e_ham}}
+    for name, mode in modes.items():
+        e = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True,
+                                  env_sampling=mode)) for n in counts}
+        t_env = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5,
+                                              env_sampling=mode))
+        s_star = next((n for n in counts if e[n] <= e_ham[S]), None)
+        t_star = (time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, s_star, nb=nb, seed=5,
+                                                env_sampling=mode)) if s_star else None)
+        # the matched count and speedup for smaller Hammersley budgets too
+        matched = {}
+        for nh in (16, 32, 64):
+            ne = next((n for n in counts if e[n] <= e_ham[nh]), None)
+            if ne is None:
+                matched[nh] = None
+                continue
+            th = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, nh, nb=nb, seed=5))
+            te = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, ne, nb=nb, seed=5,
+                                               env_sampling=mode))
+            matched[nh] = {"env_dirs": ne, "hammersley_ms": round(th, 4),
+                           "env_ms": round(te, 4), "speedup": round(th / te, 3)}
+        out["rel_rmse"][name] = e
+        out[name] = {"ms": round(t_env, 4), "S_star": s_star,
+                     "ms_at_S_star": round(t_star, 4) if t_star else None,
+                     "speedup_matched": round(t_ham / t_star, 3) if t_star else None,
+                     "matched_at_smaller_budgets": matched}
+    return out
 
 
 def trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb, S, phase,
@@ -860,7 +863,8 @@ def shadow_study(torch, sop, scenes, time_ms, bake_plan, R, subset=4096, S_ref=4
     environment importance sampling (Eq. 18) at S = 64: time of each, and their errors
     against a Hammersley reference at S_ref on a point subset, over the points the object
     shadows (reference ratio below 0.98 in some channel); S* is the fewest importance
-    samples whose error is at most the Hammersley error at 64."""
+    samples whose error is at most the Hammersley error at 64, for the draws weighted with
+    Eq. 18's density and with their exact density."""
     import numpy as np
     from paper_2510_07729_amd import _lib as L
     dev = torch.device("cuda", 0)
@@ -873,6 +877,7 @@ def shadow_study(torch, sop, scenes, time_ms, bake_plan, R, subset=4096, S_ref=4
 
     t_ham = time_ms(lambda: run(S, L.SOP_SHADOW_HAMMERSLEY))
     t_env = time_ms(lambda: run(S, L.SOP_SHADOW_ENV))
+    t_env_x = time_ms(lambda: run(S, L.SOP_SHADOW_ENV_EXACT))
     rows = torch.from_numpy(np.sort(np.random.default_rng(13).choice(N, subset, replace=False)))
     rows = rows.to(dev)
     sub = sop.Points(pts.pos[rows], pts.normal[rows], None, None, None)
@@ -886,20 +891,26 @@ def shadow_study(torch, sop, scenes, time_ms, bake_plan, R, subset=4096, S_ref=4
         x = x.double()
         return float(((x[shadowed] - ref[shadowed]) ** 2).mean().sqrt()) if n_sh else 0.0
 
-    e = {"hammersley": {}, "env": {}}
+    samplers = (("hammersley", L.SOP_SHADOW_HAMMERSLEY), ("env", L.SOP_SHADOW_ENV),
+                ("env_exact", L.SOP_SHADOW_ENV_EXACT))
+    e = {name: {} for name, _ in samplers}
     for s_ in (4, 8, 16, 32, 64, 128, 256):
-        for name, smp in (("hammersley", L.SOP_SHADOW_HAMMERSLEY), ("env", L.SOP_SHADOW_ENV)):
+        for name, smp in samplers:
             e[name][str(s_)] = round(err(sop.sop_shadow_ratio(plan, tex, env, sub, s_, nb=nb_s,
                                                               sampler=smp)), 5)
     target = e["hammersley"][str(S)]
     s_star = min((int(k) for k, v in e["env"].items() if v <= target), default=None)
     t_star = None if s_star is None else time_ms(lambda: run(s_star, L.SOP_SHADOW_ENV))
+    s_star_x = min((int(k) for k, v in e["env_exact"].items() if v <= target), default=None)
+    t_star_x = (None if s_star_x is None
+                else time_ms(lambda: run(s_star_x, L.SOP_SHADOW_ENV_EXACT)))
     mean_ratio = float(run(S, L.SOP_SHADOW_HAMMERSLEY).mean())
     return {
         "workload": "shadow_scene: object over a ground plane, 2048 ground probes (32x32) "
                     "baked from the object's 100k Gaussians, 500k ground points, 256x256 "
                     "octahedral sky with a sun, K=8",
         "dirs": S, "points": N, "hammersley_ms": round(t_ham, 4), "env_ms": round(t_env, 4),
+        "env_exact_ms": round(t_env_x, 4),
         "samples_per_s_hammersley": round(N * S / (t_ham * 1e-3)),
         "samples_per_s_env": round(N * S / (t_env * 1e-3)),
         "mean_ratio": round(mean_ratio, 4),
@@ -907,6 +918,9 @@ def shadow_study(torch, sop, scenes, time_ms, bake_plan, R, subset=4096, S_ref=4
         "rmse_ratio": e, "S_star_env": s_star,
         "env_ms_at_S_star": None if t_star is None else round(t_star, 4),
         "speedup_matched": None if t_star is None else round(t_ham / t_star, 3),
+        "S_star_env_exact": s_star_x,
+        "env_exact_ms_at_S_star": None if t_star_x is None else round(t_star_x, 4),
+        "speedup_matched_exact": None if t_star_x is None else round(t_ham / t_star_x, 3),
     }
 
 

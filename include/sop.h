@@ -202,9 +202,11 @@ typedef enum sop_sampler {
   SOP_SAMPLER_PROPOSAL = 1,       /* per-point bin distributions given in opts.probs        */
   SOP_SAMPLER_PROPOSAL_NET = 2,   /* bin distributions of the network opts.net, evaluated
                                      inside the shading call (they never reach memory)     */
-  SOP_SAMPLER_ENV = 3             /* environment importance sampling (Eq. 18) on an
+  SOP_SAMPLER_ENV = 3,            /* environment importance sampling (Eq. 18) on an
                                      octahedral env: the draws and density of
                                      SOP_SHADOW_ENV (see sop_shadow_ratio)                  */
+  SOP_SAMPLER_ENV_EXACT = 4       /* the same draws weighted by their exact density, as
+                                     SOP_SHADOW_ENV_EXACT                                  */
 } sop_sampler;
 
 typedef struct sop_mlp sop_mlp;
@@ -239,7 +241,8 @@ typedef struct sop_shade_opts {
  * SOP_ERR_UNSUPPORTED); draw j of point i (its index in pts) is the draw of the
  * SOP_SHADOW_ENV sampler with density pdf_j = (m_t / C) R_e^2 / (4 pi), and
  * rgb_i = (1/S) sum_j f L_i (n . w_j)+ / pdf_j, out_irradiance (1/S) sum_j L_i (n . w_j)+ /
- * pdf_j; draws below the horizon add nothing. It has no adjoint either. */
+ * pdf_j; draws below the horizon add nothing. SOP_SAMPLER_ENV_EXACT takes the same draws
+ * with the density of SOP_SHADOW_ENV_EXACT. Neither has an adjoint. */
 sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
                      const sop_points* pts, const sop_neighbors* nb,
                      const sop_shade_opts* opts, float* rgb,
@@ -389,8 +392,13 @@ size_t sop_shade_traced_workspace_size(const sop_plan* order_by, int64_t n_point
  *     integers, the texel t with M_t <= x < M_t + m_t (M_t = mass of the texels before t),
  *     the direction = octahedral decode of (column + (h(i,j,1) + 1/2)/2^24,
  *     row + (h(i,j,2) + 1/2)/2^24) in texel units, and the density of Eq. 18 with its
- *     normalisation read as I_t / sum(I): pdf = (m_t / C) R^2 / (4 pi). Here
- *     h(i,j,k) = pcg(pcg(pcg(seed) ^ i) ^ (4 j + k)) >> 8 (pcg as for the directions).
+ *     normalisation read as I_t / sum(I): pdf = (m_t / C) R^2 / (4 pi), which gives every
+ *     texel the mean solid angle 4 pi / R^2 (the estimate then carries the map's area
+ *     distortion as a bias). Here h(i,j,k) = pcg(pcg(pcg(seed) ^ i) ^ (4 j + k)) >> 8 (pcg
+ *     as for the directions).
+ *   SOP_SHADOW_ENV_EXACT: the same draws with their exact density,
+ *     pdf = (m_t / C) (R^2 / 4) / s^3 with s = |x| + |y| + |z| of the unit direction (the
+ *     octahedral square's area element is dw / s^3): an unbiased estimate.
  * ratio_c = sum_j L_c (1 - O') cos+ / pdf  /  sum_j L_c cos+ / pdf, and 1 where the
  * denominator is 0.
  * --------------------------------------------------------------------------------------*/
@@ -404,7 +412,8 @@ typedef struct sop_env_oct {
 
 typedef enum sop_shadow_sampler {
   SOP_SHADOW_HAMMERSLEY = 0,     /* hemisphere Hammersley set (Eq. 7)                      */
-  SOP_SHADOW_ENV = 1             /* environment importance sampling (Eq. 18)               */
+  SOP_SHADOW_ENV = 1,            /* environment importance sampling (Eq. 18)               */
+  SOP_SHADOW_ENV_EXACT = 2       /* the same draws with their exact density                */
 } sop_shadow_sampler;
 
 typedef struct sop_shadow_opts {

@@ -518,7 +518,7 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
         return fail(SOP_ERR_INVALID_ARGUMENT, "net bounds must be finite with hi > lo");
     if (!(o->mix_eps >= 0.0f && o->mix_eps <= 1.0f))
       return fail(SOP_ERR_INVALID_ARGUMENT, "mix_eps out of [0, 1]");
-  } else if (o->sampler == SOP_SAMPLER_ENV) {
+  } else if (o->sampler == SOP_SAMPLER_ENV || o->sampler == SOP_SAMPLER_ENV_EXACT) {
     if (!allow_proposal)
       return fail(SOP_ERR_UNSUPPORTED, "the environment sampler has no adjoint");
     if (env->layout != SOP_ENV_OCTAHEDRAL)
@@ -603,8 +603,9 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
     a.probs = opts->probs;
     a.mix_eps = opts->mix_eps;
     SOP_HIP(sopk::launch_shade_prop(a, kk, maps->format, s), "sop_shade");
-  } else if (opts->sampler == SOP_SAMPLER_ENV) {
+  } else if (opts->sampler == SOP_SAMPLER_ENV || opts->sampler == SOP_SAMPLER_ENV_EXACT) {
     a.env_res = env->width;
+    a.env_pdf_exact = opts->sampler == SOP_SAMPLER_ENV_EXACT ? 1 : 0;
     a.env_mass = cdf.mass;
     a.env_prefix = cdf.prefix;
     SOP_HIP(sopk::launch_env_cdf(env->texels, env->width * env->height, cdf.mass, cdf.prefix,
@@ -1289,7 +1290,8 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
   }
   if (opts->n_dirs < 1 || opts->n_dirs > SOP_MAX_DIRS)
     return fail(SOP_ERR_INVALID_ARGUMENT, "n_dirs out of [1, 4096]");
-  if (opts->sampler != SOP_SHADOW_HAMMERSLEY && opts->sampler != SOP_SHADOW_ENV)
+  if (opts->sampler != SOP_SHADOW_HAMMERSLEY && opts->sampler != SOP_SHADOW_ENV &&
+      opts->sampler != SOP_SHADOW_ENV_EXACT)
     return fail(SOP_ERR_UNSUPPORTED, "unknown shadow sampler");
   if (pts->count > 0 && (!ratio || !aligned(ratio, 4)))
     return fail(SOP_ERR_INVALID_ARGUMENT, "ratio is NULL or misaligned");
@@ -1314,6 +1316,7 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
   a.seed = opts->seed;
   a.per_point = opts->rotate_per_point ? 1 : 0;
   a.shadow_sampler = opts->sampler;
+  a.env_pdf_exact = opts->sampler == SOP_SHADOW_ENV_EXACT ? 1 : 0;
   a.rgb = ratio;
   a.irr = opts->out_irradiance;
   Bump b{(char*)ws, 0, ws_bytes};

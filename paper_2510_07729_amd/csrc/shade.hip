@@ -449,6 +449,18 @@ __global__ __launch_bounds__(1024) void k_env_add(int32_t T, const uint64_t* til
   if (t < T && blockIdx.x > 0) prefix[t] += tile_off[blockIdx.x];
 }
 
+// 1 / pdf of an environment importance draw of texel mass m (total C, T texels) in the unit
+// direction w: Eq. 18's density (m / C) T / (4 pi), or with exact the draw's own density
+// (m / C) (T / 4) / s^3, s = |w_x| + |w_y| + |w_z| (the octahedral square's area element).
+__device__ __forceinline__ float env_inv_pdf(const double w[3], uint32_t m, uint64_t C,
+                                             int32_t T, bool exact) {
+  if (exact) {
+    const double sl = fabs(w[0]) + fabs(w[1]) + fabs(w[2]);
+    return (float)(4.0 * (sl * sl * sl) * (double)C / ((double)m * (double)T));
+  }
+  return (float)(12.566370614359172 * (double)C / ((double)m * (double)T));
+}
+
 // L lanes per point (64/L points per wavefront, in processing order; L = 64 for S > 32),
 // lane l of a point takes directions l, l+L, ...; the estimates of Eq. 15 and 16 share
 // every sample, and the ratio is formed after the lane-group sums.
@@ -475,7 +487,7 @@ __global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
   Neighbors<KT> nb;
   if (valid) nb.load(a, p, k);
   const int kn = KT > 0 ? KT : nb.count(k);
-  const bool importance = a.shadow_sampler == 1;
+  const bool importance = a.shadow_sampler != 0;
   Frame64 F;
   double cr = 1.0, sr = 0.0;
   if (!importance) {
@@ -512,8 +524,7 @@ __global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
       const double cd = w64[0] * n64[0] + w64[1] * n64[1] + w64[2] * n64[2];
       if (!(cd > 0.0)) continue;
       ct = (float)cd;
-      // 1 / pdf with pdf = (m_t / C) T / (4 pi)
-      wt = (float)(12.566370614359172 * (double)C / ((double)a.env_mass[lo] * (double)T));
+      wt = env_inv_pdf(w64, a.env_mass[lo], C, T, a.env_pdf_exact != 0);
     }
     const Taps te = oct_taps64(w64, Re);
     float E[3] = {0.0f, 0.0f, 0.0f};
@@ -566,8 +577,8 @@ __global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
 // Object relighting with environment importance sampling (Sec. 3.3: relighting and shadows
 // are both estimated with the density of Eq. 18): the shading estimate of Eq. 6-9 with the
 // draws of the cast-shadow ratio's Eq. 18 sampler on an octahedral environment,
-// rgb = (1/S) sum_j f L_i cos+ / pdf_j with pdf_j = (m_t / C) R_e^2 / (4 pi); draws below
-// the horizon add nothing. L lanes per point (64/L points per wavefront), lane l of a point
+// rgb = (1/S) sum_j f L_i cos+ / pdf_j with pdf_j = (m_t / C) R_e^2 / (4 pi), or the draw's
+// exact density (env_inv_pdf); draws below the horizon add nothing. L lanes per point (64/L points per wavefront), lane l of a point
 // taking draws l, l + L, ...
 // ------------------------------------------------------------------------------------------
 template <int KT, typename TexT, int L>
@@ -604,8 +615,7 @@ __global__ __launch_bounds__(256) void k_shade_envis(ShadeArgs a, int32_t k) {
       s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
       s.ct = (float)cd;
       eval_at<KT, TexT, true>(a, ps, nb, k, s);
-      // 1 / pdf = 4 pi C / (m_t T)
-      const float wt = (float)(12.566370614359172 * (double)C / ((double)a.env_mass[lo] * (double)T));
+      const float wt = env_inv_pdf(s.w64, a.env_mass[lo], C, T, a.env_pdf_exact != 0);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1627,7 +1637,7 @@ static void launch_shadow_kt(const ShadeArgs& a, int32_t k, int32_t format, hipS
 
 hipError_t launch_shadow_ratio(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if (a.shadow_sampler == 1 && (!a.env_mass || !a.env_prefix)) return hipErrorInvalidValue;
+  if (a.shadow_sampler != 0 && (!a.env_mass || !a.env_prefix)) return hipErrorInvalidValue;
   if (a.shadow_sampler == 0 && !a.dir_tab) return hipErrorInvalidValue;
   switch (k) {
     case 4: launch_shadow_kt<4>(a, k, format, s); break;

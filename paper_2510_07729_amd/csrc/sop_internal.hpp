@@ -92,6 +92,7 @@ struct ShadeArgs {
   const uint64_t* env_prefix;  // [Re*Re + 1], env_prefix[Re*Re] = total mass
   int32_t env_res;
   int32_t shadow_sampler;   // 0 Hammersley, 1 environment importance sampling
+  int32_t env_pdf_exact;    // importance draws weighted by their exact density (else Eq. 18's)
   // learned proposal sampler / training targets
   const float* probs;       // [n,256] bin distributions
   float mix_eps;

@@ -278,14 +278,18 @@ def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
 def shade_opts(n_dirs: int, k: int, seed: int = 0, radius: float = math.inf,
                rotate_per_point: bool = False, irradiance: Optional[torch.Tensor] = None,
                probs: Optional[torch.Tensor] = None, mix_eps: float = 0.1, net=None,
-               env_sampling: bool = False):
+               env_sampling=False):
     """Shading options; `net` (an Mlp) selects the fused proposal sampler, env_sampling the
-    environment importance sampler (Eq. 18). The returned object keeps the network's C
-    struct alive (attribute _net)."""
+    environment importance sampler (True: Eq. 18's density, "exact": the draws' exact
+    density). The returned object keeps the network's C struct alive (attribute _net)."""
     o = L.sop_shade_opts()
     o.n_dirs, o.k, o.radius, o.seed = int(n_dirs), int(k), float(radius), int(seed) & 0xFFFFFFFF
     o.rotate_per_point = int(rotate_per_point)
-    if env_sampling:
+    if env_sampling == "exact":
+        o.sampler = L.SOP_SAMPLER_ENV_EXACT
+    elif env_sampling:
+        if env_sampling is not True:
+            raise ValueError(f"env_sampling must be False, True or 'exact', not {env_sampling!r}")
         o.sampler = L.SOP_SAMPLER_ENV
     elif net is not None:
         o.sampler = L.SOP_SAMPLER_PROPOSAL_NET
@@ -304,11 +308,12 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
               radius: float = math.inf, rotate_per_point: bool = False,
               irradiance: bool = False, ws: Optional[torch.Tensor] = None,
               out: Optional[torch.Tensor] = None, probs: Optional[torch.Tensor] = None,
-              mix_eps: float = 0.1, net=None, env_sampling: bool = False):
+              mix_eps: float = 0.1, net=None, env_sampling=False):
     """Forward shading: rgb [N,3] (and irradiance [N,3] when asked). With probs [N,256] the
     directions are drawn from those bin distributions (mixed with mix_eps of uniform bins);
     with net (an Mlp) from the network's distributions, evaluated inside the call; with
-    env_sampling (env an OctEnv) by environment importance sampling (Eq. 18)."""
+    env_sampling (env an OctEnv) by environment importance sampling (Eq. 18; "exact" weights
+    the draws by their exact density)."""
     dev = pts.pos.device
     n = pts.n
     pts.check()

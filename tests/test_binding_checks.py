@@ -112,3 +112,10 @@ def test_other_entry_points():
     with pytest.raises(ValueError, match="out"):
         sop.sop_shadow_ratio(plan(), tex(), torch.zeros(8, 8, 3), pts(), 16,
                              out=torch.zeros(N + 1, 3))
+
+
+def test_env_sampling_modes():
+    assert sop.shade_opts(16, 4, env_sampling="exact").sampler == sop.L.SOP_SAMPLER_ENV_EXACT
+    assert sop.shade_opts(16, 4, env_sampling=True).sampler == sop.L.SOP_SAMPLER_ENV
+    with pytest.raises(ValueError, match="env_sampling"):
+        sop.shade_opts(16, 4, env_sampling="eq18")

@@ -30,27 +30,29 @@ def sunny(sc, R, seed=0, sigma=1.0):
     return dataclasses.replace(sc, env=env, env_oct=True)
 
 
-def gpu_envis(sc, k=None, nb=None):
+def gpu_envis(sc, k=None, nb=None, exact=False):
     from paper_2510_07729_amd import sop
     plan = gpu_plan(sc)
     rgb, irr = sop.sop_shade(plan, dev(sc.texels), sop.OctEnv(dev(sc.env)), gpu_points(sc),
                              sc.n_dirs, k=sc.k if k is None else k, nb=nb, seed=sc.seed,
-                             irradiance=True, env_sampling=True)
+                             irradiance=True, env_sampling="exact" if exact else True)
     return rgb.cpu().numpy(), irr.cpu().numpy()
 
 
-@pytest.mark.parametrize("R,S,k,fmt", [(16, 64, 4, "f32"), (32, 37, 4, "f32"),
-                                       (32, 16, 3, "f32"), (16, 100, 4, "f16"),
-                                       (8, 1, 4, "f32")])
-def test_envis_tiny_scene(torch_gpu, R, S, k, fmt):
-    log(f"environment importance sampling: tiny scene, {R}x{R} sky, S={S}, K={k}, {fmt}")
+@pytest.mark.parametrize("R,S,k,fmt,exact", [(16, 64, 4, "f32", False), (32, 37, 4, "f32", False),
+                                             (32, 16, 3, "f32", False), (16, 100, 4, "f16", False),
+                                             (8, 1, 4, "f32", False), (16, 64, 4, "f32", True),
+                                             (32, 16, 3, "f32", True), (16, 100, 4, "f16", True)])
+def test_envis_tiny_scene(torch_gpu, R, S, k, fmt, exact):
+    log(f"environment importance sampling: tiny scene, {R}x{R} sky, S={S}, K={k}, {fmt}, "
+        f"{'exact density' if exact else 'Eq. 18 density'}")
     sc = sunny(scenes.tiny_shade(n_points=1001, seed=5), R, seed=R + S)
     sc = dataclasses.replace(sc, n_dirs=S, seed=11)
     if fmt == "f16":
         sc.texels = sc.texels.astype(np.float16)
-    rgb, irr = gpu_envis(sc, k=k)
+    rgb, irr = gpu_envis(sc, k=k, exact=exact)
     idx, w = oracle_knn(sc, k)
-    ref, rirr = oracle.shade_envis(sc, idx, w, irradiance=True)
+    ref, rirr = oracle.shade_envis(sc, idx, w, irradiance=True, exact=exact)
     assert report("envis rgb", parity_err(rgb, ref)) <= TOL
     assert report("envis irradiance", parity_err(irr, rirr)) <= TOL
 
@@ -69,17 +71,19 @@ def test_envis_with_given_neighbours_is_identical(torch_gpu):
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
-def test_envis_object_workload_sampled(torch_gpu):
+@pytest.mark.parametrize("exact", [False, True])
+def test_envis_object_workload_sampled(torch_gpu, exact):
     """The object workload (200k points, 4096 probes of 32x32, K = 8, S = 128) under a
     256x256 sky in one launch; 300 points checked on the oracle with their indices in the
     full set (the draws are keyed by the point index)."""
-    log("environment sampler at object scale: 200k points, 256x256 sky; 300 on the oracle")
+    log("environment sampler at object scale: 200k points, 256x256 sky; 300 on the oracle; "
+        f"{'exact density' if exact else 'Eq. 18 density'}")
     sc = sunny(scenes.object_scene(), 256, seed=2, sigma=1.5)
-    rgb, irr = gpu_envis(sc)
+    rgb, irr = gpu_envis(sc, exact=exact)
     rows = np.sort(np.random.default_rng(12).choice(sc.n, 300, replace=False))
     sub = sc.subset(rows)
     idx, w = oracle_knn(sub)
-    ref, rirr = oracle.shade_envis(sub, idx, w, ids=rows, irradiance=True)
+    ref, rirr = oracle.shade_envis(sub, idx, w, ids=rows, irradiance=True, exact=exact)
     assert report("envis object rgb", parity_err(rgb[rows], ref)) <= TOL
     assert report("envis object irradiance", parity_err(irr[rows], rirr)) <= TOL
 

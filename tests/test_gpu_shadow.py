@@ -57,7 +57,7 @@ def compare(label, got, ref):
     return max(e, report(f"{label} irradiance", parity_err(got[1], ref["irr"])))
 
 
-@pytest.mark.parametrize("sampler", [0, 1])
+@pytest.mark.parametrize("sampler", [0, 1, 2])
 def test_shadow_small_scene(torch_gpu, sampler):
     log(f"shadow: 48 probes 8x8, 333 ground points, 16x16 sky, S=64, K=4, sampler {sampler}")
     sc = small_scene()
@@ -65,7 +65,7 @@ def test_shadow_small_scene(torch_gpu, sampler):
 
 
 @pytest.mark.parametrize("S", [16, 32])
-@pytest.mark.parametrize("sampler", [0, 1])
+@pytest.mark.parametrize("sampler", [0, 1, 2])
 def test_shadow_lane_groups(torch_gpu, S, sampler):
     """S <= 32 runs 64/S-ish points per wavefront (16 or 32 lanes each); 333 points leave a
     ragged last wavefront."""
@@ -93,7 +93,7 @@ def test_shadow_edge_cases(torch_gpu):
     log("shadow: black sky, S=1, 2x2 sky, no points")
     sc = small_scene(n_points=40, seed=5)
     black = np.zeros_like(sc.env)
-    for sampler in (0, 1):
+    for sampler in (0, 1, 2):
         r, irr = gpu_shadow(sc, sampler, env=black)
         assert np.all(r == 1.0) and np.all(irr == 0.0)
     for sampler in (0, 1):
@@ -108,7 +108,7 @@ def test_shadow_edge_cases(torch_gpu):
     assert r.shape == (0, 3)
 
 
-@pytest.mark.parametrize("sampler", [0, 1])
+@pytest.mark.parametrize("sampler", [0, 1, 2])
 def test_shadow_full_size_sampled(torch_gpu, sampler):
     """The full workload in one launch (500k ground points, 2048 probes of 32x32, 256x256
     sky, S=64, K=8) as the benchmark runs it; 64 sampled points on the oracle."""
