@@ -93,6 +93,9 @@ def main() -> int:
                          "(1 warm-up + 3 timed calls; for kernel traces of that path)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only the device-rate microbenchmarks (libsop_peaks.so): HBM copy, "
+                         "FP32/FP64 FMA, float atomics, LDS and global gathers")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -109,6 +112,8 @@ def main() -> int:
     dev = torch.device("cuda", 0)
     if args.copy_calibration:
         return copy_calibration(torch, dev)
+    if args.peaks:
+        return peaks()
     if args.trace_only:
         return trace_only(torch, dev, sop, scenes)
     if args.shadow_only:
@@ -973,6 +978,27 @@ def trace_only(torch, dev, sop, scenes) -> int:
     print(json.dumps({"traced_shade_ms": round(ms, 3), "points": sc.n, "dirs": sc.n_dirs,
                       "gaussians": gs.count,
                       "rays_per_s": round(sc.n * sc.n_dirs / (ms * 1e-3))}), flush=True)
+    return 0
+
+
+def peaks() -> int:
+    """Device-rate microbenchmarks (paper_2510_07729_amd/csrc/peaks.hip), each the mean of
+    20 launches after one warm-up; prints one JSON line per benchmark."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2510_07729_amd", "libsop_peaks.so"))
+    lib.sop_peak_name.restype = C.c_char_p
+    lib.sop_peak_unit.restype = C.c_char_p
+    lib.sop_peak_run.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]
+    for w in range(lib.sop_peak_count()):
+        rate, ms = C.c_double(), C.c_double()
+        rc = lib.sop_peak_run(w, 20, C.byref(rate), C.byref(ms))
+        if rc != 0:
+            print(json.dumps({"peak": lib.sop_peak_name(w).decode(), "error": rc}), flush=True)
+            return 1
+        print(json.dumps({"peak": lib.sop_peak_name(w).decode(), "rate": round(rate.value, 2),
+                          "unit": lib.sop_peak_unit(w).decode(),
+                          "ms_per_launch": round(ms.value, 4)}), flush=True)
     return 0
 
 

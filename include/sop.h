@@ -598,7 +598,9 @@ sop_status sop_shade_noalloc(const sop_plan* plan, const sop_probe_maps* maps,
 /* ----------------------------------------------------------------------------------------
  * Misc
  * --------------------------------------------------------------------------------------*/
-const char* sop_status_string(sop_status s);
+/* Text of a status code; any int is accepted (values that name no status give
+ * "unknown status"), so the parameter is an int rather than the enum. */
+const char* sop_status_string(int status);
 const char* sop_last_error(void);
 int32_t     sop_version(void);          /* major*10000 + minor*100 + patch */
 

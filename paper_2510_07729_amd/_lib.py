@@ -9,7 +9,9 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsop.so")
+# SOP_LIBRARY names another build of the same library to load instead (for instance one
+# whose host code carries sanitizers); it must exist like the in-tree one.
+LIB_PATH = os.environ.get("SOP_LIBRARY") or os.path.join(HERE, "libsop.so")
 
 c_i32, c_i64, c_u32, c_f32, c_vp = C.c_int32, C.c_int64, C.c_uint32, C.c_float, C.c_void_p
 

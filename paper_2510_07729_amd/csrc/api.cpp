@@ -1493,8 +1493,8 @@ extern "C" sop_status sop_shade_noalloc(const sop_plan* plan, const sop_probe_ma
 }
 
 // ------------------------------------------------------------------------------------------
-extern "C" const char* sop_status_string(sop_status s) {
-  switch (s) {
+extern "C" const char* sop_status_string(int status) {
+  switch (status) {
     case SOP_OK: return "ok";
     case SOP_ERR_INVALID_ARGUMENT: return "invalid argument";
     case SOP_ERR_UNSUPPORTED: return "unsupported";

@@ -26,9 +26,13 @@ def _slice(p: sop.Points, a: int, b: int) -> sop.Points:
 def train(mlp: sop.Mlp, plan: sop.Plan, texels: torch.Tensor, env: torch.Tensor,
           pool: sop.Points, steps: int, batch: int = 4096, lr: float = 2e-3,
           samples_per_bin: int = 1, k: int = 4, seed: int = 0,
-          log_every: int = 0) -> List[float]:
+          log_every: int = 0, start: int = 0, stop: Optional[int] = None) -> List[float]:
     """Online training on `pool` (view-mode points in random order). Learning rate follows a
-    cosine decay from lr to 0. Returns the losses read back every `log_every` steps."""
+    cosine decay from lr to 0 over `steps`. Iterations start .. min(stop, steps) - 1 run: a
+    run stopped after iteration i and saved (Mlp.save) resumes with start = i + 1 and
+    continues bit for bit, since a step's batch, seed and learning rate depend only on its
+    iteration number.
+    Returns the losses read back every `log_every` steps."""
     if pool.view is None:
         raise ValueError("the training pool needs per-point view directions")
     n = pool.n
@@ -41,7 +45,7 @@ def train(mlp: sop.Mlp, plan: sop.Plan, texels: torch.Tensor, env: torch.Tensor,
                          dev)
     ws_t = sop.proposal_workspace(L.SOP_OP_PROPOSAL_TRAIN, batch, dev)
     out: List[float] = []
-    for it in range(steps):
+    for it in range(start, steps if stop is None else min(stop, steps)):
         a = (it % per_epoch) * batch
         sub = _slice(pool, a, a + batch)
         sop.sop_dump_integrand(plan, texels, env, sub, samples_per_bin, k=k,

@@ -465,6 +465,37 @@ class Mlp:
         self.step = 0
         self._lib = L.load()
 
+    def save(self, path: str, **meta) -> None:
+        """Checkpoint: parameters, Adam moments and step count, and the feature box, in a
+        safetensors file (extra string metadata, e.g. the training iteration, is kept)."""
+        from safetensors.torch import save_file
+        info = {"step": str(self.step), "bounds_lo": repr(self.lo), "bounds_hi": repr(self.hi)}
+        info.update({str(k): str(v) for k, v in meta.items()})
+        save_file({"params": self.params.detach().cpu().contiguous(),
+                   "adam_m": self.m.detach().cpu().contiguous(),
+                   "adam_v": self.v.detach().cpu().contiguous()}, path, metadata=info)
+
+    @classmethod
+    def load(cls, path: str, device=None):
+        """A checkpoint written by save(): returns (mlp, metadata dict). Training resumed
+        from it continues bit for bit (the same steps, moments and bias corrections)."""
+        import ast
+
+        from safetensors import safe_open
+        with safe_open(path, framework="pt") as f:
+            meta = dict(f.metadata() or {})
+            t = {k: f.get_tensor(k) for k in ("params", "adam_m", "adam_v")}
+        for k, x in t.items():
+            if x.dtype != torch.float32 or x.numel() != L.SOP_MLP_PARAMS:
+                raise ValueError(f"checkpoint tensor {k} is not float32[{L.SOP_MLP_PARAMS}]")
+        dev = device if device is not None else "cpu"
+        mlp = cls(t["params"].to(dev), ast.literal_eval(meta["bounds_lo"]),
+                  ast.literal_eval(meta["bounds_hi"]))
+        mlp.m = t["adam_m"].to(dev)
+        mlp.v = t["adam_v"].to(dev)
+        mlp.step = int(meta["step"])
+        return mlp, meta
+
     def c(self) -> L.sop_mlp:
         m = L.sop_mlp()
         m.params = _ptr(self.params, torch.float32, "params")

@@ -208,3 +208,19 @@ def test_placement_and_loss_validation():
     assert lib.sop_lam_loss(None, 0x1000, 4, 0x2000, None, None, 0x10000, big,
                             None) == L.SOP_ERR_INVALID_ARGUMENT
     assert lib.sop_loss_workspace_size(-1) == 0
+
+
+def test_peaks_library_exports_and_names():
+    """The microbenchmark library (bench.py --peaks) loads and describes its benchmarks
+    without touching a device; an unknown benchmark is refused before any HIP call."""
+    lib = C.CDLL(os.path.join(ROOT, "paper_2510_07729_amd", "libsop_peaks.so"))
+    lib.sop_peak_name.restype = C.c_char_p
+    lib.sop_peak_unit.restype = C.c_char_p
+    n = lib.sop_peak_count()
+    assert n >= 10
+    names = [lib.sop_peak_name(i).decode() for i in range(n)]
+    assert len(set(names)) == n and all(names)
+    assert lib.sop_peak_unit(0) == b"GB/s" and lib.sop_peak_name(n) == b""
+    rate, ms = C.c_double(), C.c_double()
+    assert lib.sop_peak_run(n, 1, C.byref(rate), C.byref(ms)) == -1
+    assert lib.sop_peak_run(0, 0, C.byref(rate), C.byref(ms)) == -1

@@ -380,3 +380,28 @@ def test_fused_network_sampler_matches_oracle(torch_gpu, scene, n_active, S, k):
     torch.cuda.synchronize()
     assert report("fused vs oracle rgb", parity_err(rgb.cpu().numpy(), ref)) <= TOL
     assert report("fused vs oracle irradiance", parity_err(irr.cpu().numpy(), ref_e)) <= TOL
+
+
+def test_training_resumes_bit_for_bit_from_checkpoint(torch_gpu, tmp_path):
+    """A training run stopped after 6 of 12 steps, saved, loaded into a fresh network and
+    resumed ends with the same parameters, Adam moments and step count, bit for bit, as
+    the run that was never interrupted."""
+    from paper_2510_07729_amd import proposal
+    sc = scenes.proposal_eval(16_384, seed=3)
+    plan = gpu_plan(sc)
+    tex, env, pool = dev(sc.texels), dev(sc.env), gpu_points(sc)
+    init = scenes.mlp_init(seed=1)
+    whole = sop().Mlp(dev(init), sc.bounds_lo, sc.bounds_hi)
+    proposal.train(whole, plan, tex, env, pool, 12, batch=4096, lr=2e-3, seed=9)
+    part = sop().Mlp(dev(init), sc.bounds_lo, sc.bounds_hi)
+    proposal.train(part, plan, tex, env, pool, 12, batch=4096, lr=2e-3, seed=9, stop=6)
+    path = str(tmp_path / "proposal.safetensors")
+    part.save(path, iteration=6)
+    resumed, meta = sop().Mlp.load(path, device="cuda")
+    assert int(meta["iteration"]) == 6 and resumed.step == 6
+    proposal.train(resumed, plan, tex, env, pool, 12, batch=4096, lr=2e-3, seed=9, start=6)
+    torch_gpu.cuda.synchronize()
+    assert resumed.step == whole.step == 12
+    for a, b in ((resumed.params, whole.params), (resumed.m, whole.m), (resumed.v, whole.v)):
+        assert torch_gpu.equal(a, b)
+    assert not torch_gpu.equal(resumed.params, dev(init))
