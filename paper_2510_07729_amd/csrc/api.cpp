@@ -763,7 +763,7 @@ size_t proposal_ws(sop_op op, int64_t n) {
   Bump b{nullptr, 0, 0};
   (void)b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
   if (op == SOP_OP_PROPOSAL_TRAIN) {
-    const size_t ld = (size_t)((n + 15) / 16) * 16;
+    const size_t ld = (size_t)((n + 31) / 32) * 32;   // the weight-gradient GEMM takes K in 32s
     (void)b.take<uint16_t>((size_t)SOP_MLP_IN * ld);
     for (int i = 0; i < 4; ++i) (void)b.take<uint16_t>((size_t)SOP_MLP_HIDDEN * ld);
     (void)b.take<uint16_t>((size_t)SOP_MLP_BINS * ld);
@@ -847,7 +847,7 @@ extern "C" sop_status sop_proposal_train_step(const sop_mlp* mlp, const sop_poin
   const hipStream_t s = (hipStream_t)stream;
   Bump b{(char*)ws, 0, ws_bytes};
   sopk::MlpArgs a = mlp_args(mlp, pts);
-  const size_t ld = (size_t)((pts->count + 15) / 16) * 16;
+  const size_t ld = (size_t)((pts->count + 31) / 32) * 32;   // K steps of 32 in the weight gradients
   uint16_t* frags = b.take<uint16_t>(sopk::mlp_frag_bytes() / sizeof(uint16_t));
   a.frags = frags;
   a.xT = b.take<uint16_t>((size_t)SOP_MLP_IN * ld);

@@ -16,16 +16,29 @@ constexpr int kOffB3 = kOffW3 + kHid * kBins;
 static_assert(kOffB3 + kBins == SOP_MLP_PARAMS, "parameter layout");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// fragment sets (in fragments of 256 bf16): forward A operands W^T per (m-block, k-block),
+// Products run on v_mfma_f32_16x16x32_bf16: a 16 x 32 A block times a 32 x 16 B block, each
+// lane holding 8 consecutive positions of K (positions 8(l/16) .. +7). The accumulator of a
+// 16-row block holds rows 4(l/16) .. +3 in lane l, so the next layer's B operand for the
+// 32 inputs 32 kb .. 32 kb + 31 is the lane's 4 values of block 2 kb followed by its 4 of
+// block 2 kb + 1: K position 8 g + j stands for input 32 kb + 4 g + j (j < 4) or
+// 32 kb + 16 + 4 g + j - 4 (j >= 4). The A fragments are laid out in the same order.
+__device__ __forceinline__ int kpos_input(int kb, int g, int j) {
+  return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// fragment sets (in fragments of 512 bf16): forward A operands W^T per (m-block, k-block),
 // backward A operands W per (m-block = input block, k-block = output block)
-constexpr int kF1 = 0;                    // W1^T: 4 x 20
-constexpr int kF2 = kF1 + 4 * 20;         // W2^T: 4 x 4
-constexpr int kF3 = kF2 + 4 * 4;          // W3^T: 16 x 4
-constexpr int kB3 = kF3 + 16 * 4;         // W3:   4 x 16
-constexpr int kB2 = kB3 + 4 * 16;         // W2:   4 x 4
-constexpr int kFrags = kB2 + 4 * 4;       // 240 fragments
+constexpr int kF1 = 0;                    // W1^T: 4 x 10
+constexpr int kF2 = kF1 + 4 * 10;         // W2^T: 4 x 2
+constexpr int kF3 = kF2 + 4 * 2;          // W3^T: 16 x 2
+constexpr int kB3 = kF3 + 16 * 2;         // W3:   4 x 8
+constexpr int kB2 = kB3 + 4 * 8;          // W2:   4 x 2
+constexpr int kFrags = kB2 + 4 * 2;       // 120 fragments
+constexpr int kFragElems = 512;
 
 __device__ __forceinline__ uint16_t f2bf(float x) {
   uint32_t u = __float_as_uint(x);
@@ -35,8 +48,14 @@ __device__ __forceinline__ uint16_t f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// B operand of a 32-input block from the lane's fragments of its two 16-row halves
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+  const bf16x8s v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
 }
 
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
@@ -48,8 +67,9 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
   return r;
 }
 
-__device__ __forceinline__ bf16x4 load_frag(const uint16_t* frags, int f, int lane) {
-  return *reinterpret_cast<const bf16x4*>(frags + ((size_t)f * 64 + lane) * 4);
+__device__ __forceinline__ bf16x8 load_frag(const uint16_t* frags, int f, int lane) {
+  return __builtin_bit_cast(
+      bf16x8, *reinterpret_cast<const bf16x8s*>(frags + ((size_t)f * 64 + lane) * 8));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -119,14 +139,18 @@ __device__ __forceinline__ void forward_tile(const float* params, const uint16_t
 #pragma unroll
     for (int t = 0; t < 4; ++t) F.z1[mb][t] = params[kOffB1 + 16 * mb + 4 * g + t];
 #pragma unroll
-  for (int kb = 0; kb < 20; ++kb) {        // fully unrolled: fi.x[kb >> 1] stays in registers
-    const bf16x4 b = feature_frag(fi, kb, g);
+  for (int kb = 0; kb < 10; ++kb) {        // fully unrolled: fi.x[kb] stays in registers
+    const bf16x4 b0 = feature_frag(fi, 2 * kb, g), b1 = feature_frag(fi, 2 * kb + 1, g);
     if (store) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) xT[(size_t)(16 * kb + 4 * g + t) * ldT + col] = (uint16_t)b[t];
+      for (int t = 0; t < 4; ++t) {
+        xT[(size_t)(32 * kb + 4 * g + t) * ldT + col] = (uint16_t)b0[t];
+        xT[(size_t)(32 * kb + 16 + 4 * g + t) * ldT + col] = (uint16_t)b1[t];
+      }
     }
+    const bf16x8 b = cat8(b0, b1);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) F.z1[mb] = mfma16(load_frag(frags, kF1 + mb * 20 + kb, lane), b, F.z1[mb]);
+    for (int mb = 0; mb < 4; ++mb) F.z1[mb] = mfma32(load_frag(frags, kF1 + mb * 10 + kb, lane), b, F.z1[mb]);
   }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -137,10 +161,12 @@ __device__ __forceinline__ void forward_tile(const float* params, const uint16_t
 #pragma unroll
     for (int t = 0; t < 4; ++t) F.z2[mb][t] = params[kOffB2 + 16 * mb + 4 * g + t];
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
+  for (int kb = 0; kb < 2; ++kb) {
+    const bf16x8 b = cat8(F.h1[2 * kb], F.h1[2 * kb + 1]);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
-      F.z2[mb] = mfma16(load_frag(frags, kF2 + mb * 4 + kb, lane), F.h1[kb], F.z2[mb]);
+      F.z2[mb] = mfma32(load_frag(frags, kF2 + mb * 2 + kb, lane), b, F.z2[mb]);
+  }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
     F.h2[mb] = pack4(fmaxf(F.z2[mb][0], 0.0f), fmaxf(F.z2[mb][1], 0.0f), fmaxf(F.z2[mb][2], 0.0f),
@@ -150,10 +176,12 @@ __device__ __forceinline__ void forward_tile(const float* params, const uint16_t
 #pragma unroll
     for (int t = 0; t < 4; ++t) F.z3[mb][t] = params[kOffB3 + 16 * mb + 4 * g + t];
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
+  for (int kb = 0; kb < 2; ++kb) {
+    const bf16x8 b = cat8(F.h2[2 * kb], F.h2[2 * kb + 1]);
 #pragma unroll
     for (int mb = 0; mb < 16; ++mb)
-      F.z3[mb] = mfma16(load_frag(frags, kF3 + mb * 4 + kb, lane), F.h2[kb], F.z3[mb]);
+      F.z3[mb] = mfma32(load_frag(frags, kF3 + mb * 2 + kb, lane), b, F.z3[mb]);
+  }
 }
 
 // max and sum over the 4 lanes that hold one point's logits (lanes r, r+16, r+32, r+48)

@@ -4,12 +4,13 @@
 // Eq. 7 (ComGS Sec. 3.1.2): the network's bin distribution is what the proposal sampler of
 // shade.hip draws from.
 //
-// Matrix products run on v_mfma_f32_16x16x16_bf16 in a transposed formulation, z^T = W^T x^T:
+// Matrix products run on v_mfma_f32_16x16x32_bf16 in a transposed formulation, z^T = W^T x^T:
 // the output neurons are the M dimension and 16 points are the N dimension, so the
-// accumulator of one layer (lane l holds rows 4(l/16)..+3 of column l%16) is, after bias,
-// ReLU and rounding, exactly the B operand of the next layer (lane l holds k = 4(l/16)..+3
-// of column l%16); no shuffles or LDS round trips between layers. Weights are pre-arranged
-// once per call into operand fragments (64 lanes x 4 bf16 = 512 B, one coalesced load).
+// accumulators of one layer (lane l holds rows 4(l/16)..+3 of column l%16), after bias,
+// ReLU and rounding, are the B operands of the next layer (two 16-row blocks per 32-input
+// block, in the K order of mlp_device.hpp); no shuffles or LDS round trips between layers.
+// Weights are pre-arranged once per call into operand fragments (64 lanes x 8 bf16 = 1 KB,
+// one coalesced load).
 // Weight gradients contract over points, so they use activations stored transposed
 // ([feature][point]) and are a plain GEMM in which each wavefront owns one 16x16 tile of a
 // weight matrix (deterministic, no atomics).
@@ -23,25 +24,25 @@ namespace sopk {
 __global__ __launch_bounds__(256) void k_mlp_frags(const float* __restrict__ P,
                                                    uint16_t* __restrict__ frags) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= kFrags * 256) return;
-  const int f = e >> 8, lane = (e >> 2) & 63, t = e & 3;
+  if (e >= kFrags * kFragElems) return;
+  const int f = e / kFragElems, lane = (e >> 3) & 63, j = e & 7;
   const int g = lane >> 4, r = lane & 15;
   int src;
-  if (f < kF2) {                 // W1^T[out][in]: A[m = out 16mb + r][k = in 16kb + 4g + t]
-    const int mb = (f - kF1) / 20, kb = (f - kF1) % 20;
-    src = kOffW1 + (16 * kb + 4 * g + t) * kHid + 16 * mb + r;
+  if (f < kF2) {                 // W1^T[out][in]: A[m = out 16mb + r][k = in]
+    const int mb = (f - kF1) / 10, kb = (f - kF1) % 10;
+    src = kOffW1 + kpos_input(kb, g, j) * kHid + 16 * mb + r;
   } else if (f < kF3) {
-    const int mb = (f - kF2) / 4, kb = (f - kF2) % 4;
-    src = kOffW2 + (16 * kb + 4 * g + t) * kHid + 16 * mb + r;
+    const int mb = (f - kF2) / 2, kb = (f - kF2) % 2;
+    src = kOffW2 + kpos_input(kb, g, j) * kHid + 16 * mb + r;
   } else if (f < kB3) {
-    const int mb = (f - kF3) / 4, kb = (f - kF3) % 4;
-    src = kOffW3 + (16 * kb + 4 * g + t) * kBins + 16 * mb + r;
-  } else if (f < kB2) {          // W3[in][out]: A[m = in 16mb + r][k = out 16kb + 4g + t]
-    const int mb = (f - kB3) / 16, kb = (f - kB3) % 16;
-    src = kOffW3 + (16 * mb + r) * kBins + 16 * kb + 4 * g + t;
+    const int mb = (f - kF3) / 2, kb = (f - kF3) % 2;
+    src = kOffW3 + kpos_input(kb, g, j) * kBins + 16 * mb + r;
+  } else if (f < kB2) {          // W3[in][out]: A[m = in 16mb + r][k = out]
+    const int mb = (f - kB3) / 8, kb = (f - kB3) % 8;
+    src = kOffW3 + (16 * mb + r) * kBins + kpos_input(kb, g, j);
   } else {
-    const int mb = (f - kB2) / 4, kb = (f - kB2) % 4;
-    src = kOffW2 + (16 * mb + r) * kHid + 16 * kb + 4 * g + t;
+    const int mb = (f - kB2) / 2, kb = (f - kB2) % 2;
+    src = kOffW2 + (16 * mb + r) * kHid + kpos_input(kb, g, j);
   }
   frags[e] = f2bf(P[src]);
 }
@@ -96,7 +97,7 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t p0 = tile * 16;
-  if (p0 >= a.ldT) return;                        // ldT = batch rounded up to 16
+  if (p0 >= a.ldT) return;                        // ldT = batch rounded up to 32
   const int64_t p = p0 + r;
   const bool valid = p < a.n;
   const int64_t col = p;
@@ -165,9 +166,11 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int kb = 0; kb < 16; ++kb)
+  for (int kb = 0; kb < 8; ++kb) {
+    const bf16x8 b = cat8(d3[2 * kb], d3[2 * kb + 1]);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma16(load_frag(a.frags, kB3 + mb * 16 + kb, lane), d3[kb], acc[mb]);
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma32(load_frag(a.frags, kB3 + mb * 8 + kb, lane), b, acc[mb]);
+  }
   bf16x4 d2[4];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
@@ -187,9 +190,11 @@ __global__ __launch_bounds__(256) void k_mlp_train(MlpArgs a) {
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int kb = 0; kb < 4; ++kb)
+  for (int kb = 0; kb < 2; ++kb) {
+    const bf16x8 b = cat8(d2[2 * kb], d2[2 * kb + 1]);
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma16(load_frag(a.frags, kB2 + mb * 4 + kb, lane), d2[kb], acc[mb]);
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = mfma32(load_frag(a.frags, kB2 + mb * 2 + kb, lane), b, acc[mb]);
+  }
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
     float dz[4];
@@ -236,13 +241,15 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(MlpArgs a) {
     else *a.loss = sum;
     return;
   }
-  const uint16_t* arow = A + (size_t)(16 * mi + r) * a.ldT + 4 * g;
-  const uint16_t* brow = B + (size_t)(16 * no + r) * a.ldT + 4 * g;
+  // K = points: lane l takes points 8(l/16) .. +7 of each 32-point step (ldT is a multiple
+  // of 32, padding points are zero)
+  const uint16_t* arow = A + (size_t)(16 * mi + r) * a.ldT + 8 * g;
+  const uint16_t* brow = B + (size_t)(16 * no + r) * a.ldT + 8 * g;
   f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int64_t ks = 0; ks < a.ldT; ks += 16) {
-    const bf16x4 av = *reinterpret_cast<const bf16x4*>(arow + ks);
-    const bf16x4 bv = *reinterpret_cast<const bf16x4*>(brow + ks);
-    acc = mfma16(av, bv, acc);
+  for (int64_t ks = 0; ks < a.ldT; ks += 32) {
+    const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const bf16x8s*>(arow + ks));
+    const bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const bf16x8s*>(brow + ks));
+    acc = mfma32(av, bv, acc);
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) a.grad[off + (16 * mi + 4 * g + t) * out_w + 16 * no + r] = acc[t];
@@ -268,12 +275,12 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
 
 // ------------------------------------------------------------------------------------------
 hipError_t launch_mlp_frags(const float* params, uint16_t* frags, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_frags, dim3((kFrags * 256 + 255) / 256), dim3(256), 0, s, params,
-                     frags);
+  hipLaunchKernelGGL(k_mlp_frags, dim3((kFrags * kFragElems + 255) / 256), dim3(256), 0, s,
+                     params, frags);
   return hipGetLastError();
 }
 
-size_t mlp_frag_bytes() { return (size_t)kFrags * 256 * sizeof(uint16_t); }
+size_t mlp_frag_bytes() { return (size_t)kFrags * kFragElems * sizeof(uint16_t); }
 
 hipError_t launch_mlp_infer(const MlpArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;

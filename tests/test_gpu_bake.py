@@ -80,14 +80,24 @@ def test_bake_scale_and_distance_extremes(torch_gpu):
 
 
 def test_bake_object_scene_sampled(torch_gpu):
-    log("bake: object scene 100k Gaussians, 4096 probes at 32x32 (4.19M rays); 400 on oracle")
+    """The benchmarked launch: probes traced in the probe grid's Morton order (as the
+    benchmark step bakes), 4096 sampled rays against the brute-force oracle, and the same
+    bytes as the unordered launch."""
+    from paper_2510_07729_amd import sop
+    log("bake: object scene 100k Gaussians, 4096 probes at 32x32 (4.19M rays), Morton "
+        "order; 4096 rays on oracle")
     gs = scenes.object_gaussians()
     probes = scenes.object_probes()
-    _, tex, dep = gpu_bake(gs, probes, 32)
+    lo, hi = scenes.OBJECT_BOUNDS
+    plan, tex0, dep0 = gpu_bake(gs, probes, 32)
+    order = sop.Plan(dev(probes), lo, hi)
+    t, d = sop.sop_bake(plan, dev(probes), 32, order_by=order)
+    tex, dep = t.cpu().numpy(), d.cpu().numpy()
     assert np.all(np.isfinite(tex))
+    assert np.array_equal(tex, tex0) and np.array_equal(dep, dep0)
     rng = np.random.default_rng(2)
-    rp = rng.integers(0, probes.shape[0], 400).astype(np.int32)
-    rt = rng.integers(0, 32 * 32, 400).astype(np.int32)
+    rp = rng.integers(0, probes.shape[0], 4096).astype(np.int32)
+    rt = rng.integers(0, 32 * 32, 4096).astype(np.int32)
     assert compare(gs, probes, 32, tex, dep, rp, rt, "object") <= TOL
 
 
