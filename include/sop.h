@@ -262,6 +262,36 @@ sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_maps* maps,
                               float* g_metal, float* g_env, float* g_tex,
                               void* ws, size_t ws_bytes, sop_stream stream);
 
+/* Deterministic adjoint: the gradients of sop_shade_backward with g_env and g_tex that do
+ * not depend on how the work was scheduled, bit for bit equal from run to run (the per-point
+ * gradients of sop_shade_backward already are). Same arguments and semantics (g_env and
+ * g_tex accumulate, +=), plus `acc`, device scratch of acc_bytes >=
+ * sop_shade_backward_acc_size(plan's P, maps->res, env->height, env->width) bytes, 256-byte
+ * aligned, owned by the caller (its contents on entry do not matter; NULL is accepted only
+ * when g_env and g_tex are both NULL). Every contribution c to an output value is added
+ * exactly, as an integer multiple of 2^-96, into four 64-bit words per value (integer
+ * addition does not depend on order); the exact sum is rounded once (through FP64) and
+ * added to the value. Contributions with |c| < 2^-96 are dropped (the bits below 2^-96 of
+ * the others are truncated towards zero); a contribution with |c| >= 2^32 or not finite
+ * sets every g_env and g_tex value of the call to NaN. Up to 2^31 contributions per value.
+ * For callers that need reproducible gradients; it is slower than sop_shade_backward
+ * (64-bit atomics, up to two per contribution, and a final pass over the words).
+ * Errors as sop_shade_backward, plus SOP_ERR_WORKSPACE_TOO_SMALL for a short acc. */
+sop_status sop_shade_backward_deterministic(const sop_plan* plan, const sop_probe_maps* maps,
+                                            const sop_envmap* env, const sop_points* pts,
+                                            const sop_neighbors* nb,
+                                            const sop_shade_opts* opts, const float* grad_rgb,
+                                            float* g_albedo, float* g_rough, float* g_metal,
+                                            float* g_env, float* g_tex, void* ws,
+                                            size_t ws_bytes, void* acc, size_t acc_bytes,
+                                            sop_stream stream);
+
+/* Accumulator bytes of sop_shade_backward_deterministic for P probes of res x res texels and
+ * an env_height x env_width environment: 32 bytes per g_tex and g_env value plus alignment
+ * (0 on a negative argument). */
+size_t sop_shade_backward_acc_size(int32_t n_probes, int32_t res, int32_t env_height,
+                                   int32_t env_width);
+
 typedef enum sop_op {
   SOP_OP_KNN = 0,
   SOP_OP_QUERY = 1,

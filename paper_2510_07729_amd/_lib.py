@@ -111,6 +111,12 @@ SIGNATURES = {
     "sop_shade_backward": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap), P(sop_points),
                                    P(sop_neighbors), P(sop_shade_opts), c_vp, c_vp, c_vp, c_vp,
                                    c_vp, c_vp, c_vp, C.c_size_t, c_vp]),
+    "sop_shade_backward_deterministic": (c_i32, [c_vp, P(sop_probe_maps), P(sop_envmap),
+                                                 P(sop_points), P(sop_neighbors),
+                                                 P(sop_shade_opts), c_vp, c_vp, c_vp, c_vp,
+                                                 c_vp, c_vp, c_vp, C.c_size_t, c_vp,
+                                                 C.c_size_t, c_vp]),
+    "sop_shade_backward_acc_size": (C.c_size_t, [c_i32, c_i32, c_i32, c_i32]),
     "sop_workspace_size": (C.c_size_t, [c_vp, c_i32, c_i64, c_i32, c_i32, c_i32, c_i32, c_i32]),
     "sop_bake_plan_create": (c_i32, [P(sop_gaussians), P(sop_bake_opts), c_vp, P(c_vp)]),
     "sop_bake_plan_update": (c_i32, [c_vp, P(sop_gaussians), c_vp]),

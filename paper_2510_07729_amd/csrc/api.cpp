@@ -655,13 +655,33 @@ extern "C" sop_status sop_dump_integrand(const sop_plan* plan, const sop_probe_m
   return SOP_OK;
 }
 
-extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_maps* maps,
-                                         const sop_envmap* env, const sop_points* pts,
-                                         const sop_neighbors* nb, const sop_shade_opts* opts,
-                                         const float* grad_rgb, float* g_albedo,
-                                         float* g_rough, float* g_metal, float* g_env,
-                                         float* g_tex, void* ws, size_t ws_bytes,
-                                         sop_stream stream) {
+namespace {
+
+// Layout of the deterministic adjoint's accumulator: the texture words (4 per g_tex value),
+// the environment words (4 per g_env value), the flag; each region 256-byte aligned.
+struct DetLayout {
+  int64_t nt = 0, ne = 0;
+  size_t off_env = 0, off_flag = 0, bytes = 0;
+};
+
+bool det_layout(int64_t P, int32_t res, int32_t env_h, int32_t env_w, DetLayout* d) {
+  if (P < 0 || res < 0 || env_h < 0 || env_w < 0) return false;
+  d->nt = P * (int64_t)res * res * 4;
+  d->ne = (int64_t)env_h * env_w * 3;
+  const size_t a = 256;
+  d->off_env = ((size_t)d->nt * 4 * 8 + a - 1) / a * a;
+  d->off_flag = d->off_env + ((size_t)d->ne * 4 * 8 + a - 1) / a * a;
+  d->bytes = d->off_flag + a;
+  return true;
+}
+
+sop_status shade_backward_impl(const sop_plan* plan, const sop_probe_maps* maps,
+                               const sop_envmap* env, const sop_points* pts,
+                               const sop_neighbors* nb, const sop_shade_opts* opts,
+                               const float* grad_rgb, float* g_albedo, float* g_rough,
+                               float* g_metal, float* g_env, float* g_tex, void* ws,
+                               size_t ws_bytes, void* acc, size_t acc_bytes, bool det,
+                               sop_stream stream, const char* fn) {
   sop_status st = validate_shade(plan, maps, env, pts, nb, opts, false);
   if (st != SOP_OK) return st;
   if (pts->count > 0 && (!grad_rgb || !aligned(grad_rgb, 4)))
@@ -673,6 +693,16 @@ extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_m
   const size_t need = ws_needed(plan, SOP_OP_SHADE_BACKWARD, pts->count, k, nb != nullptr,
                                 opts->n_dirs, env->height, env->width);
   if ((st = validate_ws(ws, ws_bytes, need)) != SOP_OK) return st;
+  DetLayout dl;
+  if (det && (g_env || g_tex)) {
+    if (!det_layout(plan->P, maps->res, env->height, env->width, &dl))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "accumulator layout");
+    if (!acc || !aligned(acc, 256))
+      return fail(SOP_ERR_INVALID_ARGUMENT, "acc is NULL or not 256-byte aligned");
+    if (acc_bytes < dl.bytes)
+      return fail(SOP_ERR_WORKSPACE_TOO_SMALL,
+                  "acc smaller than sop_shade_backward_acc_size(P, res, env_h, env_w)");
+  }
   if (pts->count == 0) return SOP_OK;
   const hipStream_t s = (hipStream_t)stream;
   sopk::ShadeArgs a = base_args(plan, maps, pts);
@@ -689,8 +719,61 @@ extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_m
   if ((st = resolve_nb(plan, pts, nb, opts->k, opts->radius, b, s, &a.order, &a.nb_idx,
                        &a.nb_w, &kk)) != SOP_OK)
     return st;
-  SOP_HIP(sopk::launch_shade_bwd(a, kk, maps->format, s), "sop_shade_backward");
+  unsigned long long* wt = nullptr;
+  unsigned long long* we = nullptr;
+  int32_t* flag = nullptr;
+  if (det && (g_env || g_tex)) {
+    char* base = (char*)acc;
+    wt = reinterpret_cast<unsigned long long*>(base);
+    we = reinterpret_cast<unsigned long long*>(base + dl.off_env);
+    flag = reinterpret_cast<int32_t*>(base + dl.off_flag);
+    // zero the words in use and the flag (a fill kernel, no memset node)
+    if (g_tex)
+      SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(wt), 0, (size_t)dl.nt * 8, s), fn);
+    if (g_env)
+      SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(we), 0, (size_t)dl.ne * 8, s), fn);
+    SOP_HIP(sopk::launch_fill_i32(flag, 0, 1, s), fn);
+    a.det_tex = g_tex ? wt : nullptr;
+    a.det_env = g_env ? we : nullptr;
+    a.det_flag = flag;
+    a.det_nt = dl.nt;
+    a.det_ne = dl.ne;
+  }
+  SOP_HIP(sopk::launch_shade_bwd(a, kk, maps->format, s), fn);
+  if (det && g_tex) SOP_HIP(sopk::launch_det_finish(wt, dl.nt, flag, g_tex, s), fn);
+  if (det && g_env) SOP_HIP(sopk::launch_det_finish(we, dl.ne, flag, g_env, s), fn);
   return SOP_OK;
+}
+
+}  // namespace
+
+extern "C" sop_status sop_shade_backward(const sop_plan* plan, const sop_probe_maps* maps,
+                                         const sop_envmap* env, const sop_points* pts,
+                                         const sop_neighbors* nb, const sop_shade_opts* opts,
+                                         const float* grad_rgb, float* g_albedo,
+                                         float* g_rough, float* g_metal, float* g_env,
+                                         float* g_tex, void* ws, size_t ws_bytes,
+                                         sop_stream stream) {
+  return shade_backward_impl(plan, maps, env, pts, nb, opts, grad_rgb, g_albedo, g_rough,
+                             g_metal, g_env, g_tex, ws, ws_bytes, nullptr, 0, false, stream,
+                             "sop_shade_backward");
+}
+
+extern "C" size_t sop_shade_backward_acc_size(int32_t n_probes, int32_t res,
+                                              int32_t env_height, int32_t env_width) {
+  DetLayout dl;
+  if (!det_layout(n_probes, res, env_height, env_width, &dl)) return 0;
+  return dl.bytes;
+}
+
+extern "C" sop_status sop_shade_backward_deterministic(
+    const sop_plan* plan, const sop_probe_maps* maps, const sop_envmap* env,
+    const sop_points* pts, const sop_neighbors* nb, const sop_shade_opts* opts,
+    const float* grad_rgb, float* g_albedo, float* g_rough, float* g_metal, float* g_env,
+    float* g_tex, void* ws, size_t ws_bytes, void* acc, size_t acc_bytes, sop_stream stream) {
+  return shade_backward_impl(plan, maps, env, pts, nb, opts, grad_rgb, g_albedo, g_rough,
+                             g_metal, g_env, g_tex, ws, ws_bytes, acc, acc_bytes, true, stream,
+                             "sop_shade_backward_deterministic");
 }
 
 // ------------------------------------------------------------------------------------------

@@ -1037,20 +1037,74 @@ __device__ __forceinline__ void sample_adjoint(const ShadeArgs& a, const PointSt
   }
 }
 
+// Exact accumulation for the deterministic adjoint. A float v is m 2^e with an integer
+// m < 2^24, so v 2^96 is the integer m 2^(e+96) whenever e >= -96 (below that the bits under
+// 2^-96 are dropped, towards zero); for |v| < 2^32 it has at most 128 bits, and its 24
+// significant bits fall into at most two of the four 32-bit chunks k = 0..3. Each chunk is
+// added, with the sign of v, to the 64-bit word k of the value (integer addition: the order
+// of the additions does not change the sum; up to 2^31 terms per value fit). A value that
+// is not finite or has |v| >= 2^32 sets *flag instead.
+__device__ __forceinline__ void det_add(unsigned long long* words, int64_t n, int64_t i,
+                                        float v, int32_t* flag) {
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t ex = (b >> 23) & 0xFFu;
+  if (ex == 0xFFu) {
+    atomicOr(flag, 1);
+    return;
+  }
+  uint32_t m = b & 0x7FFFFFu;
+  int sh;
+  if (ex == 0) {
+    sh = -149 + 96;                   // subnormal: m 2^-149
+  } else {
+    m |= 0x800000u;
+    sh = (int)ex - 150 + 96;          // m 2^(ex - 150), times 2^96
+  }
+  if (m == 0) return;
+  if (sh > 104) {                     // |v| >= 2^32
+    atomicOr(flag, 1);
+    return;
+  }
+  if (sh < 0) {
+    if (sh <= -24) return;
+    m >>= -sh;
+    sh = 0;
+    if (m == 0) return;
+  }
+  const unsigned __int128 X = (unsigned __int128)m << sh;
+  const bool neg = (b >> 31) != 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned long long c = (unsigned long long)(uint32_t)(X >> (32 * k));
+    if (c) atomicAdd(words + (size_t)k * n + i, neg ? 0ull - c : c);
+  }
+}
+
+// adds v to value i of a gradient: a float atomic into out, or (DET) exactly into words
+template <bool DET>
+__device__ __forceinline__ void add_grad(float* out, unsigned long long* words, int64_t n,
+                                         int64_t i, float v, int32_t* flag) {
+  if constexpr (DET)
+    det_add(words, n, i, v, flag);
+  else
+    unsafeAtomicAdd(out + i, v);
+}
+
+template <bool DET = false>
 __device__ __forceinline__ void scatter_env(const ShadeArgs& a, const Sample& s,
                                             const SampleAdj& r) {
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    float* dst = a.g_env + (size_t)s.et.off[t] * 3;
-    unsafeAtomicAdd(dst + 0, s.et.w[t] * r.ge[0]);
-    unsafeAtomicAdd(dst + 1, s.et.w[t] * r.ge[1]);
-    unsafeAtomicAdd(dst + 2, s.et.w[t] * r.ge[2]);
+    const int64_t o = (int64_t)s.et.off[t] * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      add_grad<DET>(a.g_env, a.det_env, a.det_ne, o + c, s.et.w[t] * r.ge[c], a.det_flag);
   }
 }
 
 // General adjoint: one wavefront per point, texture gradients scattered with atomics.
 // Used when the grouped kernel below does not apply (res > 32, more than 16384 probes).
-template <int KT, typename TexT, bool EO = false>
+template <int KT, typename TexT, bool EO = false, bool DET = false>
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
   const int64_t wv = die_block() * kWavesPerBlock + wave_id_uniform();
   if (wv >= a.n) return;
@@ -1075,19 +1129,18 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
           const int32_t id = nb.id(s2, a, ps.p, k);
           if (id < 0) continue;
           const float wk = nb.wt(s2, a, ps.p, k);
-          float* GT = a.g_tex + (size_t)id * RR * 4;
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const float cw = wk * s.tt.w[t];
-            float* dst = GT + (size_t)s.tt.off[t] * 4;
-            unsafeAtomicAdd(dst + 0, cw * r.gl[0]);
-            unsafeAtomicAdd(dst + 1, cw * r.gl[1]);
-            unsafeAtomicAdd(dst + 2, cw * r.gl[2]);
-            unsafeAtomicAdd(dst + 3, cw * r.go);
+            const int64_t o = ((int64_t)id * (int64_t)RR + s.tt.off[t]) * 4;
+            add_grad<DET>(a.g_tex, a.det_tex, a.det_nt, o + 0, cw * r.gl[0], a.det_flag);
+            add_grad<DET>(a.g_tex, a.det_tex, a.det_nt, o + 1, cw * r.gl[1], a.det_flag);
+            add_grad<DET>(a.g_tex, a.det_tex, a.det_nt, o + 2, cw * r.gl[2], a.det_flag);
+            add_grad<DET>(a.g_tex, a.det_tex, a.det_nt, o + 3, cw * r.go, a.det_flag);
           }
         }
       }
-      if (a.g_env) scatter_env(a, s, r);
+      if (a.g_env) scatter_env<DET>(a, s, r);
     }
   }
   const float r0 = wave_sum(ga[0]) * a.scale, r1 = wave_sum(ga[1]) * a.scale,
@@ -1133,8 +1186,9 @@ struct EnvRun {
 
 // Stages the environment adjoint of the lanes [32h, 32h + 32) of the wavefront and adds it
 // to g_env; every lane of the wavefront calls it (lanes without a sample pass valid=false).
-__device__ __forceinline__ void env_runs_flush(float* g_env, EnvRun* run, int lane, int h,
-                                               bool valid, const Sample& s,
+template <bool DET = false>
+__device__ __forceinline__ void env_runs_flush(const ShadeArgs& a, EnvRun* run, int lane,
+                                               int h, bool valid, const Sample& s,
                                                const SampleAdj& r) {
   if ((lane >> 5) == h) {
 #pragma unroll
@@ -1161,7 +1215,8 @@ __device__ __forceinline__ void env_runs_flush(float* g_env, EnvRun* run, int la
     if (lane < 60 && q < kEnvRuns) {
       const EnvRun& e = run[q];
       if (e.b0 >= 0)
-        unsafeAtomicAdd(g_env + (comp < 3 ? e.b0 + comp : e.b1 + comp - 3), e.v[comp]);
+        add_grad<DET>(a.g_env, a.det_env, a.det_ne, comp < 3 ? e.b0 + comp : e.b1 + comp - 3,
+                      e.v[comp], a.det_flag);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1259,7 +1314,7 @@ __device__ __forceinline__ void splat_sorted(float* H, uint32_t* scr, int lane, 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int KT, typename TexT, bool EO = false>
+template <int KT, typename TexT, bool EO = false, bool DET = false>
 __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a, int32_t k) {
   extern __shared__ float lds[];
   const int MV = a.R * a.R * 4;                         // values per map
@@ -1351,8 +1406,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
           SampleAdj r;
           if (j < a.S) sample_adjoint<KT, TexT, EO>(a, ps, nb, k, j, g, ga, gr, gm, s, r);
           if (a.g_env) {
-            env_runs_flush(a.g_env, rb, lane, 0, j < a.S, s, r);
-            env_runs_flush(a.g_env, rb, lane, 1, j < a.S, s, r);
+            env_runs_flush<DET>(a, rb, lane, 0, j < a.S, s, r);
+            env_runs_flush<DET>(a, rb, lane, 1, j < a.S, s, r);
           }
           if (a.g_tex) splat_sorted(Hb, scr, lane, j < a.S, s, r, nkey, nbits);
         }
@@ -1393,11 +1448,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_shade_bwd_batched(ShadeArgs a
 #pragma unroll
       for (int i = 0; i < kVPT; ++i) acc[i] = fmaf(w, h[b][i], acc[i]);
     }
-    float* dst = a.g_tex + (size_t)uni[u] * MV;
+    const int64_t base = (int64_t)uni[u] * MV;
 #pragma unroll
     for (int i = 0; i < kVPT; ++i) {
       const int v = tid + kBatchThreads * i;
-      if (v < MV && acc[i] != 0.0f) unsafeAtomicAdd(dst + v, acc[i]);   // texels no sample reached stay untouched
+      // texels no sample reached stay untouched
+      if (v < MV && acc[i] != 0.0f)
+        add_grad<DET>(a.g_tex, a.det_tex, a.det_nt, base + v, acc[i], a.det_flag);
     }
   }
 }
@@ -1652,39 +1709,118 @@ size_t batched_lds_bytes(int32_t R) {
          (size_t)kMaxEntries * kBatch * 4 + 4 + 15 + (size_t)kBatch * kScratchWords * 4;
 }
 
-template <int KT, bool EO>
+template <int KT, bool EO, bool DET>
 static void launch_batched_kte(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   const dim3 grid((unsigned)((a.n + kBatch - 1) / kBatch));
   const size_t lds = batched_lds_bytes(a.R);
   // dynamic LDS above 64 KB must be allowed per kernel (gfx950 has 160 KB per CU)
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, uint2, EO>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, float4, EO>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, uint2, EO, DET>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_shade_bwd_batched<KT, float4, EO, DET>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (format == SOP_TEXEL_F16)
-    hipLaunchKernelGGL((k_shade_bwd_batched<KT, uint2, EO>), grid, dim3(kBatchThreads), lds, s,
-                       a, k);
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, uint2, EO, DET>), grid, dim3(kBatchThreads), lds,
+                       s, a, k);
   else
-    hipLaunchKernelGGL((k_shade_bwd_batched<KT, float4, EO>), grid, dim3(kBatchThreads), lds, s,
-                       a, k);
+    hipLaunchKernelGGL((k_shade_bwd_batched<KT, float4, EO, DET>), grid, dim3(kBatchThreads),
+                       lds, s, a, k);
 }
 
-template <int KT>
+template <int KT, bool DET>
 static void launch_batched_kt(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   if (a.env_oct)
-    launch_batched_kte<KT, true>(a, k, format, s);
+    launch_batched_kte<KT, true, DET>(a, k, format, s);
   else
-    launch_batched_kte<KT, false>(a, k, format, s);
+    launch_batched_kte<KT, false, DET>(a, k, format, s);
+}
+
+// general adjoint (res > 32 or K > 16) with exact accumulation
+template <int KT>
+static void launch_bwd_det_kt(const ShadeArgs& a, int32_t k, int32_t format, dim3 grid,
+                              hipStream_t s) {
+  if (a.env_oct) {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_bwd<KT, uint2, true, true>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_bwd<KT, float4, true, true>), grid, dim3(256), 0, s, a, k);
+  } else {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_bwd<KT, uint2, false, true>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_bwd<KT, float4, false, true>), grid, dim3(256), 0, s, a, k);
+  }
 }
 
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
-  if (a.R > kMaxRes || k > 16) return dispatch(false, a, k, format, s);
-  switch (k) {
-    case 4: launch_batched_kt<4>(a, k, format, s); break;
-    case 8: launch_batched_kt<8>(a, k, format, s); break;
-    default: launch_batched_kt<0>(a, k, format, s); break;
+  const bool det = a.det_tex != nullptr || a.det_env != nullptr;
+  if (det && (!a.det_flag || (a.g_tex && !a.det_tex) || (a.g_env && !a.det_env)))
+    return hipErrorInvalidValue;
+  if (a.R > kMaxRes || k > 16) {
+    if (!det) return dispatch(false, a, k, format, s);
+    const dim3 grid((unsigned)((a.n + kWavesPerBlock - 1) / kWavesPerBlock));
+    switch (k) {
+      case 4: launch_bwd_det_kt<4>(a, k, format, grid, s); break;
+      case 8: launch_bwd_det_kt<8>(a, k, format, grid, s); break;
+      default: launch_bwd_det_kt<0>(a, k, format, grid, s); break;
+    }
+    return hipGetLastError();
   }
+  switch (k) {
+    case 4:
+      det ? launch_batched_kt<4, true>(a, k, format, s) : launch_batched_kt<4, false>(a, k, format, s);
+      break;
+    case 8:
+      det ? launch_batched_kt<8, true>(a, k, format, s) : launch_batched_kt<8, false>(a, k, format, s);
+      break;
+    default:
+      det ? launch_batched_kt<0, true>(a, k, format, s) : launch_batched_kt<0, false>(a, k, format, s);
+      break;
+  }
+  return hipGetLastError();
+}
+
+// The exact sum held in the four words of value i: T = sum_k w_k 2^(32k) (signed words),
+// carried into four 32-bit limbs and a signed top, its magnitude converted through FP64
+// (a fixed sequence of operations: the same words always give the same float) and scaled
+// by 2^-96.
+__global__ __launch_bounds__(256) void k_det_finish(const unsigned long long* __restrict__ w,
+                                                    int64_t n, const int32_t* __restrict__ flag,
+                                                    float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (*flag) {
+    out[i] = __int_as_float(0x7FC00000);
+    return;
+  }
+  long long c = 0;
+  unsigned __int128 lo = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long long t = (long long)w[(size_t)k * n + i] + c;     // |w_k| < 2^63 - 2^32
+    lo |= (unsigned __int128)(uint32_t)t << (32 * k);
+    c = t >> 32;                                                    // floor
+  }
+  const bool neg = c < 0;
+  unsigned long long top = (unsigned long long)c;
+  if (neg) {                                                        // magnitude of c 2^128 + lo
+    top = (unsigned long long)(-(c + 1)) + (lo == 0 ? 1ull : 0ull);
+    lo = ~lo + 1;
+  }
+  const double mag = ((double)top * 0x1p64 + (double)(unsigned long long)(lo >> 64)) * 0x1p64 +
+                     (double)(unsigned long long)lo;
+  const double v = (neg ? -mag : mag) * 0x1p-96;
+  out[i] += (float)v;
+}
+
+hipError_t launch_det_finish(const unsigned long long* words, int64_t n, const int32_t* flag,
+                             float* out, hipStream_t s) {
+  if (n == 0 || !out) return hipSuccess;
+  if (!words || !flag) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_det_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, words, n,
+                     flag, out);
   return hipGetLastError();
 }
 

@@ -108,6 +108,12 @@ struct ShadeArgs {
   float* g_metal;
   float* g_env;
   float* g_tex;
+  // deterministic adjoint: exact accumulation of the texture and environment gradients in
+  // 64-bit words, word k of value i at [k * n + i] (NULL: float atomics into g_tex / g_env)
+  unsigned long long* det_tex;
+  unsigned long long* det_env;
+  int32_t* det_flag;        // set when a contribution cannot be represented
+  int64_t det_nt, det_ne;   // values of g_tex and of g_env
 };
 
 // learned proposal network (proposal.hip)
@@ -150,6 +156,9 @@ hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4*
                            hipStream_t s);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+// out[i] += the exact sum held in words[k * n + i] (k = 0..3), rounded once; NaN if *flag
+hipError_t launch_det_finish(const unsigned long long* words, int64_t n, const int32_t* flag,
+                             float* out, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // cast-shadow ratio: texel masses and prefix of an octahedral environment [T <= 2^20

@@ -373,9 +373,12 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
                        want=("albedo", "rough", "metal", "env", "tex"),
                        g_env: Optional[torch.Tensor] = None,
                        g_tex: Optional[torch.Tensor] = None,
-                       ws: Optional[torch.Tensor] = None):
+                       ws: Optional[torch.Tensor] = None, deterministic: bool = False,
+                       acc: Optional[torch.Tensor] = None):
     """Adjoint: dict of gradients. g_env/g_tex accumulate into the given tensors (zeroed
-    new ones otherwise); per-point gradients are fresh tensors."""
+    new ones otherwise); per-point gradients are fresh tensors. deterministic=True calls
+    sop_shade_backward_deterministic (g_env/g_tex exact sums, the same bits on every run);
+    acc is its accumulator (allocated when not given)."""
     dev = pts.pos.device
     n = pts.n
     pts.check()
@@ -408,6 +411,22 @@ def sop_shade_backward(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
     m, e, cp = _maps(texels, plan), _env(env), pts.c()
     nbc = nb.c(n) if nb is not None else None
     g = grad_rgb.contiguous()
+    if deterministic:
+        et = env.texels if isinstance(env, OctEnv) else env
+        need = plan._lib.sop_shade_backward_acc_size(int(plan.n_probes), int(texels.shape[1]),
+                                                     int(et.shape[0]), int(et.shape[1]))
+        if acc is None:
+            acc = workspace(need, dev)
+        elif acc.numel() < need:
+            raise ValueError(f"acc holds {acc.numel()} bytes, the call needs {need}")
+        L.check(plan._lib.sop_shade_backward_deterministic(
+            plan.handle, C.byref(m), C.byref(e), C.byref(cp),
+            C.byref(nbc) if nbc is not None else None, C.byref(o),
+            _ptr(g, torch.float32, "grad"), _ptr(out.get("albedo")), _ptr(out.get("rough")),
+            _ptr(out.get("metal")), _ptr(out.get("env")), _ptr(out.get("tex")), ws.data_ptr(),
+            ws.numel(), acc.data_ptr(), acc.numel(), _stream()),
+            "sop_shade_backward_deterministic")
+        return out
     L.check(plan._lib.sop_shade_backward(
         plan.handle, C.byref(m), C.byref(e), C.byref(cp),
         C.byref(nbc) if nbc is not None else None, C.byref(o), _ptr(g, torch.float32, "grad"),
