@@ -321,6 +321,26 @@ def main() -> int:
                                             out=rgb_p, net=mlp_obj, mix_eps=MIX_EPS))
     proposal_paths = {"two_call_ms": round(t_two, 4), "fused_ms": round(t_fused, 4)}
 
+    # the deterministic adjoint (exact accumulation of g_env and g_tex), outside the step:
+    # its time next to the step's adjoint, and that two runs give the same bits
+    acc = sop.workspace(L.load().sop_shade_backward_acc_size(P, R, int(env.shape[0]),
+                                                             int(env.shape[1])), dev)
+    ge_d, gt_d = torch.zeros_like(g_env), torch.zeros_like(g_tex)
+
+    def det_bwd():
+        ge_d.zero_()
+        gt_d.zero_()
+        return sop.sop_shade_backward(plan, tex, env, pts, grad, S, nb=nb_p, g_env=ge_d,
+                                      g_tex=gt_d, ws=ws_b, deterministic=True, acc=acc)
+    t_det = time_ms(det_bwd, reps=5)
+    first = (ge_d.clone(), gt_d.clone())
+    det_bwd()
+    torch.cuda.synchronize()
+    deterministic_bwd = {"ms": round(t_det, 4), "atomic_ms": round(phase["shade_bwd"], 4),
+                         "same_bits_twice": bool(torch.equal(first[0], ge_d)
+                                                 and torch.equal(first[1], gt_d))}
+    del first, ge_d, gt_d, acc
+
     trace = None
     if not args.no_trace_study:
         trace = trace_study(torch, sop, scenes, time_ms, bake_plan, plan, env, pts, tex, nb_p,
@@ -398,6 +418,7 @@ def main() -> int:
         "roofline": roof,
         "shade_roofline": shade_roof,
         "proposal_paths": proposal_paths,
+        "deterministic_bwd": deterministic_bwd,
         "frames_study": frames,
         "proposal_study_as_written": study_written,
         "proposal_study": study,
