@@ -76,6 +76,9 @@ def _sig(lib):
     lib.orc_shade.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr, dptr,
                               dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int, iptr, dptr,
                               C.c_int, C.c_int, u32, C.c_int, dptr, dptr]
+    lib.orc_shade_cosine.argtypes = lib.orc_shade.argtypes
+    lib.orc_direction_cos.restype = C.c_double
+    lib.orc_direction_cos.argtypes = [C.c_int, C.c_int, u32, dptr, dptr]
     lib.orc_shade_backward.argtypes = [C.c_long, dptr, dptr, dptr, dptr, C.c_long, dptr, dptr,
                                        dptr, dptr, C.c_int, dptr, C.c_int, C.c_int, C.c_int,
                                        iptr,
@@ -354,9 +357,10 @@ def _scene_args(sc, albedo=None, rough=None, metal=None, texels=None, env=None):
 
 
 def shade(sc, idx, w, albedo=None, rough=None, metal=None, texels=None, env=None,
-          n_dirs=None, seed=None, per_point=False, irradiance=False):
+          n_dirs=None, seed=None, per_point=False, irradiance=False, cosine=False):
     """Oracle shading of a ShadeScene (or a scene with overridden inputs) with neighbour
-    lists (idx, w) from :func:`knn`. Returns rgb [N,3] (and irradiance [N,3])."""
+    lists (idx, w) from :func:`knn`. Returns rgb [N,3] (and irradiance [N,3]). cosine=True
+    takes the cosine-weighted direction set (orc_shade_cosine)."""
     keep, a = _scene_args(sc, albedo, rough, metal, texels, env)
     idx, pi = _i(idx)
     w, pw = _d(w)
@@ -365,8 +369,9 @@ def shade(sc, idx, w, albedo=None, rough=None, metal=None, texels=None, env=None
     irr = np.zeros((N, 3)) if irradiance else None
     S = sc.n_dirs if n_dirs is None else n_dirs
     sd = sc.seed if seed is None else seed
-    lib().orc_shade(*a, pi, pw, idx.shape[1], S, sd, int(per_point),
-                    rgb.ctypes.data_as(dptr), irr.ctypes.data_as(dptr) if irradiance else None)
+    fn = lib().orc_shade_cosine if cosine else lib().orc_shade
+    fn(*a, pi, pw, idx.shape[1], S, sd, int(per_point),
+       rgb.ctypes.data_as(dptr), irr.ctypes.data_as(dptr) if irradiance else None)
     del keep
     return (rgb, irr) if irradiance else rgb
 

@@ -217,6 +217,23 @@ double orc_direction(int j, int S, uint32_t rho24, const double n[3], double w[3
   return ct;
 }
 
+/* Direction j of S of the cosine-weighted set: the same (xi1, phi) pairs as orc_direction,
+ * xi1 = (j+0.5)/S read as the squared radius on the unit disk and lifted to the hemisphere
+ * (Malley's method): sin(theta) = sqrt(xi1), cos(theta) = sqrt(1 - xi1), density
+ * cos(theta)/pi. Returns cos(theta). */
+double orc_direction_cos(int j, int S, uint32_t rho24, const double n[3], double w[3]) {
+  double xi1 = (j + 0.5) / S;
+  double st = sqrt(xi1);
+  double ct = sqrt(1.0 - xi1);
+  uint32_t u24 = ((orc_bitreverse32((uint32_t)j) >> 8) + rho24) & 0xFFFFFFu;
+  double phi = 2.0 * OR_PI * (double)u24 / 16777216.0;
+  double t[3], b[3];
+  orc_frame(n, t, b);
+  for (int c = 0; c < 3; ++c)
+    w[c] = t[c] * st * cos(phi) + b[c] * st * sin(phi) + n[c] * ct;
+  return ct;
+}
+
 /* ------------------------------------------------------------------------------------
  * BRDF (Eq. 6: the simplified Disney BRDF of Burley 2012; the form is not given, reading:
  * Lambert diffuse weighted by (1-m) plus the GGX microfacet lobe of Walter et al. 2007 with
@@ -404,10 +421,13 @@ static void point_view(const orc_points* p, long i, double v[3]) {
   }
 }
 
+/* One point's estimate of Eq. 7. cosine = 0: the uniform Hammersley set, rgb =
+ * (2 pi/S) sum f L_i cos; cosine = 1: the cosine-weighted set, whose density cos/pi turns
+ * the estimate into rgb = (pi/S) sum f L_i (irradiance (pi/S) sum L_i). */
 static void shade_point(const orc_points* pts, long i, const double* tex, int R,
                         const double* env, int H, int W, int env_oct, const int32_t* nb_idx,
                         const double* nb_w, int K, int S, uint32_t seed, int per_point,
-                        double rgb[3], double irr[3]) {
+                        int cosine, double rgb[3], double irr[3]) {
   double n[3], v[3], a[3];
   for (int c = 0; c < 3; ++c) { n[c] = pts->normal[3 * i + c]; a[c] = pts->albedo[3 * i + c]; }
   point_view(pts, i, v);
@@ -416,20 +436,21 @@ static void shade_point(const orc_points* pts, long i, const double* tex, int R,
   double acc[3] = {0, 0, 0}, acc_e[3] = {0, 0, 0};
   for (int j = 0; j < S; ++j) {
     double w[3];
-    double ct = orc_direction(j, S, rho, n, w);
+    double ct = cosine ? orc_direction_cos(j, S, rho, n, w) : orc_direction(j, S, rho, n, w);
     double Lenv[3], Lin[3], O, f[3];
     orc_env_fetch_any(env, H, W, env_oct, w, Lenv);
     orc_interp(tex, R, nb_idx, nb_w, K, w, Lin, &O);
     orc_brdf(n, v, w, a, r, m, f);
     for (int c = 0; c < 3; ++c) {
       double Li = (1.0 - O) * Lenv[c] + Lin[c];
-      acc[c] += f[c] * Li * ct;
-      acc_e[c] += Li * ct;
+      acc[c] += cosine ? f[c] * Li : f[c] * Li * ct;
+      acc_e[c] += cosine ? Li : Li * ct;
     }
   }
+  const double scale = cosine ? OR_PI / S : 2.0 * OR_PI / S;
   for (int c = 0; c < 3; ++c) {
-    rgb[c] = 2.0 * OR_PI / S * acc[c];
-    if (irr) irr[c] = 2.0 * OR_PI / S * acc_e[c];
+    rgb[c] = scale * acc[c];
+    if (irr) irr[c] = scale * acc_e[c];
   }
 }
 
@@ -442,7 +463,20 @@ void orc_shade(long N, const double* pos, const double* normal, const double* vi
 #pragma omp parallel for schedule(dynamic, 16)
   for (long i = 0; i < N; ++i)
     shade_point(&p, i, tex, R, env, H, W, env_oct, idx + i * K, w + i * K, K, S, seed, per_point,
-                rgb + 3 * i, irr ? irr + 3 * i : NULL);
+                0, rgb + 3 * i, irr ? irr + 3 * i : NULL);
+}
+
+/* orc_shade with the cosine-weighted direction set (orc_direction_cos). */
+void orc_shade_cosine(long N, const double* pos, const double* normal, const double* view,
+                      const double* cam, long ppf, const double* albedo, const double* rough,
+                      const double* metal, const double* tex, int R, const double* env, int H,
+                      int W, int env_oct, const int32_t* idx, const double* w, int K, int S,
+                      uint32_t seed, int per_point, double* rgb, double* irr) {
+  orc_points p = {N, pos, normal, view, cam, ppf, albedo, rough, metal};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long i = 0; i < N; ++i)
+    shade_point(&p, i, tex, R, env, H, W, env_oct, idx + i * K, w + i * K, K, S, seed, per_point,
+                1, rgb + 3 * i, irr ? irr + 3 * i : NULL);
 }
 
 /* ------------------------------------------------------------------------------------
