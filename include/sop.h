@@ -205,8 +205,11 @@ typedef enum sop_sampler {
   SOP_SAMPLER_ENV = 3,            /* environment importance sampling (Eq. 18) on an
                                      octahedral env: the draws and density of
                                      SOP_SHADOW_ENV (see sop_shadow_ratio)                  */
-  SOP_SAMPLER_ENV_EXACT = 4       /* the same draws weighted by their exact density, as
+  SOP_SAMPLER_ENV_EXACT = 4,      /* the same draws weighted by their exact density, as
                                      SOP_SHADOW_ENV_EXACT                                  */
+  SOP_SAMPLER_COSINE = 5          /* cosine-weighted Hammersley set: the pairs of the
+                                     uniform set lifted from the unit disk (Malley's method),
+                                     density cos(theta)/pi                                 */
 } sop_sampler;
 
 typedef struct sop_mlp sop_mlp;
@@ -228,6 +231,10 @@ typedef struct sop_shade_opts {
 } sop_shade_opts;
 
 /* Forward shading. Writes rgb[N,3] (and out_irradiance when set). nb may be NULL.
+ * With SOP_SAMPLER_COSINE (the cosine fallback next to the uniform set of Eq. 7) direction j
+ * has sin(theta_j) = sqrt((j+0.5)/S), cos(theta_j) = sqrt(1-(j+0.5)/S) and the azimuth of
+ * the uniform set's direction j (same rotation), and rgb_i = (pi/S) sum_j f(w_j) L_i(w_j),
+ * out_irradiance (pi/S) sum_j L_i(w_j); it has no adjoint (sop_shade_backward refuses it).
  * With SOP_SAMPLER_PROPOSAL the S directions of point i are drawn from its bin distribution
  * (see the learned direction proposal below) and rgb_i = (1/S) sum_j f L_i cos / pdf(w_j);
  * out_irradiance is then (1/S) sum_j L_i cos / pdf(w_j). With SOP_SAMPLER_PROPOSAL_NET the

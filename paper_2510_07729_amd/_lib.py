@@ -28,7 +28,7 @@ SOP_TEXEL_F16 = 1
 SOP_OP_KNN, SOP_OP_QUERY, SOP_OP_SHADE, SOP_OP_SHADE_BACKWARD = 0, 1, 2, 3
 SOP_OP_DUMP_INTEGRAND, SOP_OP_PROPOSAL_INFER, SOP_OP_PROPOSAL_TRAIN = 4, 5, 6
 SOP_SAMPLER_HAMMERSLEY, SOP_SAMPLER_PROPOSAL, SOP_SAMPLER_PROPOSAL_NET = 0, 1, 2
-SOP_SAMPLER_ENV, SOP_SAMPLER_ENV_EXACT = 3, 4
+SOP_SAMPLER_ENV, SOP_SAMPLER_ENV_EXACT, SOP_SAMPLER_COSINE = 3, 4, 5
 SOP_MLP_IN, SOP_MLP_HIDDEN, SOP_MLP_BINS, SOP_MLP_PARAMS = 320, 64, 256, 41344
 SOP_SHADOW_HAMMERSLEY, SOP_SHADOW_ENV, SOP_SHADOW_ENV_EXACT = 0, 1, 2
 SOP_ENV_EQUIRECT, SOP_ENV_OCTAHEDRAL = 0, 1

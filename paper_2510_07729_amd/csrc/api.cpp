@@ -523,6 +523,9 @@ sop_status validate_shade(const sop_plan* plan, const sop_probe_maps* maps,
       return fail(SOP_ERR_UNSUPPORTED, "the environment sampler has no adjoint");
     if (env->layout != SOP_ENV_OCTAHEDRAL)
       return fail(SOP_ERR_UNSUPPORTED, "the environment sampler takes an octahedral env");
+  } else if (o->sampler == SOP_SAMPLER_COSINE) {
+    if (!allow_proposal)
+      return fail(SOP_ERR_UNSUPPORTED, "the cosine sampler has no adjoint");
   } else if (o->sampler != SOP_SAMPLER_HAMMERSLEY) {
     return fail(SOP_ERR_UNSUPPORTED, "unknown sampler");
   }
@@ -613,8 +616,9 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
             "sop_shade");
     SOP_HIP(sopk::launch_shade_envis(a, kk, maps->format, s), "sop_shade");
   } else {
+    a.cosine = opts->sampler == SOP_SAMPLER_COSINE ? 1 : 0;
     SOP_HIP(sopk::launch_dir_sort(opts->n_dirs, opts->seed, opts->rotate_per_point ? 1 : 0,
-                                  sorted, s),
+                                  sorted, s, a.cosine),
             "sop_shade");
     a.dir_sorted = sorted;
     SOP_HIP(sopk::launch_shade_fwd(a, kk, maps->format, s), "sop_shade");

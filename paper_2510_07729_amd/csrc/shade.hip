@@ -262,7 +262,7 @@ __device__ __forceinline__ void order_by_probe(Neighbors<KT>& nb) {
 // units stay ~86% busy): the texture path remains the bound. The sum over a point's
 // directions is order-free (Eq. 7); the 8 lanes' partial sums meet by shuffles.
 constexpr int kFwdLanes = 8;          // lanes per point (points per wavefront: 64 / kFwdLanes)
-template <int KT, typename TexT, bool EO = false>
+template <int KT, typename TexT, bool EO = false, bool COS = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_shade_fwd_cl(ShadeArgs a, int32_t k) {
   constexpr int PPW = 64 / kFwdLanes;
   const int lane = threadIdx.x & 63, q = lane % kFwdLanes;
@@ -287,11 +287,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       s.ct = (float)e.z;
       eval_at<KT, TexT, EO>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
+      // the cosine-weighted set weighs each sample by 1/(2 cos) relative to 2 pi/S
+      const float wj = COS ? (float)e.w : 1.0f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float Li = (1.0f - s.O) * s.Le[c] + s.Lin[c];
-        acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li;
-        acc_e[c] += Li * s.ct;
+        if constexpr (COS) {
+          acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li * wj;
+          acc_e[c] += Li * s.ct * wj;
+        } else {
+          acc[c] += fcos(ps.M, bt, al[c], s.ct) * Li;
+          acc_e[c] += Li * s.ct;
+        }
       }
     }
   }
@@ -1571,6 +1578,13 @@ template <int KT, bool EO>
 static void launch_fwd_e(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s) {
   constexpr int per_block = kWavesPerBlock * (64 / kFwdLanes);
   const dim3 grid((unsigned)((a.n + per_block - 1) / per_block));
+  if (a.cosine) {
+    if (format == SOP_TEXEL_F16)
+      hipLaunchKernelGGL((k_shade_fwd_cl<KT, uint2, EO, true>), grid, dim3(256), 0, s, a, k);
+    else
+      hipLaunchKernelGGL((k_shade_fwd_cl<KT, float4, EO, true>), grid, dim3(256), 0, s, a, k);
+    return;
+  }
   if (format == SOP_TEXEL_F16)
     hipLaunchKernelGGL((k_shade_fwd_cl<KT, uint2, EO>), grid, dim3(256), 0, s, a, k);
   else
@@ -1860,14 +1874,15 @@ __device__ __forceinline__ uint32_t morton2(uint32_t x, uint32_t y) {
 // The S directions of the call (dir_entry) ordered by the Z curve of their position on the
 // hemispherical octahedral square (u, v) = (x + y, x - y) / (|x| + |y| + z) at 10 bits per
 // axis, ties by index: a bitonic sort of (code << 12 | j) in one workgroup (S <= 4096).
-__global__ __launch_bounds__(1024) void k_dir_sort(int32_t S, uint32_t rho, double4* sorted) {
+__global__ __launch_bounds__(1024) void k_dir_sort(int32_t S, uint32_t rho, double4* sorted,
+                                                  int32_t cosine) {
   __shared__ uint32_t key[SOP_MAX_DIRS];
   int n = 1;
   while (n < S) n <<= 1;
   for (int i = threadIdx.x; i < n; i += 1024) {
     uint32_t kv = 0xFFFFFFFFu;
     if (i < S) {
-      const double4 e = dir_entry(i, S, rho);
+      const double4 e = dir_entry(i, S, rho, cosine != 0);
       const double l1 = fabs(e.x) + fabs(e.y) + e.z;
       const double u = (e.x + e.y) / l1, v = (e.x - e.y) / l1;
       const uint32_t qu = (uint32_t)fmin(fmax((u + 1.0) * 512.0, 0.0), 1023.0);
@@ -1889,14 +1904,15 @@ __global__ __launch_bounds__(1024) void k_dir_sort(int32_t S, uint32_t rho, doub
       }
       __syncthreads();
     }
-  for (int i = threadIdx.x; i < S; i += 1024) sorted[i] = dir_entry((int)(key[i] & 0xFFFu), S, rho);
+  for (int i = threadIdx.x; i < S; i += 1024)
+    sorted[i] = dir_entry((int)(key[i] & 0xFFFu), S, rho, cosine != 0);
 }
 
 hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4* sorted,
-                           hipStream_t s) {
+                           hipStream_t s, int32_t cosine) {
   if (S < 1 || S > SOP_MAX_DIRS || !sorted) return hipErrorInvalidValue;
   const uint32_t rho = per_point ? 0u : rotation24(seed, false, 0u);
-  hipLaunchKernelGGL(k_dir_sort, dim3(1), dim3(1024), 0, s, S, rho, sorted);
+  hipLaunchKernelGGL(k_dir_sort, dim3(1), dim3(1024), 0, s, S, rho, sorted, cosine);
   return hipGetLastError();
 }
 

@@ -73,13 +73,23 @@ __device__ __forceinline__ Frame64 make_frame64(double nx, double ny, double nz)
 // sin(phi), cos(theta)) with cos(theta) = 1 - (j + 0.5)/S and
 // phi = 2 pi ((bitrev(j) >> 8) + rho) mod 2^24 / 2^24. The sample directions are the same
 // for every point of a call (one rotation per call), so they are formed once per call.
-__device__ __forceinline__ double4 dir_entry(int j, int S, uint32_t rho) {
-  const double ct = (double)(2 * S - 2 * j - 1) / (2.0 * (double)S);
-  const double st = sqrt((1.0 - ct) * (1.0 + ct));
+// With cosine, the cosine-weighted set: sin(theta) = sqrt((j + 0.5)/S), cos(theta) =
+// sqrt(1 - (j + 0.5)/S), same phi, and .w = 1/(2 cos(theta)), the sample's weight relative
+// to the uniform set's 2 pi/S (the density cos/pi instead of 1/(2 pi)).
+__device__ __forceinline__ double4 dir_entry(int j, int S, uint32_t rho, bool cosine = false) {
+  double ct, st, wgt = 0.0;
+  if (cosine) {
+    ct = sqrt((double)(2 * S - 2 * j - 1) / (2.0 * (double)S));
+    st = sqrt((double)(2 * j + 1) / (2.0 * (double)S));
+    wgt = 0.5 / ct;
+  } else {
+    ct = (double)(2 * S - 2 * j - 1) / (2.0 * (double)S);
+    st = sqrt((1.0 - ct) * (1.0 + ct));
+  }
   const uint32_t u24 = ((__builtin_bitreverse32((uint32_t)j) >> 8) + rho) & 0xFFFFFFu;
   double sp, cp;
   sincospi((double)u24 * 0x1p-23, &sp, &cp);
-  return make_double4(st * cp, st * sp, ct, 0.0);
+  return make_double4(st * cp, st * sp, ct, wgt);
 }
 
 // world direction t*a + b*b + n*ct in FP64

@@ -87,6 +87,7 @@ struct ShadeArgs {
   float* irr;
   const float4* traced;     // [n,S] (L_in rgb, O) per sample (traced shading)
   int32_t env_oct;          // env is an octahedral map [W,W,3] (else equirectangular [H,W,3])
+  int32_t cosine;           // forward: dir_sorted is the cosine-weighted set (weights in .w)
   // cast-shadow ratio: octahedral environment in env, its texel masses and their prefix
   const uint32_t* env_mass; // [Re*Re]
   const uint64_t* env_prefix;  // [Re*Re + 1], env_prefix[Re*Re] = total mass
@@ -153,7 +154,7 @@ hipError_t launch_dir_table(int32_t S, uint32_t seed, int32_t per_point, int32_t
                             double4* tab, double2* col_ref, double2* row_ref, hipStream_t s);
 // the call's directions in the order of a Z curve over the hemisphere (shading forward)
 hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4* sorted,
-                           hipStream_t s);
+                           hipStream_t s, int32_t cosine = 0);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // out[i] += the exact sum held in words[k * n + i] (k = 0..3), rounded once; NaN if *flag

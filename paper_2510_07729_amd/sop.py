@@ -278,14 +278,19 @@ def sop_query(plan: Plan, texels: torch.Tensor, pts: Points, dirs: torch.Tensor,
 def shade_opts(n_dirs: int, k: int, seed: int = 0, radius: float = math.inf,
                rotate_per_point: bool = False, irradiance: Optional[torch.Tensor] = None,
                probs: Optional[torch.Tensor] = None, mix_eps: float = 0.1, net=None,
-               env_sampling=False):
+               env_sampling=False, cosine: bool = False):
     """Shading options; `net` (an Mlp) selects the fused proposal sampler, env_sampling the
     environment importance sampler (True: Eq. 18's density, "exact": the draws' exact
-    density). The returned object keeps the network's C struct alive (attribute _net)."""
+    density), cosine the cosine-weighted direction set. The returned object keeps the
+    network's C struct alive (attribute _net)."""
     o = L.sop_shade_opts()
     o.n_dirs, o.k, o.radius, o.seed = int(n_dirs), int(k), float(radius), int(seed) & 0xFFFFFFFF
     o.rotate_per_point = int(rotate_per_point)
-    if env_sampling == "exact":
+    if cosine:
+        if env_sampling or net is not None or probs is not None:
+            raise ValueError("cosine is a direction set of its own: no probs, net or env_sampling")
+        o.sampler = L.SOP_SAMPLER_COSINE
+    elif env_sampling == "exact":
         o.sampler = L.SOP_SAMPLER_ENV_EXACT
     elif env_sampling:
         if env_sampling is not True:
@@ -308,12 +313,12 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
               radius: float = math.inf, rotate_per_point: bool = False,
               irradiance: bool = False, ws: Optional[torch.Tensor] = None,
               out: Optional[torch.Tensor] = None, probs: Optional[torch.Tensor] = None,
-              mix_eps: float = 0.1, net=None, env_sampling=False):
+              mix_eps: float = 0.1, net=None, env_sampling=False, cosine: bool = False):
     """Forward shading: rgb [N,3] (and irradiance [N,3] when asked). With probs [N,256] the
     directions are drawn from those bin distributions (mixed with mix_eps of uniform bins);
     with net (an Mlp) from the network's distributions, evaluated inside the call; with
     env_sampling (env an OctEnv) by environment importance sampling (Eq. 18; "exact" weights
-    the draws by their exact density)."""
+    the draws by their exact density); with cosine from the cosine-weighted set."""
     dev = pts.pos.device
     n = pts.n
     pts.check()
@@ -330,7 +335,7 @@ def sop_shade(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts: Points, 
         ws = workspace(plan.workspace_size(L.SOP_OP_SHADE, n, kk, n_dirs, env.shape[:2],
                                            nb is not None), dev)
     o = shade_opts(n_dirs, kk, seed, radius, rotate_per_point, irr, probs, mix_eps, net,
-                   env_sampling)
+                   env_sampling, cosine)
     m, e, cp = _maps(texels, plan), _env(env), pts.c()
     nbc = nb.c(n) if nb is not None else None
     L.check(plan._lib.sop_shade(plan.handle, C.byref(m), C.byref(e), C.byref(cp),
