@@ -457,6 +457,12 @@ def _proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, mask) -> dict:
     for S in (32, 64, 128):
         out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7))
         ham[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
+    # the cosine-weighted set of the same counts (no adjoint, forward only)
+    cos = {}
+    for S in (32, 64, 128):
+        out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7,
+                                              cosine=True))
+        cos[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
     probs, t_mlp = timed(lambda: sop.sop_proposal_infer(mlp, ev))
     prop = {}
     for S in (8, 16, 24, 32, 64):
@@ -472,7 +478,8 @@ def _proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, mask) -> dict:
     t_two = (t_mlp + prop[s_star]["ms"]) if s_star else None
     best = min(t_two, t_fused) if s_star else None
     speedup = (ham[128]["ms"] / best) if s_star else None
-    return {"hammersley": ham, "proposal": prop, "network_ms": round(t_mlp, 4),
+    return {"hammersley": ham, "cosine": cos, "proposal": prop,
+            "network_ms": round(t_mlp, 4),
             "S_star": s_star,
             "speedup_vs_hammersley_128": round(speedup, 3) if speedup else None,
             "speedup_path": ("fused" if t_fused < t_two else "two_call") if s_star else None,
@@ -693,12 +700,14 @@ def envis_study(torch, sop, scenes, time_ms, plan, tex, pts, nb, S, K, t_fwd_equ
     modes = {"env": True, "env_exact": "exact"}
     e_ham = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True))
              for n in counts}
+    e_cos = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True,
+                                  cosine=True)) for n in counts}
     t_ham = time_ms(lambda: sop.sop_shade(plan, tex, sky, pts, S, nb=nb, seed=5))
     out = {"workload": "object: 200k points, K=8, 256x256 octahedral sky with a sun "
                        "(~70% of the energy); errors on 4096 points against 4096 "
                        "Hammersley directions",
            "error_on": "irradiance", "dirs": S, "hammersley_ms": round(t_ham, 4),
-           "rel_rmse": {"hammersley": e_ham}}
+           "rel_rmse": {"hammersley": e_ham, "cosine": e_cos}}
     for name, mode in modes.items():
         e = {n: err(sop.sop_shade(plan, tex, sky, sub, n, nb=nbs, seed=5, irradiance=True,
                                   env_sampling=mode)) for n in counts}

@@ -313,7 +313,10 @@ typedef enum sop_op {
  * and an environment map of env_height x env_width texels (shading ops keep per-call
  * direction and environment reference tables there) on `plan`, assuming the neighbour
  * search runs inside the call (nb == NULL); with_neighbors != 0 gives the smaller figure
- * for calls that receive nb. Returns 0 on an invalid argument. */
+ * for calls that receive nb. For SOP_OP_SHADE_BACKWARD it includes, for environments of up
+ * to 4096 x 2048 texels, 64 bytes per 2x2 texel block in each of 4 block offsets
+ * (~21 bytes per texel), where the environment adjoint is gathered before it is added to
+ * g_env. Returns 0 on an invalid argument. */
 size_t sop_workspace_size(const sop_plan* plan, sop_op op, int64_t n_points, int32_t k,
                           int32_t n_dirs, int32_t env_height, int32_t env_width,
                           int32_t with_neighbors);

@@ -243,6 +243,16 @@ EnvCdf carve_env_cdf(Bump& b, size_t T) {
 }
 
 // Workspace layout: [direction table (shade ops)] [order, idx, w] [search scratch]
+// the float adjoint's environment blocks (sopk::env_block_cols), for environments up to
+// sopk::kEnvBlkMaxTexels texels; larger ones are added with runs straight into g_env
+bool env_blocks_fit(int32_t env_h, int32_t env_w) {
+  return env_h > 0 && env_w > 0 && (int64_t)env_h * env_w <= sopk::kEnvBlkMaxTexels;
+}
+size_t env_block_floats(int32_t env_h, int32_t env_w) {
+  return (size_t)4 * sopk::env_block_cols(env_w) * sopk::env_block_rows(env_h) *
+         sopk::kEnvBlkFloats;
+}
+
 size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool with_nb,
                  int32_t n_dirs, int32_t env_h = 0, int32_t env_w = 0) {
   Bump b{nullptr, 0, 0};
@@ -265,6 +275,8 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     carve_nb(b, N, k);
     carve_knn(b, plan, N);
   }
+  if (op == SOP_OP_SHADE_BACKWARD && env_blocks_fit(env_h, env_w))
+    (void)b.take<float>(env_block_floats(env_h, env_w));
   return b.used;
 }
 
@@ -743,7 +755,21 @@ sop_status shade_backward_impl(const sop_plan* plan, const sop_probe_maps* maps,
     a.det_nt = dl.nt;
     a.det_ne = dl.ne;
   }
+  const bool blocks = !det && g_env && env_blocks_fit(env->height, env->width) &&
+                      sopk::shade_bwd_batched(maps->res, kk);
+  if (blocks) {
+    const size_t nf = env_block_floats(env->height, env->width);
+    a.env_blk = b.take<float>(nf);
+    a.env_bw = sopk::env_block_cols(env->width);
+    a.env_bh = sopk::env_block_rows(env->height);
+    SOP_HIP(sopk::launch_fill_i32(reinterpret_cast<int32_t*>(a.env_blk), 0, nf, s), fn);
+  }
   SOP_HIP(sopk::launch_shade_bwd(a, kk, maps->format, s), fn);
+  if (blocks)
+    SOP_HIP(sopk::launch_env_blk_finish(a.env_blk, a.env_bw, a.env_bh, env->height,
+                                        env->width, env->layout == SOP_ENV_OCTAHEDRAL, g_env,
+                                        s),
+            fn);
   if (det && g_tex) SOP_HIP(sopk::launch_det_finish(wt, dl.nt, flag, g_tex, s), fn);
   if (det && g_env) SOP_HIP(sopk::launch_det_finish(we, dl.ne, flag, g_env, s), fn);
   return SOP_OK;

@@ -106,6 +106,7 @@ __device__ __forceinline__ void world_dir64(const Frame64& F, double a, double b
 struct Taps {
   int off[4];    // texel index j*R + i of each tap
   float w[4];    // bilinear weights
+  int i0, j0;    // corner tap before the wrap, in [-1, R-1]
 };
 
 __device__ __forceinline__ void oct_wrap(int i, int j, int R, int& oi, int& oj) {
@@ -135,6 +136,8 @@ __device__ __forceinline__ Taps oct_taps(v3 w, int R, float halfR) {
   const float fx = cu - i0f, fy = cv - j0f;
   const int i0 = (int)i0f, j0 = (int)j0f;
   Taps t;
+  t.i0 = i0;
+  t.j0 = j0;
   int ii, jj;
   oct_wrap(i0, j0, R, ii, jj);
   t.off[0] = jj * R + ii;
@@ -187,6 +190,8 @@ __device__ __forceinline__ Taps oct_taps64(const double w[3], int R) {
   const double fx = cu - i0f, fy = cv - j0f;
   const int i0 = (int)i0f, j0 = (int)j0f;
   Taps t;
+  t.i0 = i0;
+  t.j0 = j0;
   int ii, jj;
   oct_wrap(i0, j0, R, ii, jj);
   t.off[0] = jj * R + ii;
@@ -227,6 +232,7 @@ __device__ __forceinline__ float4 load_texel(const uint2* tex, size_t i) {
 struct EnvTaps {
   int off[4];
   float w[4];
+  int vi, vj;    // corner tap before the wrap and the clamp, plus 2 (>= 0)
 };
 
 __device__ __forceinline__ EnvTaps env_taps(v3 w, int H, int W, float u_scale, float v_scale) {
@@ -240,12 +246,15 @@ __device__ __forceinline__ EnvTaps env_taps(v3 w, int H, int W, float u_scale, f
   const float i0f = floorf(cu), j0f = floorf(cv);
   const float fx = cu - i0f, fy = cv - j0f;
   int i0 = (int)i0f, j0 = (int)j0f;
+  const int vi = i0 + 2, vj = j0 + 2;
   int i1 = i0 + 1, j1 = j0 + 1;
   i0 = i0 < 0 ? i0 + W : (i0 >= W ? i0 - W : i0);
   i1 = i1 < 0 ? i1 + W : (i1 >= W ? i1 - W : i1);
   j0 = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
   j1 = j1 < 0 ? 0 : (j1 > H - 1 ? H - 1 : j1);
   EnvTaps t;
+  t.vi = vi;
+  t.vj = vj;
   t.off[0] = j0 * W + i0;
   t.off[1] = j0 * W + i1;
   t.off[2] = j1 * W + i0;
@@ -325,6 +334,7 @@ __device__ __forceinline__ EnvTaps env_taps64(const double w[3], int H, int W, f
   fx = fmin(fmax(fx, 0.0), 1.0);
   fy = fmin(fmax(fy, 0.0), 1.0);
   // wrap columns (i0 may now be -2 .. W) and clamp rows
+  const int vi = i0 + 2, vj = j0 + 2;
   int i1 = i0 + 1, j1 = j0 + 1;
   i0 = i0 < 0 ? i0 + W : (i0 >= W ? i0 - W : i0);
   i1 = i1 < 0 ? i1 + W : (i1 >= W ? i1 - W : i1);
@@ -333,6 +343,8 @@ __device__ __forceinline__ EnvTaps env_taps64(const double w[3], int H, int W, f
   j0 = j0 < 0 ? 0 : (j0 > H - 1 ? H - 1 : j0);
   j1 = j1 < 0 ? 0 : (j1 > H - 1 ? H - 1 : j1);
   EnvTaps t;
+  t.vi = vi;
+  t.vj = vj;
   t.off[0] = j0 * W + i0;
   t.off[1] = j0 * W + i1;
   t.off[2] = j1 * W + i0;

@@ -115,6 +115,10 @@ struct ShadeArgs {
   unsigned long long* det_env;
   int32_t* det_flag;        // set when a contribution cannot be represented
   int64_t det_nt, det_ne;   // values of g_tex and of g_env
+  // float adjoint of the environment: 2x2-texel blocks (see env_block_count), NULL: float
+  // atomics straight into g_env
+  float* env_blk;
+  int32_t env_bw, env_bh;   // blocks per row and per column of one parity class
 };
 
 // learned proposal network (proposal.hip)
@@ -157,9 +161,25 @@ hipError_t launch_dir_sort(int32_t S, uint32_t seed, int32_t per_point, double4*
                            hipStream_t s, int32_t cosine = 0);
 hipError_t launch_shade_fwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_shade_bwd(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
+// whether launch_shade_bwd takes the batched kernel (the one that reads a.env_blk)
+bool shade_bwd_batched(int32_t res, int32_t k);
 // out[i] += the exact sum held in words[k * n + i] (k = 0..3), rounded once; NaN if *flag
 hipError_t launch_det_finish(const unsigned long long* words, int64_t n, const int32_t* flag,
                              float* out, hipStream_t s);
+// Environment adjoint in blocks. A sample's bilinear footprint is the 2x2 texels whose
+// corner is its (unwrapped) base tap (i0, j0); with the corner shifted by 2 (so that every
+// corner the lookups make is >= 0), blocks of parity class (i0 & 1, j0 & 1) tile the
+// plane so that the footprint is exactly one block: 12 floats (4 texels x 3 channels) in
+// a 64-byte record. Classes x rows x columns of blocks for an H x W environment:
+constexpr int kEnvBlkFloats = 16;
+inline int32_t env_block_cols(int32_t W) { return W / 2 + 3; }
+inline int32_t env_block_rows(int32_t H) { return H / 2 + 3; }
+// the largest environment (texels) whose adjoint goes through blocks (~540 MB of them)
+constexpr int64_t kEnvBlkMaxTexels = (int64_t)4096 * 2048;
+// g_env += the blocks' values at their wrapped (equirectangular) or mirrored (octahedral)
+// texels
+hipError_t launch_env_blk_finish(const float* blk, int32_t bw, int32_t bh, int32_t H,
+                                 int32_t W, bool octahedral, float* g_env, hipStream_t s);
 hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // cast-shadow ratio: texel masses and prefix of an octahedral environment [T <= 2^20
