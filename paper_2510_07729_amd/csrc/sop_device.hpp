@@ -303,10 +303,12 @@ __device__ __noinline__ double wide_atan2(double y, double x) {
 }
 
 __device__ __forceinline__ double angle_from(double c, double s, double x, double y) {
-  // signed angle from direction (c, s) to (x, y), both in one plane, |angle| < pi/2
+  // signed angle from direction (c, s) to (x, y), both in one plane; the series covers
+  // small angles only (dt > 0), the rest (texels wider than a right angle, W < 8 or H < 4)
+  // goes through the full arctangent
   const double cr = c * y - s * x, dt = c * x + s * y;
   const double z = cr / dt;
-  return fabs(z) <= 0.2 ? small_atan(z) : wide_atan2(cr, dt);
+  return (dt > 0.0 && fabs(z) <= 0.2) ? small_atan(z) : wide_atan2(cr, dt);
 }
 
 __device__ __forceinline__ EnvTaps env_taps64(const double w[3], int H, int W, float u_scale,

@@ -211,3 +211,26 @@ def test_backward_list_naming_a_probe_twice(torch_gpu):
     assert report("repeated probe forward", parity_err(rgb.cpu().numpy(), ro)) <= TOL
     ref = oracle.shade_backward(sc, idx, wf, grad.astype(np.float64), mass=True)
     assert check_all({k2: v.cpu().numpy() for k2, v in g.items()}, ref, "repeated probe")
+
+
+@pytest.mark.parametrize("hw,oct_sky", [((1, 1), False), ((1, 2), False), ((2, 1), False),
+                                         ((3, 5), False), ((4, 3), False), ((2, 2), True),
+                                         ((3, 3), True)])
+def test_backward_small_environments(torch_gpu, hw, oct_sky):
+    """Environments of a few texels: every bilinear footprint wraps (columns) and clamps
+    (rows), or mirrors (octahedral), so the environment adjoint's 2x2 blocks fold back onto
+    few texels, each from several block offsets."""
+    from paper_2510_07729_amd import sop
+    log(f"backward with a {hw[0]}x{hw[1]} {'octahedral' if oct_sky else 'equirectangular'} sky")
+    sc = scenes.tiny_shade(n_points=300, seed=41)
+    sky = np.random.default_rng(42).lognormal(0.0, 0.7, (*hw, 3)).astype(np.float32)
+    sc = dataclasses.replace(sc, env=sky, env_oct=oct_sky)
+    grad = np.random.default_rng(43).standard_normal((sc.n, 3)).astype(np.float32)
+    plan = gpu_plan(sc)
+    env = sop.OctEnv(dev(sky)) if oct_sky else dev(sky)
+    g = sop.sop_shade_backward(plan, dev(sc.texels), env, gpu_points(sc), dev(grad),
+                               sc.n_dirs, k=sc.k, seed=sc.seed)
+    g = {k2: v.cpu().numpy() for k2, v in g.items()}
+    idx, w = oracle_knn(sc)
+    ref = oracle.shade_backward(sc, idx, w, grad.astype(np.float64), mass=True)
+    assert check_all(g, ref, f"sky {hw} oct={oct_sky}")
