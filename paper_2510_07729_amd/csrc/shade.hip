@@ -260,8 +260,8 @@ __device__ __forceinline__ void order_by_probe(Neighbors<KT>& nb) {
 // neighbour lists mostly coincide (ordered by probe index), look the same way, and the
 // per-point work (neighbour lists, frame, material, the final sums) is shared by 8 lanes
 // instead of 64. On the object workload this layout takes 0.95 ms against 1.19 ms for one
-// point per wavefront, but its gathers still touch ~55 cache lines each (the texture
-// units stay ~86% busy): the texture path remains the bound. The sum over a point's
+// point per wavefront; its texture units stay ~86% busy (32 16-byte gathers per sample),
+// so the texture path remains the bound. The sum over a point's
 // directions is order-free (Eq. 7); the 8 lanes' partial sums meet by shuffles.
 constexpr int kFwdLanes = 8;          // lanes per point (points per wavefront: 64 / kFwdLanes)
 template <int KT, typename TexT, bool EO = false, bool COS = false>
@@ -1175,11 +1175,12 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, int32_t k) {
 // (v = t + kBatchThreads * i) and adds it to g_tex[k] with atomics that are coalesced
 // (consecutive lanes, consecutive words). This replaces K*4*4 scattered atomics per
 // sample by about (distinct probes / kBatch) * res^2 * 4 coalesced atomics per point.
-// The environment adjoint of a sample covers two rows of its bilinear footprint, each two
-// adjacent texels = six consecutive floats (a "run"). Scattered one float per lane, every
-// atomic instruction touches 64 cache lines; instead each wavefront stages the runs of 32
-// samples in LDS and adds them with six consecutive lanes per run, about a tenth of the
-// lines per instruction.
+// The environment adjoint of a sample is its bilinear footprint, 4 texels x 3 channels.
+// Scattered one float per lane, every atomic instruction touches 64 cache lines; instead
+// each wavefront stages the footprints of 32 samples in LDS and adds each with
+// consecutive lanes: as one 64-byte block record (env_blk_flush, the float adjoint) or as
+// two rows of six consecutive floats, "runs" (env_runs_flush: the exact adjoint, and
+// environments beyond the block limit).
 // ------------------------------------------------------------------------------------------
 constexpr int kBatch = 8;
 constexpr int kBatchThreads = kBatch * 64;

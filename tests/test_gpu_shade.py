@@ -233,3 +233,22 @@ def test_shade_reference_direction_count(torch_gpu):
     idx, w = oracle_knn(sc)
     ro = oracle.shade(sc, idx, w, n_dirs=4096, seed=123)
     assert report("shade S=4096", parity_err(rgb, ro)) <= TOL
+
+
+@pytest.mark.parametrize("hw", [(1, 2), (2, 3), (3, 5), (5, 7)])
+def test_shade_small_equirect_environments(torch_gpu, hw):
+    """Equirectangular skies whose texels span more than a right angle (W < 8 or H < 4):
+    the lookup's FP64 fraction then comes from the full arctangent, not the small-angle
+    series."""
+    import dataclasses
+    from paper_2510_07729_amd import sop
+    log(f"forward with a {hw[0]}x{hw[1]} equirectangular sky")
+    sc = scenes.tiny_shade(n_points=400, seed=44)
+    sky = np.random.default_rng(45).lognormal(0.0, 0.7, (*hw, 3)).astype(np.float32)
+    sc = dataclasses.replace(sc, env=sky)
+    rgb, irr = sop.sop_shade(gpu_plan(sc), dev(sc.texels), dev(sky), gpu_points(sc),
+                             sc.n_dirs, k=sc.k, seed=sc.seed, irradiance=True)
+    idx, w = oracle_knn(sc)
+    ref, rirr = oracle.shade(sc, idx, w, irradiance=True)
+    assert report(f"sky {hw} rgb", parity_err(rgb.cpu().numpy(), ref)) <= TOL
+    assert report(f"sky {hw} irradiance", parity_err(irr.cpu().numpy(), rirr)) <= TOL
