@@ -275,6 +275,7 @@ size_t ws_needed(const sop_plan* plan, sop_op op, int64_t N, int32_t k, bool wit
     carve_nb(b, N, k);
     carve_knn(b, plan, N);
   }
+  if (op == SOP_OP_SHADE_BACKWARD) (void)b.take<double4>((size_t)n_dirs);   // Z-curve order
   if (op == SOP_OP_SHADE_BACKWARD && env_blocks_fit(env_h, env_w))
     (void)b.take<float>(env_block_floats(env_h, env_w));
   return b.used;
@@ -755,6 +756,11 @@ sop_status shade_backward_impl(const sop_plan* plan, const sop_probe_maps* maps,
     a.det_nt = dl.nt;
     a.det_ne = dl.ne;
   }
+  double4* sorted = b.take<double4>((size_t)opts->n_dirs);
+  SOP_HIP(sopk::launch_dir_sort(opts->n_dirs, opts->seed, opts->rotate_per_point ? 1 : 0,
+                                sorted, s),
+          fn);
+  a.dir_sorted = sorted;
   const bool blocks = !det && g_env && env_blocks_fit(env->height, env->width) &&
                       sopk::shade_bwd_batched(maps->res, kk);
   if (blocks) {

@@ -202,7 +202,10 @@ template <int KT, typename TexT, bool EO = false>
 __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState& ps,
                                             const Neighbors<KT>& nb, int32_t k, int j,
                                             Sample& s) {
-  const double4 e = a.dir_tab[j];
+  // the adjoint walks the directions along the Z curve over the hemisphere (dir_sorted):
+  // a wavefront's 64 lanes then look into one compact region, and its gathers share more
+  // cache lines than in the table's own order (the sum over directions is order-free)
+  const double4 e = a.dir_sorted ? a.dir_sorted[j] : a.dir_tab[j];
   const double da = e.x * ps.cr - e.y * ps.sr;
   const double db = e.x * ps.sr + e.y * ps.cr;
   world_dir64(ps.F, da, db, e.z, s.w64);
