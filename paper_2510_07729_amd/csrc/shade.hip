@@ -158,8 +158,24 @@ __device__ __forceinline__ void eval_env(const ShadeArgs& a, Sample& s) {
   }
 }
 
-// environment and probe fetches of a sample whose direction (w64, w, ct) is set
-template <int KT, typename TexT, bool EO = false>
+// the value of v in the other lane of the lane's pair (2i, 2i + 1)
+__device__ __forceinline__ int pair_swap(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(pair_swap(__float_as_int(v)));
+}
+
+// environment and probe fetches of a sample whose direction (w64, w, ct) is set.
+// PAIRED (both lanes of every pair (2i, 2i + 1) shade the same point): when every pair of
+// the wavefront is active, the two lanes split the taps of both their samples so that each
+// load instruction reads, per pair, two texels of one row of one sample (one cache line
+// unless the row crosses a line boundary) instead of one texel of each of two directions:
+// the even lane takes taps 0 and 2, the odd lane taps 1 and 3, of both samples; each lane
+// adds its two taps of its own sample and its two taps of the partner's, and the
+// partner's part changes lanes once per sample. The sum per sample is the same (its terms
+// are grouped in two halves instead of one running sum).
+template <int KT, typename TexT, bool EO = false, bool PAIRED = false>
 __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps,
                                         const Neighbors<KT>& nb, int32_t k, Sample& s) {
   s.et = env_taps_of<EO>(a, s.w64);
@@ -177,6 +193,52 @@ __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps
   const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
   const size_t RR = (size_t)a.R * a.R;
   const int kn = KT > 0 ? KT : nb.count(k);
+  if constexpr (PAIRED) {
+    const uint64_t act = __ballot(1);
+    if (((act ^ (act >> 1)) & 0x5555555555555555ull) == 0) {   // uniform: all pairs whole
+      const bool odd = (__lane_id() & 1) != 0;
+      // partner's taps: the even lane needs 0 and 2, the odd lane 1 and 3
+      const int q0 = pair_swap(odd ? s.tt.off[0] : s.tt.off[1]);
+      const int q1 = pair_swap(odd ? s.tt.off[2] : s.tt.off[3]);
+      const float u0 = pair_swap(odd ? s.tt.w[0] : s.tt.w[1]);
+      const float u1 = pair_swap(odd ? s.tt.w[2] : s.tt.w[3]);
+      // loads 1..4: row 0 of the even sample, row 0 of the odd sample, then row 1 of each
+      const int ad0 = odd ? q0 : s.tt.off[0];
+      const int ad1 = odd ? s.tt.off[1] : q0;
+      const int ad2 = odd ? q1 : s.tt.off[2];
+      const int ad3 = odd ? s.tt.off[3] : q1;
+      // weights of loads 1, 3 (even sample) and 2, 4 (odd sample) in this lane
+      const float c0 = odd ? u0 : s.tt.w[0];
+      const float c1 = odd ? s.tt.w[1] : u0;
+      const float c2 = odd ? u1 : s.tt.w[2];
+      const float c3 = odd ? s.tt.w[3] : u1;
+      float4 ev = make_float4(0.0f, 0.0f, 0.0f, 0.0f), od = ev;
+#pragma unroll
+      for (int s2 = 0; s2 < kn; ++s2) {
+        const int32_t id = nb.id(s2, a, ps.p, k);
+        if (id < 0) continue;
+        const float wk = nb.wt(s2, a, ps.p, k);
+        const TexT* T = tex + (size_t)id * RR;
+        const float4 x0 = load_texel(T, (size_t)ad0), x1 = load_texel(T, (size_t)ad1);
+        const float4 x2 = load_texel(T, (size_t)ad2), x3 = load_texel(T, (size_t)ad3);
+        const float e0 = wk * c0, e1 = wk * c1, e2 = wk * c2, e3 = wk * c3;
+        ev.x += e0 * x0.x + e2 * x2.x;
+        ev.y += e0 * x0.y + e2 * x2.y;
+        ev.z += e0 * x0.z + e2 * x2.z;
+        ev.w += e0 * x0.w + e2 * x2.w;
+        od.x += e1 * x1.x + e3 * x3.x;
+        od.y += e1 * x1.y + e3 * x3.y;
+        od.z += e1 * x1.z + e3 * x3.z;
+        od.w += e1 * x1.w + e3 * x3.w;
+      }
+      const float4 keep = odd ? od : ev, send = odd ? ev : od;
+      s.Lin[0] = keep.x + pair_swap(send.x);
+      s.Lin[1] = keep.y + pair_swap(send.y);
+      s.Lin[2] = keep.z + pair_swap(send.z);
+      s.O = keep.w + pair_swap(send.w);
+      return;
+    }
+  }
 #pragma unroll
   for (int s2 = 0; s2 < kn; ++s2) {
     const int32_t id = nb.id(s2, a, ps.p, k);
@@ -211,7 +273,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
   world_dir64(ps.F, da, db, e.z, s.w64);
   s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
   s.ct = (float)e.z;
-  eval_at<KT, TexT, EO>(a, ps, nb, k, s);
+  eval_at<KT, TexT, EO, true>(a, ps, nb, k, s);
 }
 
 // Sum over the L lanes of a lane group (L = 64: the whole wavefront, with DPP).
@@ -290,7 +352,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       world_dir64(ps.F, da, db, e.z, s.w64);
       s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
       s.ct = (float)e.z;
-      eval_at<KT, TexT, EO>(a, ps, nb, k, s);
+      eval_at<KT, TexT, EO, true>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
       // the cosine-weighted set weighs each sample by 1/(2 cos) relative to 2 pi/S
       const float wj = COS ? (float)e.w : 1.0f;
