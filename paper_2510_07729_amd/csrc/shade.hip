@@ -158,24 +158,28 @@ __device__ __forceinline__ void eval_env(const ShadeArgs& a, Sample& s) {
   }
 }
 
-// the value of v in the other lane of the lane's pair (2i, 2i + 1)
+// the value of v in the other lane of the lane's pair: lanes l and l ^ D (D = 1: DPP
+// quad permutation; D = 16: across rows, through the LDS crossbar)
+template <int D>
 __device__ __forceinline__ int pair_swap(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  if constexpr (D == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+  else return __shfl_xor(v, D);
 }
+template <int D>
 __device__ __forceinline__ float pair_swap(float v) {
-  return __int_as_float(pair_swap(__float_as_int(v)));
+  return __int_as_float(pair_swap<D>(__float_as_int(v)));
 }
 
 // environment and probe fetches of a sample whose direction (w64, w, ct) is set.
-// PAIRED (both lanes of every pair (2i, 2i + 1) shade the same point): when every pair of
-// the wavefront is active, the two lanes split the taps of both their samples so that each
+// PAIR = D > 0 (lanes l and l ^ D shade the same point): when every pair of the wavefront
+// is active, the two lanes split the taps of both their samples so that each
 // load instruction reads, per pair, two texels of one row of one sample (one cache line
 // unless the row crosses a line boundary) instead of one texel of each of two directions:
 // the even lane takes taps 0 and 2, the odd lane taps 1 and 3, of both samples; each lane
 // adds its two taps of its own sample and its two taps of the partner's, and the
 // partner's part changes lanes once per sample. The sum per sample is the same (its terms
 // are grouped in two halves instead of one running sum).
-template <int KT, typename TexT, bool EO = false, bool PAIRED = false>
+template <int KT, typename TexT, bool EO = false, int PAIR = 0>
 __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps,
                                         const Neighbors<KT>& nb, int32_t k, Sample& s) {
   s.et = env_taps_of<EO>(a, s.w64);
@@ -193,15 +197,18 @@ __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps
   const TexT* tex = reinterpret_cast<const TexT*>(a.tex);
   const size_t RR = (size_t)a.R * a.R;
   const int kn = KT > 0 ? KT : nb.count(k);
-  if constexpr (PAIRED) {
+  if constexpr (PAIR > 0) {
+    // lanes whose bit PAIR is clear (the pairs' low lanes)
+    constexpr uint64_t kLow = PAIR == 1 ? 0x5555555555555555ull : 0x0000FFFF0000FFFFull;
+    static_assert(PAIR == 1 || PAIR == 16, "pairs are lanes l, l ^ 1 or l, l ^ 16");
     const uint64_t act = __ballot(1);
-    if (((act ^ (act >> 1)) & 0x5555555555555555ull) == 0) {   // uniform: all pairs whole
-      const bool odd = (__lane_id() & 1) != 0;
+    if (((act ^ (act >> PAIR)) & kLow) == 0) {   // uniform: all pairs whole
+      const bool odd = (__lane_id() & PAIR) != 0;
       // partner's taps: the even lane needs 0 and 2, the odd lane 1 and 3
-      const int q0 = pair_swap(odd ? s.tt.off[0] : s.tt.off[1]);
-      const int q1 = pair_swap(odd ? s.tt.off[2] : s.tt.off[3]);
-      const float u0 = pair_swap(odd ? s.tt.w[0] : s.tt.w[1]);
-      const float u1 = pair_swap(odd ? s.tt.w[2] : s.tt.w[3]);
+      const int q0 = pair_swap<PAIR>(odd ? s.tt.off[0] : s.tt.off[1]);
+      const int q1 = pair_swap<PAIR>(odd ? s.tt.off[2] : s.tt.off[3]);
+      const float u0 = pair_swap<PAIR>(odd ? s.tt.w[0] : s.tt.w[1]);
+      const float u1 = pair_swap<PAIR>(odd ? s.tt.w[2] : s.tt.w[3]);
       // loads 1..4: row 0 of the even sample, row 0 of the odd sample, then row 1 of each
       const int ad0 = odd ? q0 : s.tt.off[0];
       const int ad1 = odd ? s.tt.off[1] : q0;
@@ -232,10 +239,10 @@ __device__ __forceinline__ void eval_at(const ShadeArgs& a, const PointState& ps
         od.w += e1 * x1.w + e3 * x3.w;
       }
       const float4 keep = odd ? od : ev, send = odd ? ev : od;
-      s.Lin[0] = keep.x + pair_swap(send.x);
-      s.Lin[1] = keep.y + pair_swap(send.y);
-      s.Lin[2] = keep.z + pair_swap(send.z);
-      s.O = keep.w + pair_swap(send.w);
+      s.Lin[0] = keep.x + pair_swap<PAIR>(send.x);
+      s.Lin[1] = keep.y + pair_swap<PAIR>(send.y);
+      s.Lin[2] = keep.z + pair_swap<PAIR>(send.z);
+      s.O = keep.w + pair_swap<PAIR>(send.w);
       return;
     }
   }
@@ -273,7 +280,7 @@ __device__ __forceinline__ void eval_sample(const ShadeArgs& a, const PointState
   world_dir64(ps.F, da, db, e.z, s.w64);
   s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
   s.ct = (float)e.z;
-  eval_at<KT, TexT, EO, true>(a, ps, nb, k, s);
+  eval_at<KT, TexT, EO, 1>(a, ps, nb, k, s);
 }
 
 // Sum over the L lanes of a lane group (L = 64: the whole wavefront, with DPP).
@@ -352,7 +359,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       world_dir64(ps.F, da, db, e.z, s.w64);
       s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
       s.ct = (float)e.z;
-      eval_at<KT, TexT, EO, true>(a, ps, nb, k, s);
+      eval_at<KT, TexT, EO, 1>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
       // the cosine-weighted set weighs each sample by 1/(2 cos) relative to 2 pi/S
       const float wj = COS ? (float)e.w : 1.0f;
@@ -892,7 +899,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // sampler above do, and then shades the 16 points with lane l%16 + 16g taking draws
 // g, g+4, ... of point l%16. The bin probabilities never leave the chip.
 template <int KT, typename TexT>
-__global__ __launch_bounds__(256) void k_shade_prop_net(ShadeArgs a, int32_t k) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_shade_prop_net(ShadeArgs a, int32_t k) {
   __shared__ uint32_t s_cum[kWavesPerBlock][16][SOP_MLP_BINS + 1];
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int64_t tile = die_block() * kWavesPerBlock + wave_id_uniform();
@@ -976,7 +983,7 @@ __global__ __launch_bounds__(256) void k_shade_prop_net(ShadeArgs a, int32_t k) 
       world_dir64(ps.F, wl[0], wl[1], wl[2], s.w64);
       s.w = mk3((float)s.w64[0], (float)s.w64[1], (float)s.w64[2]);
       s.ct = (float)wl[2];
-      eval_at<KT, TexT>(a, ps, nb, k, s);
+      eval_at<KT, TexT, false, 16>(a, ps, nb, k, s);
       const BrdfTerms bt = brdf_terms(ps.M, half_geom(ps.n64, ps.v64, s.w64), s.ct);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
