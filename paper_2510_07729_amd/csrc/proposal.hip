@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_mlp_frags(const float* __restrict__ P,
 // ------------------------------------------------------------------------------------------
 // inference: one wavefront per 16 points
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_infer(MlpArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_infer(MlpArgs a) {
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t p0 = tile * 16;
