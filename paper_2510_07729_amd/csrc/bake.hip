@@ -232,7 +232,7 @@ __device__ __forceinline__ void box_cell(const int c0[3], int nx, int ny, int t,
 // The count pass keeps the acceptance bits of the first 64 kCellMaskWords cells of every box
 // (one wavefront ballot per 64 cells), so the fill pass repeats the exact test only beyond
 // them.
-__global__ __launch_bounds__(256) void k_gauss_count(BakeGrid G, const float4* aabb,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gauss_count(BakeGrid G, const float4* aabb,
                                                      int32_t* counts, uint64_t* cellmask,
                                                      int32_t* overflow) {
   const int32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
