@@ -231,6 +231,7 @@ struct EnvCdf {
   uint64_t* prefix;
   uint64_t* tiles;
   float* imax;
+  int32_t* guide;
 };
 
 EnvCdf carve_env_cdf(Bump& b, size_t T) {
@@ -239,6 +240,7 @@ EnvCdf carve_env_cdf(Bump& b, size_t T) {
   c.prefix = b.take<uint64_t>(T + 1);
   c.tiles = b.take<uint64_t>((T + 1023) / 1024 + 1);
   c.imax = b.take<float>(1);
+  c.guide = b.take<int32_t>((size_t)sopk::kEnvGuide + 1);
   return c;
 }
 
@@ -624,8 +626,9 @@ extern "C" sop_status sop_shade(const sop_plan* plan, const sop_probe_maps* maps
     a.env_pdf_exact = opts->sampler == SOP_SAMPLER_ENV_EXACT ? 1 : 0;
     a.env_mass = cdf.mass;
     a.env_prefix = cdf.prefix;
+    a.env_guide = cdf.guide;
     SOP_HIP(sopk::launch_env_cdf(env->texels, env->width * env->height, cdf.mass, cdf.prefix,
-                                 cdf.tiles, cdf.imax, s),
+                                 cdf.tiles, cdf.imax, cdf.guide, s),
             "sop_shade");
     SOP_HIP(sopk::launch_shade_envis(a, kk, maps->format, s), "sop_shade");
   } else {
@@ -1362,6 +1365,7 @@ size_t shadow_ws(const sop_plan* plan, int64_t N, int32_t k, int32_t S, int32_t 
   (void)b.take<uint64_t>((size_t)Re * Re + 1);
   (void)b.take<uint64_t>(((size_t)Re * Re + 1023) / 1024);
   (void)b.take<float>(1);
+  (void)b.take<int32_t>((size_t)sopk::kEnvGuide + 1);
   if (!with_nb) {
     carve_nb(b, N, k);
     carve_knn(b, plan, N);
@@ -1445,6 +1449,7 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
   uint64_t* prefix = b.take<uint64_t>((size_t)T + 1);
   uint64_t* tile_tmp = b.take<uint64_t>(((size_t)T + 1023) / 1024);
   float* imax = b.take<float>(1);
+  int32_t* guide = b.take<int32_t>((size_t)sopk::kEnvGuide + 1);
   if (opts->sampler == SOP_SHADOW_HAMMERSLEY) {
     a.dir_tab = tab;
     // the table's environment references are not used here (width/height 0)
@@ -1454,7 +1459,8 @@ extern "C" sop_status sop_shadow_ratio(const sop_plan* plan, const sop_probe_map
   } else {
     a.env_mass = mass;
     a.env_prefix = prefix;
-    SOP_HIP(sopk::launch_env_cdf(env->texels, T, mass, prefix, tile_tmp, imax, s),
+    a.env_guide = guide;
+    SOP_HIP(sopk::launch_env_cdf(env->texels, T, mass, prefix, tile_tmp, imax, guide, s),
             "sop_shadow_ratio");
   }
   int32_t kk;

@@ -469,6 +469,41 @@ __device__ __forceinline__ float env_intensity(const float* e) {
 // scan of the tile totals (one workgroup; T <= 2^20), and the tile offsets added.
 constexpr int kCdfTile = 1024;
 
+// cell width (log2) of the guide of a mass line of total C: 2^16 cells at most
+__device__ __forceinline__ int env_guide_shift(uint64_t C) {
+  const int bits = C ? 64 - __clzll((long long)C) : 0;
+  return bits > 16 ? bits - 16 : 0;
+}
+
+// the texel whose stretch of the mass line holds x < C: the largest t with prefix[t] <= x,
+// searched between the guide entries of x's cell
+__device__ __forceinline__ int env_pick(const uint64_t* __restrict__ prefix,
+                                        const int32_t* __restrict__ guide, int32_t T,
+                                        uint64_t C, uint64_t x) {
+  const uint64_t g = x >> env_guide_shift(C);
+  int lo = guide[g], hi = min(guide[g + 1] + 1, T);
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// guide[g] = the texel of x = g << shift, by a full search (kEnvGuide + 1 entries)
+__global__ __launch_bounds__(256) void k_env_guide(const uint64_t* __restrict__ prefix,
+                                                   int32_t T, int32_t* __restrict__ guide) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g > kEnvGuide) return;
+  const uint64_t C = prefix[T];
+  const uint64_t v = (uint64_t)g << env_guide_shift(C);
+  int lo = 0, hi = T;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= v) lo = mid; else hi = mid;
+  }
+  guide[g] = lo;
+}
+
 __global__ __launch_bounds__(1024) void k_env_max(const float* env, int32_t T, float* imax) {
   __shared__ float smax[1024];
   const int tid = threadIdx.x;
@@ -594,11 +629,7 @@ __global__ __launch_bounds__(256) void k_shadow_ratio(ShadeArgs a, int32_t k) {
       // the j-th of S slices of the mass line, then the texel whose stretch holds x
       const uint64_t r = hash24(sh, (uint32_t)p, (uint32_t)j, 0);
       const uint64_t x = ((uint64_t)j * C + ((r * C) >> 24)) / (uint64_t)a.S;
-      int lo = 0, hi = T;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.env_prefix[mid] <= x) lo = mid; else hi = mid;
-      }
+      const int lo = env_pick(a.env_prefix, a.env_guide, T, C, x);
       const double xu = ((double)hash24(sh, (uint32_t)p, (uint32_t)j, 1) + 0.5) * 0x1p-24;
       const double xv = ((double)hash24(sh, (uint32_t)p, (uint32_t)j, 2) + 0.5) * 0x1p-24;
       oct_decode64((double)(lo % Re) + xu, (double)(lo / Re) + xv, Re, w64);
@@ -682,11 +713,7 @@ __global__ __launch_bounds__(256) void k_shade_envis(ShadeArgs a, int32_t k) {
       // the j-th of S slices of the mass line, then the texel whose stretch holds x
       const uint64_t r = hash24(sh, pi, (uint32_t)j, 0);
       const uint64_t x = ((uint64_t)j * C + ((r * C) >> 24)) / (uint64_t)a.S;
-      int lo = 0, hi = T;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (a.env_prefix[mid] <= x) lo = mid; else hi = mid;
-      }
+      const int lo = env_pick(a.env_prefix, a.env_guide, T, C, x);
       const double xu = ((double)hash24(sh, pi, (uint32_t)j, 1) + 0.5) * 0x1p-24;
       const double xv = ((double)hash24(sh, pi, (uint32_t)j, 2) + 0.5) * 0x1p-24;
       Sample s;
@@ -1766,8 +1793,8 @@ hipError_t launch_shade_traced(const ShadeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t* prefix,
-                          uint64_t* tile_tmp, float* imax, hipStream_t s) {
-  if (T < 1 || T > (1 << 20) || !env || !mass || !prefix || !tile_tmp || !imax)
+                          uint64_t* tile_tmp, float* imax, int32_t* guide, hipStream_t s) {
+  if (T < 1 || T > (1 << 20) || !env || !mass || !prefix || !tile_tmp || !imax || !guide)
     return hipErrorInvalidValue;
   const int ntiles = (T + kCdfTile - 1) / kCdfTile;
   hipLaunchKernelGGL(k_env_max, dim3(1), dim3(1024), 0, s, env, T, imax);
@@ -1775,6 +1802,8 @@ hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t*
                      tile_tmp);
   hipLaunchKernelGGL(k_env_tile_scan, dim3(1), dim3(1024), 0, s, ntiles, tile_tmp, prefix, T);
   hipLaunchKernelGGL(k_env_add, dim3(ntiles), dim3(1024), 0, s, T, tile_tmp, prefix);
+  hipLaunchKernelGGL(k_env_guide, dim3((kEnvGuide + 1 + 255) / 256), dim3(256), 0, s, prefix, T,
+                     guide);
   return hipGetLastError();
 }
 

@@ -91,6 +91,7 @@ struct ShadeArgs {
   // cast-shadow ratio: octahedral environment in env, its texel masses and their prefix
   const uint32_t* env_mass; // [Re*Re]
   const uint64_t* env_prefix;  // [Re*Re + 1], env_prefix[Re*Re] = total mass
+  const int32_t* env_guide;    // [kEnvGuide + 1] guide of the mass line (launch_env_cdf)
   int32_t env_res;
   int32_t shadow_sampler;   // 0 Hammersley, 1 environment importance sampling
   int32_t env_pdf_exact;    // importance draws weighted by their exact density (else Eq. 18's)
@@ -184,8 +185,13 @@ hipError_t launch_shade_prop(const ShadeArgs& a, int32_t k, int32_t format, hipS
 hipError_t launch_dump_integrand(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // cast-shadow ratio: texel masses and prefix of an octahedral environment [T <= 2^20
 // texels]; tile_tmp holds ceil(T/1024) values, imax one
+// The sampler's texel for a point x of the mass line is the largest t with prefix[t] <= x.
+// guide[g] is that texel for x = g << shift (shift = max(0, bit length of the total - 16),
+// so g < 2^16 + 1 cells cover the line): the texel of any x in cell g lies in
+// [guide[g], guide[g + 1]], a few texels instead of the whole map.
+constexpr int kEnvGuide = 65536;
 hipError_t launch_env_cdf(const float* env, int32_t T, uint32_t* mass, uint64_t* prefix,
-                          uint64_t* tile_tmp, float* imax, hipStream_t s);
+                          uint64_t* tile_tmp, float* imax, int32_t* guide, hipStream_t s);
 // relighting with environment importance sampling (a.env octahedral, a.env_mass/prefix)
 hipError_t launch_shade_envis(const ShadeArgs& a, int32_t k, int32_t format, hipStream_t s);
 // ratio [n,3] in a.rgb (optional unshadowed estimate in a.irr)
