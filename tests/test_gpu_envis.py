@@ -105,3 +105,22 @@ def test_envis_rejections(torch_gpu):
                                       C.byref(o), 16, None, None, None, None, None, None, 0,
                                       None)
     assert st == L.SOP_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("R,hot", [(2, 1e6), (3, 1e5), (64, 1e7), (64, 1.0)])
+def test_envis_extreme_mass_lines(torch_gpu, R, hot):
+    """Skies whose mass line stresses the sampler's guide: one texel carrying almost all of
+    the mass (it spans most guide cells, the others share a few), a sky of 2 or 3 texels a
+    side, and a flat sky (every cell the same few texels). The texel of every draw must be
+    the one the oracle's full search finds."""
+    log(f"environment sampler: {R}x{R} sky, one texel {hot:g}x the rest")
+    sc = scenes.tiny_shade(n_points=700, seed=8)
+    sky = np.full((R, R, 3), 0.05, F32)
+    sky[R // 2, (R - 1) // 2] = 0.05 * hot
+    sc = dataclasses.replace(sc, env=sky, env_oct=True, n_dirs=64, seed=13)
+    for exact in (False, True):
+        rgb, irr = gpu_envis(sc, exact=exact)
+        idx, w = oracle_knn(sc)
+        ref, rirr = oracle.shade_envis(sc, idx, w, irradiance=True, exact=exact)
+        assert report(f"extreme sky rgb exact={exact}", parity_err(rgb, ref)) <= TOL
+        assert report(f"extreme sky irradiance exact={exact}", parity_err(irr, rirr)) <= TOL
