@@ -234,3 +234,27 @@ def test_backward_small_environments(torch_gpu, hw, oct_sky):
     idx, w = oracle_knn(sc)
     ref = oracle.shade_backward(sc, idx, w, grad.astype(np.float64), mass=True)
     assert check_all(g, ref, f"sky {hw} oct={oct_sky}")
+
+
+def test_backward_sky_beyond_the_block_limit(torch_gpu):
+    """A 2050x4100 sky (8.4M texels, above the 4096x2048 limit of the environment blocks):
+    the float adjoint adds its environment gradient as runs straight into g_env, and the
+    workspace holds no blocks."""
+    from paper_2510_07729_amd import _lib as L
+    from paper_2510_07729_amd import sop
+    log("backward under a 2050x4100 sky: environment runs instead of blocks")
+    sc = scenes.tiny_shade(n_points=120, seed=51)
+    H, W = 2050, 4100
+    sky = np.random.default_rng(52).lognormal(0.0, 0.5, (H, W, 3)).astype(np.float32)
+    sc = dataclasses.replace(sc, env=sky)
+    grad = np.random.default_rng(53).standard_normal((sc.n, 3)).astype(np.float32)
+    plan = gpu_plan(sc)
+    small = plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, sc.n, sc.k, sc.n_dirs, (H, W - 8))
+    large = plan.workspace_size(L.SOP_OP_SHADE_BACKWARD, sc.n, sc.k, sc.n_dirs, (H, W))
+    assert large < small          # 4092 columns still take blocks, 4100 do not
+    g = sop.sop_shade_backward(plan, dev(sc.texels), dev(sky), gpu_points(sc), dev(grad),
+                               sc.n_dirs, k=sc.k, seed=sc.seed)
+    g = {k2: v.cpu().numpy() for k2, v in g.items()}
+    idx, w = oracle_knn(sc)
+    ref = oracle.shade_backward(sc, idx, w, grad.astype(np.float64), mass=True)
+    assert check_all(g, ref, "sky 2050x4100")
