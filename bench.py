@@ -119,7 +119,7 @@ def main() -> int:
     if args.shadow_only:
         return shadow_only(torch, dev, sop, scenes)
     if args.frames_only:
-        print(json.dumps(frames_study(torch, dev, sop, scenes, reps=3)), flush=True)
+        print(json.dumps(frames_study(torch, dev, sop, scenes, reps=3, cpu=False)), flush=True)
         return 0
 
     if args.place_only:
@@ -380,7 +380,7 @@ def main() -> int:
 
     frames = None
     if not args.no_frames_study:
-        frames = frames_study(torch, dev, sop, scenes)
+        frames = frames_study(torch, dev, sop, scenes, cpu=not args.no_cpu_baseline)
         print(f"# frames study: {json.dumps(frames)}", file=sys.stderr, flush=True)
 
     envis = None
@@ -625,7 +625,42 @@ def proposal_study(torch, dev, steps: int) -> dict:
     return out
 
 
-def frames_study(torch, dev, sop, scenes, reps=10) -> dict:
+def frames_oracle(sc, stride=256) -> dict:
+    """The oracle's forward on every stride-th pixel of the frames workload (its neighbour
+    lists found and its maps widened to FP64 beforehand, after one untimed warm-up call),
+    with all host threads, extrapolated to the whole workload and labelled as such."""
+    import dataclasses
+
+    import numpy as np
+
+    import oracle
+    # every stride-th pixel of every frame, frame-major, so each point keeps its camera
+    ppf = sc.points_per_frame
+    per = np.arange(0, ppf, stride)
+    rows = np.concatenate([f * ppf + per for f in range(sc.cam_pos.shape[0])])
+    sub = dataclasses.replace(sc, pos=sc.pos[rows], normal=sc.normal[rows],
+                              albedo=sc.albedo[rows], rough=sc.rough[rows],
+                              metal=sc.metal[rows], points_per_frame=len(per),
+                              texels=sc.texels.astype(np.float64))
+    idx, w = oracle.knn(sub.probe_pos, sub.bounds_lo, sub.bounds_hi, sub.pos, sub.normal,
+                        sub.k)
+    warm = dataclasses.replace(sub, pos=sub.pos[:64], normal=sub.normal[:64],
+                               albedo=sub.albedo[:64], rough=sub.rough[:64],
+                               metal=sub.metal[:64], points_per_frame=64)
+    oracle.shade(warm, idx[:64], w[:64])
+    t = time.time()
+    oracle.shade(sub, idx, w)
+    dt = time.time() - t
+    samples = len(rows) * sc.n_dirs
+    return {"kind": "oracle", "samples_per_s": round(samples / dt, 1),
+            "cores": oracle.max_threads(),
+            "sample": f"shade forward on every {stride}th pixel of each frame ({len(rows)} of "
+                      f"{sc.n} points, "
+                      f"{dt:.1f}s), neighbour lists found beforehand; "
+                      f"extrapolated to all points: {sc.n * sc.n_dirs / (samples / dt):.1f}s"}
+
+
+def frames_study(torch, dev, sop, scenes, reps=10, cpu=True) -> dict:
     """The G-buffer frames workload: 8 frames of 1920x1080 (16,588,800 points, views from
     the frames' cameras), 16,384 probes with 32x32 f16 maps, S = 64, K = 8, 256x512
     environment: one forward call over all frames with the neighbour lists given, timed with
@@ -641,6 +676,7 @@ def frames_study(torch, dev, sop, scenes, reps=10) -> dict:
                      cam_pos=d(sc.cam_pos), points_per_frame=sc.points_per_frame)
     plan = sop.Plan(d(sc.probe_pos), sc.bounds_lo, sc.bounds_hi)
     tex, env = d(sc.texels), d(sc.env)
+    cpu_ref = frames_oracle(sc) if cpu else None
     del sc
     t_knn = time_ms_plain(lambda: sop.sop_knn(plan, pts, K), reps=3)
     nb = sop.sop_knn(plan, pts, K)
@@ -657,6 +693,7 @@ def frames_study(torch, dev, sop, scenes, reps=10) -> dict:
            "knn_ms": round(t_knn, 3), "shade_fwd_ms": round(t, 3),
            "samples_per_s": round(samples / (t * 1e-3), 1),
            "frames_per_s": round(8 / (t * 1e-3), 2),
+           "cpu_oracle": cpu_ref,
            "roofline": {"bound": "alu", "kernel": "k_shade_fwd_cl", "achieved": round(ach, 3),
                         "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                         "frac": round(ach / PEAK_FP32_TFLOPS, 4),
