@@ -454,18 +454,18 @@ def _proposal_eval(torch, sop, plan, tex, env, ev, nb, mlp, ref, mask) -> dict:
         return out, a.elapsed_time(b) / reps
 
     ham = {}
-    for S in (32, 64, 128):
+    for S in (16, 32, 64, 128, 256):
         out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7))
         ham[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
     # the cosine-weighted set of the same counts (no adjoint, forward only)
     cos = {}
-    for S in (32, 64, 128):
+    for S in (16, 32, 64, 128, 256):
         out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7,
                                               cosine=True))
         cos[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
     probs, t_mlp = timed(lambda: sop.sop_proposal_infer(mlp, ev))
     prop = {}
-    for S in (8, 16, 24, 32, 64):
+    for S in (4, 8, 16, 24, 32, 64):
         out, ms = timed(lambda: sop.sop_shade(plan, tex, env, ev, S, nb=nb, seed=7, probs=probs,
                                               mix_eps=MIX_EPS))
         prop[S] = {"rmse": round(rmse(out), 5), "ms": round(ms, 4)}
