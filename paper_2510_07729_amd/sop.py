@@ -474,6 +474,47 @@ def sop_dump_integrand(plan: Plan, texels: torch.Tensor, env: torch.Tensor, pts:
     return T
 
 
+def save_probe_maps(path: str, texels: torch.Tensor, depth: Optional[torch.Tensor] = None,
+                    probe_pos: Optional[torch.Tensor] = None, **meta) -> None:
+    """Baked probe maps for reuse (the bake runs once per scene): texels [P,R,R,4] (float32
+    or float16), optionally the depth maps [P,R,R] and the probe positions [P,3], in a
+    safetensors file with string metadata."""
+    from safetensors.torch import save_file
+    _maps_shape(texels)
+    if texels.dtype not in (torch.float32, torch.float16):
+        raise ValueError("probe textures must be float32 or float16")
+    P, R = int(texels.shape[0]), int(texels.shape[1])
+    t = {"texels": texels.detach().cpu().contiguous()}
+    if depth is not None:
+        _shape(depth, (P, R, R), "depth", torch.float32)
+        t["depth"] = depth.detach().cpu().contiguous()
+    if probe_pos is not None:
+        _shape(probe_pos, (P, 3), "probe_pos", torch.float32)
+        t["probe_pos"] = probe_pos.detach().cpu().contiguous()
+    save_file(t, path, metadata={str(k): str(v) for k, v in meta.items()})
+
+
+def load_probe_maps(path: str, device=None):
+    """Maps written by save_probe_maps: (dict of tensors on `device`, metadata). Refuses a
+    file whose tensors do not have the shapes and types save_probe_maps writes."""
+    from safetensors import safe_open
+    with safe_open(path, framework="pt") as f:
+        meta = dict(f.metadata() or {})
+        t = {k: f.get_tensor(k) for k in f.keys()}
+    if set(t) - {"texels", "depth", "probe_pos"} or "texels" not in t:
+        raise ValueError("not a probe-map file: expected texels [, depth, probe_pos]")
+    _maps_shape(t["texels"])
+    if t["texels"].dtype not in (torch.float32, torch.float16):
+        raise ValueError("probe textures must be float32 or float16")
+    P, R = int(t["texels"].shape[0]), int(t["texels"].shape[1])
+    if "depth" in t:
+        _shape(t["depth"], (P, R, R), "depth", torch.float32)
+    if "probe_pos" in t:
+        _shape(t["probe_pos"], (P, 3), "probe_pos", torch.float32)
+    dev = device if device is not None else "cpu"
+    return {k: v.to(dev) for k, v in t.items()}, meta
+
+
 class Mlp:
     """Proposal network parameters (f32 [41344] on the GPU) with the scene box of its
     position features, and optional Adam state."""

@@ -31,3 +31,36 @@ def test_checkpoint_rejects_wrong_shapes(tmp_path):
               metadata={"step": "0", "bounds_lo": "[0, 0, 0]", "bounds_hi": "[1, 1, 1]"})
     with pytest.raises(ValueError):
         sop.Mlp.load(path)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_probe_maps_round_trip(tmp_path, dtype):
+    g = torch.Generator().manual_seed(3)
+    tex = torch.rand(5, 8, 8, 4, generator=g).to(dtype)
+    depth = torch.rand(5, 8, 8, generator=g)
+    pos = torch.randn(5, 3, generator=g)
+    path = str(tmp_path / "maps.safetensors")
+    sop.save_probe_maps(path, tex, depth, pos, scene="object", res=8)
+    back, meta = sop.load_probe_maps(path)
+    assert meta == {"scene": "object", "res": "8"}
+    assert back["texels"].dtype == dtype and torch.equal(back["texels"], tex)
+    assert torch.equal(back["depth"], depth) and torch.equal(back["probe_pos"], pos)
+    sop.save_probe_maps(path, tex)
+    back, _ = sop.load_probe_maps(path)
+    assert set(back) == {"texels"}
+
+
+def test_probe_maps_refuse_bad_shapes(tmp_path):
+    from safetensors.torch import save_file
+    with pytest.raises(ValueError):
+        sop.save_probe_maps(str(tmp_path / "a.safetensors"), torch.zeros(2, 4, 4, 3))
+    with pytest.raises(ValueError):
+        sop.save_probe_maps(str(tmp_path / "b.safetensors"), torch.zeros(2, 4, 4, 4),
+                            depth=torch.zeros(2, 4, 5))
+    path = str(tmp_path / "c.safetensors")
+    save_file({"texels": torch.zeros(2, 4, 4, 4), "depth": torch.zeros(3, 4, 4)}, path)
+    with pytest.raises(ValueError):
+        sop.load_probe_maps(path)
+    save_file({"texels": torch.zeros(2, 4, 4, 4, dtype=torch.float64)}, path)
+    with pytest.raises(ValueError):
+        sop.load_probe_maps(path)
