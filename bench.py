@@ -625,7 +625,7 @@ def proposal_study(torch, dev, steps: int) -> dict:
     return out
 
 
-def frames_oracle(sc, stride=256) -> dict:
+def frames_oracle(sc, stride=64) -> dict:
     """The oracle's forward on every stride-th pixel of the frames workload (its neighbour
     lists found and its maps widened to FP64 beforehand, after one untimed warm-up call),
     with all host threads, extrapolated to the whole workload and labelled as such."""
