@@ -98,8 +98,10 @@ def main() -> int:
                          "FP32/FP64 FMA, float atomics, LDS and global gathers")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (it would "
+              "shard the shading points by Morton range over replicated probes and "
+              "environment, with one all-reduce of the environment and probe-texture "
+              "gradients in the backward, and the bake by probe)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -1,6 +1,6 @@
 """Pins of the oracle's cosine-weighted direction set (orc_direction_cos, orc_shade_cosine):
 the uniform estimate of Eq. 7 with the density cos(theta)/pi in place of 1/(2 pi), the
-the benchmark spec's cosine fallback next to the uniform set. Checked against closed forms (a
+cosine-weighted alternative to the uniform set. Checked against closed forms (a
 constant sky, the Lambert part, full occlusion), properties of the set itself (the disk
 radius, the azimuths of the uniform set, the first moment 2/3 of the cosine density), and
 agreement with the uniform set's estimate at many directions."""
