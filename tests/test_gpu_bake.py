@@ -33,7 +33,10 @@ def compare(gs, probe_pos, res, tex, dep, rays_p, rays_t, label):
     d = dep.reshape(-1, res * res)[rays_p, rays_t]
     e1 = report(f"{label} rgbo", parity_err(flat[keep], ref[keep, :4]))
     e2 = report(f"{label} depth", parity_err(d[keep], ref[keep, 4]))
-    assert keep.mean() > 0.85
+    # the oracle flags a ray when a float32 decision on it sits within its margin of a cut;
+    # on these seeded inputs that leaves 0-4.3% of the rays out (4.3% on the one-cell cloud,
+    # 2.6% on the object's sample)
+    assert keep.mean() >= 0.95
     return max(e1, e2)
 
 
@@ -116,7 +119,7 @@ def test_bake_nonzero_t_min_and_cutoffs(torch_gpu):
     log(f"t_min: {amb.sum()} of {len(amb)} rays ambiguous (excluded)")
     flat = tex.reshape(-1, 64, 4)[rp, rt]
     d = dep.reshape(-1, 64)[rp, rt]
-    assert keep.mean() > 0.85
+    assert keep.mean() >= 0.95
     assert report("t_min rgbo", parity_err(flat[keep], ref[keep, :4])) <= TOL
     assert report("t_min depth", parity_err(d[keep], ref[keep, 4])) <= TOL
 
