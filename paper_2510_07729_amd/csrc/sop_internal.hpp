@@ -211,7 +211,8 @@ struct BakeGrid {
   float cell[3];           // cell size per axis
   float inv_cell[3];
   const float4* gdata;     // [G][5]: (M row0 | mu.x) (M row1 | mu.y) (M row2 | mu.z)
-                           //          (color rgb | opacity) (r^2, r, 0, 0) bounding sphere
+                           //          (color rgb | opacity) (r^2, r, cut-off radius,
+                           //          opacity) with r the bounding sphere's radius
   const int32_t* cell_start;  // [cells + 1]
   const int32_t* entries;     // [capacity] Gaussian indices, cell-major
   int32_t capacity;
